@@ -1,0 +1,400 @@
+"""Oracle renderer: march, lookup, attention, compositing, deferred MLP.
+
+What one ray computes (paper sections in brackets):
+
+1. Ray setup.  Box scenes: the ray enters and leaves the cube ROI at
+   [t0, t1) by the slab test; lattice t_k = t0 + k * step.  Contracted scenes:
+   the scene lives in the image of x -> x (|x| <= 1), (2 - 1/|x|) x/|x|
+   (|x| > 1); the ray starts at t = 0 and advances by equal contracted arc
+   length, t_{k+1} = t_k + step / |J(x_k) d|, ending once it moves outward
+   with 1/|x| < step.  Every sample carries delta = step (the lattice
+   interval it opens) [Eq. 2].
+2. Occupancy test at each lattice point; occupied points are sampled.  The
+   skip march reads the distance grid G (Eq. 9): after reading G = g > 0 at a
+   lattice point, points within g voxels of it (less a margin) are known to be
+   empty and are not read.  Box scenes turn that into a jump of
+   floor(g * (voxel / step) / |d|) lattice points; contracted scenes keep a
+   ball of radius g * voxel - voxel/1024 around the read point.  The naive
+   march reads every lattice point; both must yield the same samples
+   (the paper's Table 4: the occupied-point count is unchanged by G).
+3. At a sample: trilinear lookup in every hash level [Sec. 3 Eq. 3,
+   Sec. 4.1 Eq. 6] of 8 feature channels and 1 attention logit.
+4. Attention across levels [Sec. 4.2 Eq. 7-8, softmax reading]: weights
+   w_l = softmax_l(logit_l) (max-subtracted), fused channel = sum_l w_l v_l;
+   density and colour share the weights.
+5. Activation and compositing [Eq. 2, Eq. 5; supplement "Activation
+   Layers"]: sigma = exp(fused_0); alpha = 1 - exp(-sigma * delta);
+   C_d += T alpha c_d, F += T alpha v_s, T *= 1 - alpha; the ray stops once
+   T < threshold (after compositing that sample) [supplement "Real-time
+   Rendering" item 2] or after max_samples samples.
+6. Deferred MLP once per ray [Eq. 5]: C = sigmoid(C_d + MLP(C_d, F)), MLP
+   7 -> 16 -> 16 -> 3 with ReLU hidden layers and a linear output.
+
+Decisions (steps 1-2 and the termination test) are taken in the float32
+mirror of exact32; all reported values are recomputed in float64 on the
+decided sample list.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+from .exact32 import F32, exp32, pairwise_sum, sqrt32
+from .hashgrid import corners32, corners64
+from . import quant
+
+BOX = 0
+CONTRACT = 1
+DT_F32, DT_BF16, DT_FP8 = 0, 1, 2
+MAX_LATTICE = 1 << 16
+
+
+@dataclass
+class OracleInputs:
+    tables: np.ndarray            # float32 [L, T, 9]
+    occ: np.ndarray               # uint8 [R, R, R]
+    dist: np.ndarray              # uint8 [R, R, R]
+    mlp: np.ndarray               # float32 [451]
+    resolutions: List[int]
+    domain: int
+    roi_half: float
+    step: float
+    max_samples: int
+    t_threshold: float
+    dtype: int = DT_F32
+    mlp_dims: tuple = (7, 16, 16, 3)
+    # derived
+    stored: Optional[np.ndarray] = None     # stored codes / values [L, T, 9]
+    scales: Optional[np.ndarray] = None     # float32 [L, 9] (FP8 only)
+    deq32: Optional[np.ndarray] = None      # float32 decoded code values (before scale)
+    val64: Optional[np.ndarray] = None      # float64 dequantised values [L, T, 9]
+
+    def __post_init__(self):
+        t = np.asarray(self.tables, dtype=F32)
+        if self.dtype == DT_F32:
+            self.stored = t
+            self.deq32 = t
+            self.scales = None
+            self.val64 = t.astype(np.float64)
+        elif self.dtype == DT_BF16:
+            self.stored = quant.quantize_tables_bf16(t)
+            self.deq32 = quant.bf16_decode(self.stored)
+            self.scales = None
+            self.val64 = self.deq32.astype(np.float64)
+        elif self.dtype == DT_FP8:
+            self.stored, self.scales = quant.quantize_tables_fp8(t)
+            self.deq32 = quant.fp8_decode(self.stored)
+            self.val64 = self.deq32.astype(np.float64) * self.scales.astype(np.float64)[:, None, :]
+        else:
+            raise ValueError("unknown table dtype")
+        self.occ_flat = np.ascontiguousarray(self.occ, dtype=np.uint8).ravel()
+        self.dist_flat = np.ascontiguousarray(self.dist, dtype=np.uint8).ravel()
+
+    @property
+    def L(self):
+        return len(self.resolutions)
+
+    @property
+    def T(self):
+        return self.tables.shape[1]
+
+    @property
+    def R(self):
+        return self.occ.shape[0]
+
+
+# --------------------------------------------------------------------------
+# per-sample lookup + attention
+
+
+def fused32(inp: OracleInputs, u: np.ndarray):
+    """Float32 mirror of the lookup + attention chain at grid coordinates u.
+
+    Returns fused channels [m, 8], attention weights [m, L], corner indices
+    [m, L, 8]."""
+    m = u.shape[0]
+    logits, vals, idxs = [], [], []
+    for l, N in enumerate(inp.resolutions):
+        idx, w = corners32(u, N, inp.T)
+        idxs.append(idx)
+        g = inp.deq32[l][idx]                        # [m, 8 corners, 9 channels]
+        acc = np.zeros((m, 9), dtype=F32)
+        for c in range(8):                           # acc = acc + w_c * v_c, c = 0..7
+            acc = acc + w[:, c:c + 1] * g[:, c, :]
+        if inp.scales is not None:
+            acc = inp.scales[l][None, :] * acc
+        logits.append(acc[:, 8])
+        vals.append([acc[:, ch] for ch in range(8)])
+    mx = logits[0]
+    for a in logits[1:]:
+        mx = np.maximum(mx, a)
+    e = [exp32(a - mx) for a in logits]
+    S = pairwise_sum(e)
+    wl = [x / S for x in e]
+    fused = np.stack([pairwise_sum([wl[l] * vals[l][ch] for l in range(inp.L)])
+                      for ch in range(8)], axis=1)
+    return fused, np.stack(wl, axis=1), np.stack(idxs, axis=1)
+
+
+def fused64(inp: OracleInputs, u: np.ndarray):
+    """Float64 lookup + attention; returns fused [m, 8], weights [m, L]."""
+    u = np.asarray(u, dtype=np.float64)
+    m = u.shape[0]
+    logits, vals = [], []
+    for l, N in enumerate(inp.resolutions):
+        idx, w = corners64(u, N, inp.T)
+        v = np.zeros((m, 9))
+        for c in range(8):
+            v += w[:, c:c + 1] * inp.val64[l][idx[:, c]]
+        logits.append(v[:, 8])
+        vals.append(v[:, :8])
+    a = np.stack(logits, axis=1)
+    a = a - a.max(axis=1, keepdims=True)
+    e = np.exp(a)
+    wl = e / e.sum(axis=1, keepdims=True)
+    fused = np.einsum("ml,mlc->mc", wl, np.stack(vals, axis=1))
+    return fused, wl
+
+
+def grid_coords32(inp: OracleInputs, pos: np.ndarray) -> np.ndarray:
+    """u = (x - lo) * inv_extent, float32."""
+    lo = F32(-inp.roi_half)
+    inv = F32(1.0) / (F32(inp.roi_half) - lo)
+    return (np.asarray(pos, dtype=F32) - lo) * inv
+
+
+def grid_coords64(inp: OracleInputs, pos: np.ndarray) -> np.ndarray:
+    lo = -float(inp.roi_half)
+    return (np.asarray(pos, dtype=np.float64) - lo) / (2.0 * inp.roi_half)
+
+
+# --------------------------------------------------------------------------
+# ray setup
+
+
+def ray_box32(o: np.ndarray, d: np.ndarray, half: float):
+    """Slab test in float32: entry t0 (clamped at 0), exit t1, validity."""
+    lo, hi = F32(-half), F32(half)
+    n = o.shape[0]
+    t0 = np.zeros(n, dtype=F32)
+    t1 = np.full(n, np.inf, dtype=F32)
+    valid = np.isfinite(o).all(axis=1) & np.isfinite(d).all(axis=1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        for a in range(3):
+            da, oa = d[:, a], o[:, a]
+            nz = da != 0
+            ta = (lo - oa) / da
+            tb = (hi - oa) / da
+            t0 = np.where(nz, np.maximum(t0, np.minimum(ta, tb)), t0)
+            t1 = np.where(nz, np.minimum(t1, np.maximum(ta, tb)), t1)
+            valid &= nz | ((oa >= lo) & (oa <= hi))
+    valid &= t0 < t1
+    return t0, t1, valid
+
+
+@dataclass
+class RenderResult:
+    n_samples: np.ndarray         # int32 [n]
+    n_reads: np.ndarray           # int32 [n]
+    t_final32: np.ndarray         # float32 [n] (decision mirror)
+    t_final: np.ndarray           # float64 [n]
+    c_d: np.ndarray               # float64 [n, 3]
+    feat: np.ndarray              # float64 [n, 4]
+    depth: np.ndarray             # float64 [n]
+    rgb: np.ndarray               # float64 [n, 3]
+    s_ray: np.ndarray             # int64 [S] samples sorted by (ray, k)
+    s_k: np.ndarray               # int64 [S] lattice index of each sample
+    s_t: np.ndarray               # float32 [S]
+    s_pos: np.ndarray             # float32 [S, 3] grid-domain position
+    extra: dict = field(default_factory=dict)
+
+
+def march(inp: OracleInputs, o: np.ndarray, d: np.ndarray, naive: bool = False,
+          terminate: bool = True):
+    """March all rays in lock-step over the lattice index k.
+
+    Returns per-ray sample lists and counts; transmittance decisions in the
+    float32 mirror."""
+    o = np.asarray(o, dtype=F32)
+    d = np.asarray(d, dtype=F32)
+    n = o.shape[0]
+    R = inp.R
+    RF = F32(R)
+    step = F32(inp.step)
+    thr = F32(inp.t_threshold) if terminate else F32(0.0)
+    vox = (F32(inp.roi_half) - F32(-inp.roi_half)) / RF
+    T = np.ones(n, dtype=F32)
+    nsamp = np.zeros(n, dtype=np.int64)
+    nreads = np.zeros(n, dtype=np.int64)
+    dn2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+    dn = sqrt32(dn2)
+    if inp.domain == BOX:
+        t0, t1, alive = ray_box32(o, d, inp.roi_half)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            rho = (vox / step) / dn
+        next_read = np.zeros(n, dtype=np.int64)
+    else:
+        alive = np.isfinite(o).all(axis=1) & np.isfinite(d).all(axis=1) & (dn2 > 0)
+        t = np.zeros(n, dtype=F32)
+        has_ball = np.zeros(n, dtype=bool)
+        ball_c = np.zeros((n, 3), dtype=F32)
+        ball_r2 = np.zeros(n, dtype=F32)
+        margin = vox * F32(1.0 / 1024.0)
+    rec_ray, rec_k, rec_t, rec_pos = [], [], [], []
+    k = 0
+    while alive.any() and k < MAX_LATTICE:
+        ids = np.nonzero(alive)[0]
+        if inp.domain == BOX:
+            tk = t0[ids] + F32(k) * step
+            inside = tk < t1[ids]
+            alive[ids[~inside]] = False
+            ids, tk = ids[inside], tk[inside]
+            pos = o[ids] + tk[:, None] * d[ids]
+            need = np.ones(len(ids), dtype=bool) if naive else (k >= next_read[ids])
+        else:
+            tk = t[ids]
+            x = o[ids] + tk[:, None] * d[ids]
+            r2 = (x[:, 0] * x[:, 0] + x[:, 1] * x[:, 1]) + x[:, 2] * x[:, 2]
+            outer = r2 > F32(1.0)
+            pos = x.copy()
+            jn = dn[ids].copy()
+            with np.errstate(divide="ignore", invalid="ignore"):
+                r = sqrt32(r2)
+                inv_r = F32(1.0) / r
+                s = (F32(2.0) - inv_r) * inv_r
+                xd = ((x[:, 0] * d[ids, 0] + x[:, 1] * d[ids, 1]) + x[:, 2] * d[ids, 2]) * inv_r
+                perp2 = np.maximum(dn2[ids] - xd * xd, F32(0.0))
+                rad = xd * (inv_r * inv_r)
+                jn_o = sqrt32((s * s) * perp2 + rad * rad)
+            pos[outer] = s[outer, None] * x[outer]
+            jn[outer] = jn_o[outer]
+            gone = outer & (inv_r < step) & (xd >= F32(0.0))
+            alive[ids[gone]] = False
+            keep = ~gone
+            ids, tk, pos, jn = ids[keep], tk[keep], pos[keep], jn[keep]
+            if naive:
+                need = np.ones(len(ids), dtype=bool)
+            else:
+                dv = pos - ball_c[ids]
+                dd = (dv[:, 0] * dv[:, 0] + dv[:, 1] * dv[:, 1]) + dv[:, 2] * dv[:, 2]
+                need = ~(has_ball[ids] & (dd < ball_r2[ids]))
+        # occupancy / distance read
+        u = grid_coords32(inp, pos)
+        q = np.clip(np.floor(u * RF), 0, R - 1).astype(np.int64)
+        vflat = q[:, 0] + R * (q[:, 1] + R * q[:, 2])
+        rd = ids[need]
+        nreads[rd] += 1
+        occv = inp.occ_flat[vflat[need]] != 0
+        g = inp.dist_flat[vflat[need]].astype(np.int64)
+        if not naive:
+            if inp.domain == BOX:
+                jump = np.floor(g.astype(F32) * rho[rd]).astype(np.int64)
+                upd = (~occv) & (g > 0)
+                next_read[rd[upd]] = k + np.maximum(jump[upd], 1)
+            else:
+                upd = (~occv) & (g > 0)
+                has_ball[rd] = upd
+                rb = g.astype(F32) * vox - margin
+                ball_r2[rd[upd]] = (rb * rb)[upd]
+                ball_c[rd[upd]] = pos[need][upd]
+        # samples
+        smp = rd[occv]
+        if len(smp):
+            spos = pos[need][occv]
+            su = u[need][occv]
+            fz, _, _ = fused32(inp, su)
+            sigma = exp32(fz[:, 0])
+            e = exp32(-(sigma * step))
+            T[smp] = T[smp] * e
+            nsamp[smp] += 1
+            rec_ray.append(smp)
+            rec_k.append(np.full(len(smp), k, dtype=np.int64))
+            rec_t.append(tk[need][occv])
+            rec_pos.append(spos)
+            stop = (T[smp] < thr) | (nsamp[smp] >= inp.max_samples)
+            alive[smp[stop]] = False
+        if inp.domain == CONTRACT:
+            with np.errstate(divide="ignore"):
+                t[ids] = tk + step / jn
+        k += 1
+    if rec_ray:
+        s_ray = np.concatenate(rec_ray)
+        s_k = np.concatenate(rec_k)
+        s_t = np.concatenate(rec_t).astype(F32)
+        s_pos = np.concatenate(rec_pos).astype(F32)
+        order = np.lexsort((s_k, s_ray))
+        s_ray, s_k, s_t, s_pos = s_ray[order], s_k[order], s_t[order], s_pos[order]
+    else:
+        s_ray = np.zeros(0, np.int64)
+        s_k = np.zeros(0, np.int64)
+        s_t = np.zeros(0, F32)
+        s_pos = np.zeros((0, 3), F32)
+    return dict(n_samples=nsamp.astype(np.int32), n_reads=nreads.astype(np.int32),
+                t_final32=T, s_ray=s_ray, s_k=s_k, s_t=s_t, s_pos=s_pos)
+
+
+def mlp64(params: np.ndarray, x: np.ndarray, dims=(7, 16, 16, 3)) -> np.ndarray:
+    """Deferred MLP: W2 relu(W1 relu(W0 x + b0) + b1) + b2 (float64)."""
+    p = np.asarray(params, dtype=np.float64)
+    i, h1, h2, o = dims
+    off = 0
+    W0 = p[off:off + h1 * i].reshape(h1, i); off += h1 * i
+    b0 = p[off:off + h1]; off += h1
+    W1 = p[off:off + h2 * h1].reshape(h2, h1); off += h2 * h1
+    b1 = p[off:off + h2]; off += h2
+    W2 = p[off:off + o * h2].reshape(o, h2); off += o * h2
+    b2 = p[off:off + o]
+    a1 = np.maximum(x @ W0.T + b0, 0.0)
+    a2 = np.maximum(a1 @ W1.T + b1, 0.0)
+    return a2 @ W2.T + b2
+
+
+def composite64(inp: OracleInputs, n: int, s_ray, s_t, fused):
+    """Front-to-back compositing of decided samples (float64)."""
+    sigma = np.exp(fused[:, 0])
+    alpha = 1.0 - np.exp(-sigma * float(F32(inp.step)))
+    c_d = np.zeros((n, 3))
+    feat = np.zeros((n, 4))
+    depth = np.zeros(n)
+    T = np.ones(n)
+    # samples are sorted by (ray, k): walk them by their rank within the ray
+    if len(s_ray):
+        starts = np.r_[0, np.nonzero(np.diff(s_ray))[0] + 1]
+        rank = np.arange(len(s_ray)) - np.repeat(starts, np.diff(np.r_[starts, len(s_ray)]))
+        for r in range(int(rank.max()) + 1):
+            sel = rank == r
+            rays = s_ray[sel]
+            w = T[rays] * alpha[sel]
+            c_d[rays] += w[:, None] * fused[sel, 1:4]
+            feat[rays] += w[:, None] * fused[sel, 4:8]
+            depth[rays] += w * s_t[sel].astype(np.float64)
+            T[rays] = T[rays] * (1.0 - alpha[sel])
+    return c_d, feat, depth, T
+
+
+def render(inp: OracleInputs, o: np.ndarray, d: np.ndarray, naive: bool = False,
+           terminate: bool = True) -> RenderResult:
+    o = np.asarray(o, dtype=F32)
+    n = o.shape[0]
+    m = march(inp, o, d, naive=naive, terminate=terminate)
+    if len(m["s_ray"]):
+        fz, _ = fused64(inp, grid_coords64(inp, m["s_pos"]))
+    else:
+        fz = np.zeros((0, 8))
+    c_d, feat, depth, T = composite64(inp, n, m["s_ray"], m["s_t"], fz)
+    rgb = 1.0 / (1.0 + np.exp(-(c_d + mlp64(inp.mlp, np.concatenate([c_d, feat], axis=1),
+                                              inp.mlp_dims))))
+    return RenderResult(n_samples=m["n_samples"], n_reads=m["n_reads"],
+                        t_final32=m["t_final32"], t_final=T, c_d=c_d, feat=feat,
+                        depth=depth, rgb=rgb, s_ray=m["s_ray"], s_k=m["s_k"],
+                        s_t=m["s_t"], s_pos=m["s_pos"])
+
+
+def inputs_from_scene(scene, dist: np.ndarray, dtype: int = DT_F32) -> OracleInputs:
+    cfg = scene.cfg
+    return OracleInputs(tables=scene.tables, occ=scene.occ, dist=dist, mlp=scene.mlp,
+                        resolutions=list(cfg.resolutions), domain=cfg.domain,
+                        roi_half=cfg.roi_half, step=cfg.step, max_samples=cfg.max_samples,
+                        t_threshold=cfg.t_threshold, dtype=dtype, mlp_dims=cfg.mlp_dims)

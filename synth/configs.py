@@ -1,0 +1,112 @@
+"""Workload definitions for the synthetic NGP-RT scenes.
+
+Five workloads are defined.  They are inputs to the renderer, not part of the
+rendering arithmetic:
+
+* ``tiny``      -- 8 hash levels (16..256), 2^14 entries, box ROI [-1,1]^3,
+                   64^3 occupancy, one 64x64 camera on the unit sphere,
+                   lattice step 1/256.  Small enough for the CPU oracle.
+* ``hd``        -- 16 hash levels (16..4096), 2^19 entries, FP32, scene in
+                   the contracted unbounded domain (radius 2), 256^3
+                   occupancy, 8 cameras of 1920x1080 on a ring of radius 3,
+                   at most 1024 samples per ray, termination at T < 1e-4.
+* ``precision`` -- ``tiny`` with BF16 or FP8-E4M3 tables.
+* ``train``     -- one differentiable step on the ``tiny`` grid shape.
+* ``proposal``  -- the learned sample-interval proposal on the ``tiny`` scene.
+
+Level resolutions follow a geometric progression between the coarsest and
+finest resolution (the multi-resolution hash encoding the method builds on,
+Sec. 3 "Preliminaries", Eq. 3), rounded down after adding 1e-6 so that the
+end points are exact; the integer list is handed to the renderer explicitly.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Tuple
+
+
+def geometric_resolutions(n_min: int, n_max: int, n_levels: int) -> List[int]:
+    """Integer per-level grid resolutions N_l = floor(n_min * b**l + 1e-6)."""
+    if n_levels == 1:
+        return [n_min]
+    b = (n_max / n_min) ** (1.0 / (n_levels - 1))
+    return [int(math.floor(n_min * b ** l + 1e-6)) for l in range(n_levels)]
+
+
+DOMAIN_BOX = 0        # axis-aligned cube ROI, straight lattice t_k = t0 + k*step
+DOMAIN_CONTRACT = 1   # unbounded scene contracted into the ball of radius 2
+
+DTYPE_F32 = 0
+DTYPE_BF16 = 1
+DTYPE_FP8 = 2
+
+
+@dataclass
+class SceneConfig:
+    name: str
+    n_levels: int
+    n_min: int
+    n_max: int
+    log2_table: int
+    domain: int
+    roi_half: float            # grid covers [-roi_half, roi_half]^3
+    occ_res: int
+    step: float                # lattice step (world units for the box, contracted units otherwise)
+    max_samples: int
+    t_threshold: float
+    n_blobs: int
+    blob_sigma: Tuple[float, float]
+    blob_centre_half: float    # box: centres ~ U[-h, h]^3 ; contract: radius of the ball of centres
+    density_scale: float       # s_sigma of the density channel
+    cam_width: int
+    cam_height: int
+    n_cams: int
+    cam_radius: float
+    fov_deg: float = 60.0
+    table_dtype: int = DTYPE_F32
+    seed: int = 0
+    mlp_dims: Tuple[int, int, int, int] = (7, 16, 16, 3)
+    resolutions: List[int] = field(default_factory=list)
+
+    def __post_init__(self):
+        if not self.resolutions:
+            self.resolutions = geometric_resolutions(self.n_min, self.n_max, self.n_levels)
+
+    @property
+    def table_size(self) -> int:
+        return 1 << self.log2_table
+
+    @property
+    def n_mlp_params(self) -> int:
+        i, h1, h2, o = self.mlp_dims
+        return h1 * i + h1 + h2 * h1 + h2 + o * h2 + o
+
+
+# Lattice step of the contracted domain: 2*sqrt(3)/512, the base marching step
+# the paper uses inside its [-1,1]^3 ROI (supplement, "Auto-tuning of Marching
+# Step Size").  Rounded to fp32 once here.
+CONTRACT_STEP = 2.0 * math.sqrt(3.0) / 512.0
+
+
+def tiny(seed: int = 0, table_dtype: int = DTYPE_F32) -> SceneConfig:
+    return SceneConfig(
+        name="tiny", n_levels=8, n_min=16, n_max=256, log2_table=14,
+        domain=DOMAIN_BOX, roi_half=1.0, occ_res=64, step=1.0 / 256.0,
+        max_samples=1024, t_threshold=1e-4, n_blobs=3, blob_sigma=(0.1, 0.3),
+        blob_centre_half=0.5, density_scale=600.0,
+        cam_width=64, cam_height=64, n_cams=1, cam_radius=1.0,
+        table_dtype=table_dtype, seed=seed)
+
+
+def hd(seed: int = 0, table_dtype: int = DTYPE_F32) -> SceneConfig:
+    return SceneConfig(
+        name="hd", n_levels=16, n_min=16, n_max=4096, log2_table=19,
+        domain=DOMAIN_CONTRACT, roi_half=2.0, occ_res=256, step=CONTRACT_STEP,
+        max_samples=1024, t_threshold=1e-4, n_blobs=200, blob_sigma=(0.03, 0.12),
+        blob_centre_half=1.9, density_scale=400.0,
+        cam_width=1920, cam_height=1080, n_cams=8, cam_radius=3.0,
+        table_dtype=table_dtype, seed=seed)
+
+
+CONFIGS = {"tiny": tiny, "hd": hd}
