@@ -1,0 +1,161 @@
+"""Benchmark of the NGP-RT render path on one MI355X.
+
+One step = one render of the full 'hd' workload: 8 views of 1920x1080 rays
+(16,588,800 rays) through 16 hash levels (16..4096, 2^19 entries each), a
+256^3 occupancy/distance grid in the contracted domain, <= 1024 samples per
+ray, termination at T < 1e-4, and the deferred MLP per ray.  Scene, rays and
+outputs are resident in HBM before the timed region.
+
+Prints one JSON line (metric = frames/s of 1080p views; Msamples/s beside it),
+with the dominant kernel's roofline figure and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_ENTRY = {0: 36, 1: 18, 2: 9}     # 8 feature channels + 1 logit per entry
+DTYPE_NAME = {0: "f32", 1: "bf16", 2: "fp8"}
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--dtype", choices=["f32", "bf16", "fp8"], default="f32")
+    p.add_argument("--cpu-seconds", type=float, default=15.0,
+                   help="approximate CPU time for the oracle baseline (0 skips it)")
+    p.add_argument("--views", type=int, default=8)
+    return p.parse_args()
+
+
+def cpu_baseline(sc, dist, o, d, dtype, seconds):
+    """The oracle, as it stands, on a deterministic subsample of the rays."""
+    from oracle.render import inputs_from_scene, render
+    inp = inputs_from_scene(sc, dist, dtype)
+    n_total = len(o)
+    n = 256
+    t0 = time.perf_counter()
+    stride = max(1, n_total // n)
+    render(inp, o[::stride][:n], d[::stride][:n])
+    dt = time.perf_counter() - t0
+    # scale the sample to the requested budget
+    n2 = int(min(max(n * seconds / max(dt, 1e-3), n), 200_000))
+    stride = max(1, n_total // n2)
+    so, sd = o[::stride][:n2], d[::stride][:n2]
+    t0 = time.perf_counter()
+    res = render(inp, so, sd)
+    dt = time.perf_counter() - t0
+    rays_per_s = len(so) / dt
+    return {
+        "value": rays_per_s / (1920 * 1080),
+        "unit": "frames/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{len(so)} rays (every {stride}th ray of the 8 views), {dt:.1f} s, "
+                  f"{res.n_samples.sum() / dt / 1e6:.4f} Msamples/s",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    import synth
+    from paper_2407_10482_amd.renderer import Renderer
+
+    dtype = {"f32": 0, "bf16": 1, "fp8": 2}[args.dtype]
+    cfg = synth.hd(table_dtype=dtype)
+    t0 = time.time()
+    sc = synth.make_scene(cfg)
+    cams = synth.camera_positions(cfg)[: args.views]
+    o, d, _ = synth.scene_rays(cfg, cams=cams)
+    print(f"# scene + rays generated in {time.time() - t0:.1f} s ({len(o)} rays)", file=sys.stderr,
+          flush=True)
+    torch.cuda.set_device(0)
+    r = Renderer.from_config(cfg, dtype)
+    r.load_scene(torch.from_numpy(sc.tables).cuda(), torch.from_numpy(sc.occ).cuda(),
+                 torch.from_numpy(sc.mlp).cuda())
+    go = torch.from_numpy(o).cuda()
+    gd = torch.from_numpy(d).cuda()
+    n = len(o)
+    # one render with every output, outside the timed region: sample and read counts
+    aux = r.render(go, gd)
+    torch.cuda.synchronize()
+    n_samples = int(aux["n_samples"].sum().item())
+    n_reads = int(aux["n_reads"].sum().item())
+    dist = r.export_distance().cpu().numpy()
+    out = {"rgb": torch.empty((n, 3), dtype=torch.float32, device="cuda")}
+    for _ in range(args.warmup):
+        r.render(go, gd, out=out)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(args.steps):
+        r.render(go, gd, out=out)
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / args.steps
+    views = len(cams)
+    fps = views / (ms / 1e3)
+    L = cfg.n_levels
+    gather = n_samples * L * 8 * BYTES_PER_ENTRY[dtype]
+    alg_bytes = gather + 2 * n_reads + n * (24 + 12)
+    achieved = alg_bytes / (ms / 1e3) / 1e9
+    res = {
+        "metric": "1080p frames/s (plain distance-grid marching)",
+        "value": round(fps, 3),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE_NAME[dtype],
+        "data": "synthetic",
+        "config": {
+            "workload": "hd: 8 views x 1920x1080 rays, 16 hash levels 16..4096, 2^19 entries, "
+                        f"{DTYPE_NAME[dtype]} tables, contracted scene of 200 blobs, 256^3 "
+                        "occupancy + distance grid, <=1024 samples/ray, T<1e-4",
+            "rays_per_step": n,
+            "views": views,
+        },
+        "msamples_per_s": round(n_samples / (ms / 1e3) / 1e6, 1),
+        "samples_per_ray": round(n_samples / n, 3),
+        "reads_per_ray": round(n_reads / n, 3),
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "render_kernel",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "algorithmic_bytes_per_launch": alg_bytes,
+        },
+    }
+    if args.cpu_seconds > 0:
+        res["cpu_baseline"] = cpu_baseline(sc, dist, o, d, dtype, args.cpu_seconds)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

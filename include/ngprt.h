@@ -1,0 +1,173 @@
+/*
+ * ngprt.h -- C ABI of the MI355X (gfx950) NGP-RT rendering library.
+ *
+ * The library renders rays through a baked NGP-RT-style scene (arXiv
+ * 2407.10482): it marches each ray with an occupancy grid and the occupancy
+ * distance grid (Sec. 4.3, Eq. 9), looks up every level of multi-level hash
+ * tables of explicit deferred features at each occupied sample (Sec. 4.1,
+ * Eq. 6; Sec. 3, Eq. 3), fuses the levels with attention (Sec. 4.2,
+ * Eq. 7-8, softmax form), composites front to back (Sec. 3, Eq. 2 and
+ * Eq. 5) and runs one deferred MLP per ray (Eq. 5).
+ *
+ * Conventions
+ *  - Every pointer named dev_* is device memory on the current HIP device.
+ *    Host pointers are named host_* or are plain structs.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Every call that
+ *    takes a stream only enqueues work on it and returns; results are valid
+ *    once the stream has passed the call.  No call synchronises the device
+ *    except ngprt_create / ngprt_destroy and the load functions (which may).
+ *  - The library owns the scene: load_* copy (and re-layout / quantise) the
+ *    caller's buffers into library memory; the caller may free its buffers
+ *    once the stream has passed the call.  Render calls borrow the ray and
+ *    output pointers only for the duration of the enqueued work.
+ *  - Every function returns NGPRT_OK (0) or a negative NGPRT_E_* code.  No
+ *    C++ exception crosses this boundary.  ngprt_last_error() holds a
+ *    message for the most recent failure on a context.
+ *  - A context is not thread-safe; calls that overlap on one context race.
+ *
+ * Arithmetic contract
+ *  - Integer outputs (hash indices, the distance grid, sample lattice
+ *    indices, sample and read counts, quantised table bytes) are exact.
+ *  - The chain that decides them (positions, voxel and corner indices,
+ *    trilinear weights, interpolated density and logits, the softmax across
+ *    levels, the density activation and transmittance) uses IEEE float32
+ *    add/sub/mul/div/sqrt without contraction, a fixed summation order and a
+ *    library-defined exponential, so it is reproducible off the GPU.
+ */
+#ifndef NGPRT_H
+#define NGPRT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NGPRT_MAX_LEVELS 16
+
+enum ngprt_status {
+  NGPRT_OK = 0,
+  NGPRT_E_INVALID_ARG = -1, /* null pointer, bad enum, negative count */
+  NGPRT_E_SHAPE = -2,       /* sizes inconsistent with the descriptor */
+  NGPRT_E_DTYPE = -3,       /* unsupported table dtype */
+  NGPRT_E_NOT_LOADED = -4,  /* render before tables / occupancy / MLP were loaded */
+  NGPRT_E_ALLOC = -5,       /* device allocation failed */
+  NGPRT_E_HIP = -6,         /* a HIP runtime call or kernel launch failed */
+  NGPRT_E_UNSUPPORTED = -7  /* valid request this build does not implement */
+};
+
+enum ngprt_dtype { NGPRT_F32 = 0, NGPRT_BF16 = 1, NGPRT_FP8E4M3 = 2 };
+
+enum ngprt_domain {
+  /* Axis-aligned cube ROI [-roi_half, roi_half]^3; straight lattice
+   * t_k = t0 + k*step from the ray's entry t0. */
+  NGPRT_ROI_BOX = 0,
+  /* Unbounded scene contracted into the ball of radius 2
+   * (x -> x for |x| <= 1, (2 - 1/|x|) x/|x| otherwise); the grids cover
+   * [-2, 2]^3 (roi_half must be 2); lattice of equal contracted arc length
+   * starting at t = 0. */
+  NGPRT_ROI_CONTRACT = 1
+};
+
+/* Scene descriptor (copied by ngprt_create). */
+typedef struct ngprt_desc {
+  int32_t n_levels;                          /* L, 1..16 */
+  int32_t resolutions[NGPRT_MAX_LEVELS];     /* N_l per level, >= 1 (explicit integers) */
+  int32_t log2_table_size;                   /* T = 1 << log2_table_size, 4..24 */
+  int32_t table_dtype;                       /* enum ngprt_dtype: storage of the tables */
+  int32_t domain;                            /* enum ngprt_domain */
+  float roi_half;                            /* grid extent; a power of two */
+  int32_t occ_res;                           /* R: occupancy / distance grids are R^3, 2..1024 */
+  float step;                                /* lattice step (box: world units; contract: contracted units) */
+  int32_t max_samples;                       /* cap on evaluated samples per ray, >= 1 */
+  float t_threshold;                         /* stop once T < t_threshold; 0 disables */
+  int32_t mlp_in, mlp_hidden, mlp_out;       /* must be 7, 16, 3 */
+} ngprt_desc;
+
+typedef struct ngprt_ctx ngprt_ctx;
+
+/* Optional per-ray outputs of ngprt_render.  rgb is required; NULL skips a field. */
+typedef struct ngprt_outputs {
+  float* rgb;        /* [n][3] sigmoid(C_d + MLP(C_d, F))           (Eq. 5) */
+  float* c_d;        /* [n][3] composited diffuse colour C_d          (Eq. 5) */
+  float* feat;       /* [n][4] composited specular feature F          (Eq. 5) */
+  float* t_final;    /* [n]    transmittance after the last sample    (Eq. 2) */
+  float* depth;      /* [n]    sum_i w_i t_i */
+  int32_t* n_samples;/* [n]    evaluated (occupied) samples */
+  int32_t* n_reads;  /* [n]    occupancy/distance grid reads (marching points) */
+} ngprt_outputs;
+
+/* Create a context on the current HIP device.  Validates the descriptor
+ * (host only).  *out is set only on success. */
+int ngprt_create(const ngprt_desc* desc, ngprt_ctx** out);
+
+/* Free the context and all library-owned device memory (synchronises). */
+void ngprt_destroy(ngprt_ctx* ctx);
+
+/* Validate a descriptor without creating anything (host only). */
+int ngprt_validate_desc(const ngprt_desc* desc);
+
+/* Load hash tables from float32 [L][T][9] (channels sigma_raw, r, g, b,
+ * s0..s3, logit; Sec. 4.1 explicit deferred features plus one attention
+ * logit per entry) and store them in desc.table_dtype:
+ *  F32 as is; BF16 round-to-nearest-even; FP8E4M3 (OCP E4M3FN) with one
+ *  float32 scale per (level, channel), s = amax/448 (1 if amax = 0),
+ *  code = RNE-saturate(x / s).  Stored internally as a feature array
+ *  [L][T][8] and a logit array [L][T]. */
+int ngprt_load_tables(ngprt_ctx* ctx, const float* dev_tables, void* stream);
+
+/* Read back the stored tables as [L][T][9] in the storage dtype
+ * (float32 / bf16 bits / e4m3 bytes) and, for FP8, the scales [L][9]
+ * (dev_scales may be NULL otherwise). */
+int ngprt_export_tables(ngprt_ctx* ctx, void* dev_codes, float* dev_scales, void* stream);
+
+/* Load the occupancy grid (uint8 [R][R][R], x fastest, nonzero = occupied).
+ * dev_dist: the occupancy distance grid G (uint8 [R^3]) or NULL to build it
+ * on the GPU: G = min(255, floor(box-gap distance in voxels to the nearest
+ * occupied voxel)), 0 for occupied voxels and their 26 neighbours, 255 when
+ * nothing is occupied (Sec. 4.3). */
+int ngprt_load_occupancy(ngprt_ctx* ctx, const uint8_t* dev_occ, const uint8_t* dev_dist,
+                         void* stream);
+
+/* Copy the distance grid in use to dev_dist (uint8 [R^3]). */
+int ngprt_export_distance(ngprt_ctx* ctx, uint8_t* dev_dist, void* stream);
+
+/* Load the deferred MLP (Eq. 5): float32 W0[16][7], b0[16], W1[16][16],
+ * b1[16], W2[3][16], b2[3] (451 values, row-major, out x in). */
+int ngprt_load_mlp(ngprt_ctx* ctx, const float* dev_params, void* stream);
+
+/* Render n_rays rays.  dev_origins, dev_dirs: float32 [n][3] (directions
+ * need not be unit length; the lattice step is in units of t*|d| only for
+ * the contracted domain).  Rays with a non-finite component, a zero
+ * direction, or missing the ROI get zero samples and rgb = sigmoid(MLP(0)).
+ * n_rays = 0 is a no-op. */
+int ngprt_render(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins,
+                 const float* dev_dirs, const ngprt_outputs* out, void* stream);
+
+/* Parity helpers.  Evaluate the lookup + attention chain at n positions in
+ * the grid's domain (box: world coordinates; contract: contracted
+ * coordinates).  Any output may be NULL: dev_idx int32 [n][L][8] corner
+ * table indices, dev_fused float32 [n][8] fused channels, dev_weights
+ * float32 [n][L] attention weights. */
+int ngprt_debug_eval_points(ngprt_ctx* ctx, int64_t n, const float* dev_pos, int32_t* dev_idx,
+                            float* dev_fused, float* dev_weights, void* stream);
+
+/* March only (no MLP): per ray, the lattice indices of the first `cap`
+ * evaluated samples (dev_sample_k int32 [n][cap], -1 padded), the sample
+ * count and the grid-read count.  naive != 0 reads every lattice point
+ * instead of skipping with the distance grid. */
+int ngprt_debug_march(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins,
+                      const float* dev_dirs, int32_t cap, int32_t* dev_sample_k,
+                      int32_t* dev_n_samples, int32_t* dev_n_reads, int32_t naive, void* stream);
+
+/* Human-readable name of a status code (static storage). */
+const char* ngprt_status_string(int status);
+
+/* Message of the last failure on ctx ("" if none; static-lifetime while ctx lives). */
+const char* ngprt_last_error(const ngprt_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NGPRT_H */

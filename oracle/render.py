@@ -7,7 +7,7 @@ What one ray computes (paper sections in brackets):
    the scene lives in the image of x -> x (|x| <= 1), (2 - 1/|x|) x/|x|
    (|x| > 1); the ray starts at t = 0 and advances by equal contracted arc
    length, t_{k+1} = t_k + step / |J(x_k) d|, ending once it moves outward
-   with 1/|x| < step.  Every sample carries delta = step (the lattice
+   with 1/|x| < step (or |x|^2 overflows).  Every sample carries delta = step (the lattice
    interval it opens) [Eq. 2].
 2. Occupancy test at each lattice point; occupied points are sampled.  The
    skip march reads the distance grid G (Eq. 9): after reading G = g > 0 at a
@@ -270,7 +270,7 @@ def march(inp: OracleInputs, o: np.ndarray, d: np.ndarray, naive: bool = False,
                 jn_o = sqrt32((s * s) * perp2 + rad * rad)
             pos[outer] = s[outer, None] * x[outer]
             jn[outer] = jn_o[outer]
-            gone = outer & (inv_r < step) & (xd >= F32(0.0))
+            gone = (outer & (inv_r < step) & (xd >= F32(0.0))) | ~np.isfinite(r2)
             alive[ids[gone]] = False
             keep = ~gone
             ids, tk, pos, jn = ids[keep], tk[keep], pos[keep], jn[keep]

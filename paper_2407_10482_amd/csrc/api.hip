@@ -1,0 +1,239 @@
+// C ABI entry points: validation, context and scene ownership, dispatch.
+// Validation is pure host code so it runs (and is tested) without a GPU.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "internal.h"
+
+namespace ngprt {
+
+int fail(ngprt_ctx* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->last_error = msg;
+  return code;
+}
+
+int check_launch(ngprt_ctx* ctx, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess)
+    return fail(ctx, NGPRT_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  return NGPRT_OK;
+}
+
+SceneArgs scene_args(const ngprt_ctx* ctx) {
+  const ngprt_desc& d = ctx->desc;
+  SceneArgs S;
+  std::memset(&S, 0, sizeof(S));
+  S.L = d.n_levels;
+  S.log2T = d.log2_table_size;
+  S.mask = uint32_t((int64_t(1) << d.log2_table_size) - 1);
+  for (int l = 0; l < kMaxLevels; ++l) {
+    S.N[l] = l < d.n_levels ? d.resolutions[l] : 1;
+    S.Nf[l] = float(S.N[l]);
+    for (int c = 0; c < 9; ++c) S.scale[l][c] = ctx->scales_host[l][c];
+  }
+  S.feat = ctx->feat;
+  S.logit = ctx->logit;
+  S.grid = ctx->grid;
+  S.R = d.occ_res;
+  S.Rf = float(d.occ_res);
+  S.lo = -d.roi_half;
+  S.inv_ext = 1.0f / (d.roi_half - (-d.roi_half));
+  S.vox = (d.roi_half - (-d.roi_half)) / float(d.occ_res);
+  S.v_over_step = S.vox / d.step;
+  S.step = d.step;
+  S.thr = d.t_threshold;
+  S.max_samples = d.max_samples;
+  return S;
+}
+
+static size_t dtype_bytes(int dt) { return dt == DT_F32 ? 4 : (dt == DT_BF16 ? 2 : 1); }
+
+}  // namespace ngprt
+
+using namespace ngprt;
+
+extern "C" {
+
+const char* ngprt_status_string(int status) {
+  switch (status) {
+    case NGPRT_OK: return "NGPRT_OK";
+    case NGPRT_E_INVALID_ARG: return "NGPRT_E_INVALID_ARG";
+    case NGPRT_E_SHAPE: return "NGPRT_E_SHAPE";
+    case NGPRT_E_DTYPE: return "NGPRT_E_DTYPE";
+    case NGPRT_E_NOT_LOADED: return "NGPRT_E_NOT_LOADED";
+    case NGPRT_E_ALLOC: return "NGPRT_E_ALLOC";
+    case NGPRT_E_HIP: return "NGPRT_E_HIP";
+    case NGPRT_E_UNSUPPORTED: return "NGPRT_E_UNSUPPORTED";
+    default: return "NGPRT_E_UNKNOWN";
+  }
+}
+
+const char* ngprt_last_error(const ngprt_ctx* ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+static bool is_pow2_float(float x) {
+  if (!(x > 0.0f) || !std::isfinite(x)) return false;
+  int e;
+  return std::frexp(x, &e) == 0.5f;
+}
+
+int ngprt_validate_desc(const ngprt_desc* d) {
+  if (!d) return NGPRT_E_INVALID_ARG;
+  if (d->n_levels < 1 || d->n_levels > NGPRT_MAX_LEVELS) return NGPRT_E_SHAPE;
+  for (int l = 0; l < d->n_levels; ++l)
+    if (d->resolutions[l] < 1 || d->resolutions[l] > (1 << 20)) return NGPRT_E_SHAPE;
+  if (d->log2_table_size < 4 || d->log2_table_size > 24) return NGPRT_E_SHAPE;
+  if (d->table_dtype < 0 || d->table_dtype > 2) return NGPRT_E_DTYPE;
+  if (d->domain != NGPRT_ROI_BOX && d->domain != NGPRT_ROI_CONTRACT) return NGPRT_E_INVALID_ARG;
+  if (!is_pow2_float(d->roi_half)) return NGPRT_E_INVALID_ARG;
+  if (d->domain == NGPRT_ROI_CONTRACT && d->roi_half != 2.0f) return NGPRT_E_INVALID_ARG;
+  if (d->occ_res < 2 || d->occ_res > 1024) return NGPRT_E_SHAPE;
+  if (!(d->step > 0.0f) || !std::isfinite(d->step)) return NGPRT_E_INVALID_ARG;
+  // the box march's skip keeps a margin of one lattice step from occupied
+  // voxels; it must dwarf float32 position error
+  if (d->domain == NGPRT_ROI_BOX && d->step < d->roi_half * (1.0f / 65536.0f)) return NGPRT_E_INVALID_ARG;
+  if (d->max_samples < 1) return NGPRT_E_INVALID_ARG;
+  if (!(d->t_threshold >= 0.0f) || !std::isfinite(d->t_threshold)) return NGPRT_E_INVALID_ARG;
+  if (d->mlp_in != 7 || d->mlp_hidden != 16 || d->mlp_out != 3) return NGPRT_E_UNSUPPORTED;
+  return NGPRT_OK;
+}
+
+void ngprt_destroy(ngprt_ctx* ctx) {
+  if (!ctx) return;
+  int cur = 0;
+  bool switched = hipGetDevice(&cur) == hipSuccess && cur != ctx->device &&
+                  hipSetDevice(ctx->device) == hipSuccess;
+  (void)hipDeviceSynchronize();
+  if (ctx->feat) (void)hipFree(ctx->feat);
+  if (ctx->logit) (void)hipFree(ctx->logit);
+  if (ctx->scales_dev) (void)hipFree(ctx->scales_dev);
+  if (ctx->grid) (void)hipFree(ctx->grid);
+  if (ctx->mlp) (void)hipFree(ctx->mlp);
+  if (switched) (void)hipSetDevice(cur);
+  delete ctx;
+}
+
+int ngprt_create(const ngprt_desc* desc, ngprt_ctx** out) {
+  if (!out) return NGPRT_E_INVALID_ARG;
+  int rc = ngprt_validate_desc(desc);
+  if (rc) return rc;
+  ngprt_ctx* ctx = new (std::nothrow) ngprt_ctx();
+  if (!ctx) return NGPRT_E_ALLOC;
+  ctx->desc = *desc;
+  ctx->T = int64_t(1) << desc->log2_table_size;
+  for (int l = 0; l < NGPRT_MAX_LEVELS; ++l)
+    for (int c = 0; c < 9; ++c) ctx->scales_host[l][c] = 1.0f;
+  if (hipGetDevice(&ctx->device) != hipSuccess) {
+    (void)hipGetLastError();
+    delete ctx;
+    return NGPRT_E_HIP;
+  }
+  const int64_t L = desc->n_levels;
+  const size_t eb = dtype_bytes(desc->table_dtype);
+  const int64_t R = desc->occ_res;
+  bool ok = hipMalloc(&ctx->feat, size_t(L * ctx->T * 8) * eb) == hipSuccess &&
+            hipMalloc(&ctx->logit, size_t(L * ctx->T) * eb) == hipSuccess &&
+            hipMalloc((void**)&ctx->scales_dev, sizeof(float) * NGPRT_MAX_LEVELS * 9) == hipSuccess &&
+            hipMalloc((void**)&ctx->grid, size_t(R * R * R) * sizeof(uint16_t)) == hipSuccess &&
+            hipMalloc((void**)&ctx->mlp, sizeof(float) * kMlpParams) == hipSuccess;
+  if (ok)
+    ok = hipMemcpy(ctx->scales_dev, &ctx->scales_host[0][0], sizeof(float) * NGPRT_MAX_LEVELS * 9,
+                   hipMemcpyHostToDevice) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    ngprt_destroy(ctx);
+    return NGPRT_E_ALLOC;
+  }
+  *out = ctx;
+  return NGPRT_OK;
+}
+
+int ngprt_load_tables(ngprt_ctx* ctx, const float* dev_tables, void* stream) {
+  if (!ctx) return NGPRT_E_INVALID_ARG;
+  if (!dev_tables) return fail(ctx, NGPRT_E_INVALID_ARG, "dev_tables is NULL");
+  int rc = launch_load_tables(ctx, dev_tables, (hipStream_t)stream);
+  if (rc == NGPRT_OK) ctx->tables_loaded = true;
+  return rc;
+}
+
+int ngprt_export_tables(ngprt_ctx* ctx, void* dev_codes, float* dev_scales, void* stream) {
+  if (!ctx) return NGPRT_E_INVALID_ARG;
+  if (!dev_codes) return fail(ctx, NGPRT_E_INVALID_ARG, "dev_codes is NULL");
+  if (!ctx->tables_loaded) return fail(ctx, NGPRT_E_NOT_LOADED, "tables not loaded");
+  return launch_export_tables(ctx, dev_codes, dev_scales, (hipStream_t)stream);
+}
+
+int ngprt_load_occupancy(ngprt_ctx* ctx, const uint8_t* dev_occ, const uint8_t* dev_dist, void* stream) {
+  if (!ctx) return NGPRT_E_INVALID_ARG;
+  if (!dev_occ) return fail(ctx, NGPRT_E_INVALID_ARG, "dev_occ is NULL");
+  int rc = launch_build_distance(ctx, dev_occ, dev_dist, (hipStream_t)stream);
+  if (rc == NGPRT_OK) ctx->occ_loaded = true;
+  return rc;
+}
+
+int ngprt_export_distance(ngprt_ctx* ctx, uint8_t* dev_dist, void* stream) {
+  if (!ctx) return NGPRT_E_INVALID_ARG;
+  if (!dev_dist) return fail(ctx, NGPRT_E_INVALID_ARG, "dev_dist is NULL");
+  if (!ctx->occ_loaded) return fail(ctx, NGPRT_E_NOT_LOADED, "occupancy not loaded");
+  return launch_export_distance(ctx, dev_dist, (hipStream_t)stream);
+}
+
+int ngprt_load_mlp(ngprt_ctx* ctx, const float* dev_params, void* stream) {
+  if (!ctx) return NGPRT_E_INVALID_ARG;
+  if (!dev_params) return fail(ctx, NGPRT_E_INVALID_ARG, "dev_params is NULL");
+  if (hipMemcpyAsync(ctx->mlp, dev_params, sizeof(float) * kMlpParams, hipMemcpyDeviceToDevice,
+                     (hipStream_t)stream) != hipSuccess)
+    return check_launch(ctx, "mlp copy");
+  ctx->mlp_loaded = true;
+  return NGPRT_OK;
+}
+
+static int check_ready(ngprt_ctx* ctx) {
+  if (!ctx->tables_loaded) return fail(ctx, NGPRT_E_NOT_LOADED, "tables not loaded");
+  if (!ctx->occ_loaded) return fail(ctx, NGPRT_E_NOT_LOADED, "occupancy not loaded");
+  return NGPRT_OK;
+}
+
+int ngprt_render(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins, const float* dev_dirs,
+                 const ngprt_outputs* out, void* stream) {
+  if (!ctx) return NGPRT_E_INVALID_ARG;
+  if (n_rays < 0) return fail(ctx, NGPRT_E_INVALID_ARG, "n_rays < 0");
+  if (!out || !out->rgb) return fail(ctx, NGPRT_E_INVALID_ARG, "out->rgb is required");
+  if (n_rays == 0) return NGPRT_OK;
+  if (!dev_origins || !dev_dirs) return fail(ctx, NGPRT_E_INVALID_ARG, "ray pointers are NULL");
+  int rc = check_ready(ctx);
+  if (rc) return rc;
+  if (!ctx->mlp_loaded) return fail(ctx, NGPRT_E_NOT_LOADED, "mlp not loaded");
+  RayOut o{out->rgb, out->c_d, out->feat, out->t_final, out->depth, out->n_samples, out->n_reads};
+  return launch_render(ctx, n_rays, dev_origins, dev_dirs, o, (hipStream_t)stream);
+}
+
+int ngprt_debug_eval_points(ngprt_ctx* ctx, int64_t n, const float* dev_pos, int32_t* dev_idx,
+                            float* dev_fused, float* dev_weights, void* stream) {
+  if (!ctx) return NGPRT_E_INVALID_ARG;
+  if (n < 0) return fail(ctx, NGPRT_E_INVALID_ARG, "n < 0");
+  if (n == 0) return NGPRT_OK;
+  if (!dev_pos) return fail(ctx, NGPRT_E_INVALID_ARG, "dev_pos is NULL");
+  if (!ctx->tables_loaded) return fail(ctx, NGPRT_E_NOT_LOADED, "tables not loaded");
+  return launch_eval_points(ctx, n, dev_pos, dev_idx, dev_fused, dev_weights, (hipStream_t)stream);
+}
+
+int ngprt_debug_march(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins, const float* dev_dirs,
+                      int32_t cap, int32_t* dev_sample_k, int32_t* dev_n_samples, int32_t* dev_n_reads,
+                      int32_t naive, void* stream) {
+  if (!ctx) return NGPRT_E_INVALID_ARG;
+  if (n_rays < 0 || cap < 0) return fail(ctx, NGPRT_E_INVALID_ARG, "negative size");
+  if (cap > 0 && !dev_sample_k) return fail(ctx, NGPRT_E_INVALID_ARG, "dev_sample_k is NULL");
+  if (n_rays == 0) return NGPRT_OK;
+  if (!dev_origins || !dev_dirs) return fail(ctx, NGPRT_E_INVALID_ARG, "ray pointers are NULL");
+  int rc = check_ready(ctx);
+  if (rc) return rc;
+  return launch_march(ctx, n_rays, dev_origins, dev_dirs, cap, dev_sample_k, dev_n_samples,
+                      dev_n_reads, naive, (hipStream_t)stream);
+}
+
+}  // extern "C"

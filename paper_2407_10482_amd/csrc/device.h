@@ -1,0 +1,250 @@
+// Device-side building blocks of the NGP-RT render path for gfx950.
+//
+// Everything on the decision chain (positions, voxel/corner indices,
+// trilinear weights, interpolated density and logit, softmax, density
+// activation, transmittance) is written with plain float32 operators; the
+// library is compiled with -ffp-contract=off and correctly rounded
+// division/sqrt, so each operator is one IEEE binary32 operation.  Colour
+// and specular channels, which decide nothing, use explicit fmaf.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace ngprt {
+
+// ---------------------------------------------------------------------------
+// exponential of the decision chain: Cody-Waite reduction by ln 2 (split in a
+// 9-bit head and a float32 tail), degree-7 Taylor polynomial of e^r by
+// Horner without fused multiply-add, and exact scaling by 2^k.
+__device__ __forceinline__ float exp32(float x) {
+  if (x != x) return x;
+  if (x > 88.0f) return __int_as_float(0x7F800000);
+  if (x < -86.0f) return 0.0f;
+  const float log2e = __int_as_float(0x3FB8AA3B);
+  const float ln2_hi = __int_as_float(0x3F318000);
+  const float ln2_lo = __int_as_float(0xB95E8083);
+  float k = floorf(x * log2e + 0.5f);
+  float r = (x - k * ln2_hi) - k * ln2_lo;
+  float p = __int_as_float(0x39500D01);          // 1/7!
+  p = p * r + __int_as_float(0x3AB60B61);        // 1/6!
+  p = p * r + __int_as_float(0x3C088889);        // 1/5!
+  p = p * r + __int_as_float(0x3D2AAAAB);        // 1/4!
+  p = p * r + __int_as_float(0x3E2AAAAB);        // 1/3!
+  p = p * r + 0.5f;
+  p = p * r + 1.0f;
+  p = p * r + 1.0f;
+  int n = (int)k;
+  return p * __int_as_float((n + 127) << 23);
+}
+
+// Spatial hash of a corner (multi-resolution hash encoding): products modulo
+// 2^32, xor, then the low log2(T) bits.
+__device__ __forceinline__ uint32_t hash3(uint32_t x, uint32_t y, uint32_t z, uint32_t mask) {
+  return ((x * 1u) ^ (y * 2654435761u) ^ (z * 805459861u)) & mask;
+}
+
+// ---------------------------------------------------------------------------
+// Table storage: features [L][T][8] and logits [L][T] in the storage dtype.
+
+template <int DT> struct Store;
+
+template <> struct Store<DT_F32> {
+  __device__ static __forceinline__ float logit(const void* p, size_t i) {
+    return reinterpret_cast<const float*>(p)[i];
+  }
+  __device__ static __forceinline__ void feat(const void* p, size_t i, float v[8]) {
+    const float4* q = reinterpret_cast<const float4*>(p) + 2 * i;
+    float4 a = q[0], b = q[1];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  }
+};
+
+template <> struct Store<DT_BF16> {
+  __device__ static __forceinline__ float logit(const void* p, size_t i) {
+    return __uint_as_float(uint32_t(reinterpret_cast<const uint16_t*>(p)[i]) << 16);
+  }
+  __device__ static __forceinline__ void feat(const void* p, size_t i, float v[8]) {
+    uint4 w = reinterpret_cast<const uint4*>(p)[i];
+    v[0] = __uint_as_float(w.x << 16); v[1] = __uint_as_float(w.x & 0xFFFF0000u);
+    v[2] = __uint_as_float(w.y << 16); v[3] = __uint_as_float(w.y & 0xFFFF0000u);
+    v[4] = __uint_as_float(w.z << 16); v[5] = __uint_as_float(w.z & 0xFFFF0000u);
+    v[6] = __uint_as_float(w.w << 16); v[7] = __uint_as_float(w.w & 0xFFFF0000u);
+  }
+};
+
+// OCP E4M3FN code -> float32 (exact).  Written from the format definition:
+// exponent bias 7, subnormals m * 2^-9.  Codes 0x7F/0xFF (NaN) never occur
+// in tables written by the library's encoder.
+__device__ __forceinline__ float fp8_decode(uint32_t b) {
+  uint32_t e = (b >> 3) & 15u, m = b & 7u;
+  float mag = e ? __uint_as_float(((e + 120u) << 23) | (m << 20)) : float(m) * 0.001953125f;
+  return (b & 0x80u) ? -mag : mag;
+}
+
+template <> struct Store<DT_FP8> {
+  __device__ static __forceinline__ float logit(const void* p, size_t i) {
+    return fp8_decode(reinterpret_cast<const uint8_t*>(p)[i]);
+  }
+  __device__ static __forceinline__ void feat(const void* p, size_t i, float v[8]) {
+    uint2 w = reinterpret_cast<const uint2*>(p)[i];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = fp8_decode((w.x >> (8 * j)) & 0xFFu);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[4 + j] = fp8_decode((w.y >> (8 * j)) & 0xFFu);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// One hash level at grid coordinate u: corner indices and trilinear weights.
+struct Corners {
+  uint32_t idx[8];
+  float w[8];
+};
+
+__device__ __forceinline__ void level_corners(const float u[3], int N, float Nf, uint32_t mask,
+                                              Corners& c) {
+  int i0[3];
+  float f[3], g[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float p = u[a] * Nf;
+    int i = (int)floorf(p);
+    i = i < 0 ? 0 : (i > N - 1 ? N - 1 : i);
+    i0[a] = i;
+    f[a] = p - (float)i;
+    g[a] = 1.0f - f[a];
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int bx = k & 1, by = (k >> 1) & 1, bz = (k >> 2) & 1;
+    c.w[k] = ((bx ? f[0] : g[0]) * (by ? f[1] : g[1])) * (bz ? f[2] : g[2]);
+    c.idx[k] = hash3(uint32_t(i0[0] + bx), uint32_t(i0[1] + by), uint32_t(i0[2] + bz), mask);
+  }
+}
+
+// Balanced-tree accumulator over a compile-time number of leaves (a power of
+// two): leaves pushed in order, merged as a binary counter, so the result is
+// ((v0+v1)+(v2+v3))+... exactly.
+template <int LMAX, int W> struct TreeSum {
+  static constexpr int DEPTH = (LMAX >= 16) ? 5 : (LMAX >= 8 ? 4 : (LMAX >= 4 ? 3 : 2));
+  float s[DEPTH][W];
+  int top = 0;
+  template <int LEAF>
+  __device__ __forceinline__ void push(const float v[W]) {
+#pragma unroll
+    for (int j = 0; j < W; ++j) s[top][j] = v[j];
+    ++top;
+    // merges = trailing zeros of (LEAF + 1)
+    constexpr int m = __builtin_ctz(LEAF + 1);
+#pragma unroll
+    for (int q = 0; q < m; ++q) {
+#pragma unroll
+      for (int j = 0; j < W; ++j) s[top - 2][j] = s[top - 2][j] + s[top - 1][j];
+      --top;
+    }
+  }
+};
+
+template <int LMAX, int I> struct Unroll {
+  template <class F> __device__ __forceinline__ static void run(F&& f) {
+    Unroll<LMAX, I - 1>::run(f);
+    f(std::integral_constant<int, I - 1>{});
+  }
+};
+template <int LMAX> struct Unroll<LMAX, 0> {
+  template <class F> __device__ __forceinline__ static void run(F&&) {}
+};
+
+// Lookup + attention at grid coordinate u: fused channels [8]; optionally
+// attention weights [L] and corner indices [L][8].
+template <int DT, int LMAX>
+__device__ __forceinline__ void eval_fused(const SceneArgs& S, const float u[3], float fused[8],
+                                           float* wout = nullptr, int32_t* idxout = nullptr) {
+  float a[LMAX];
+  // pass 1: interpolated logits of every level
+#pragma unroll
+  for (int l = 0; l < LMAX; ++l) {
+    a[l] = 0.0f;
+    if (l < S.L) {
+      Corners c;
+      level_corners(u, S.N[l], S.Nf[l], S.mask, c);
+      const size_t base = size_t(l) << S.log2T;
+      float v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] = Store<DT>::logit(S.logit, base + c.idx[k]);
+      float acc = 0.0f;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) acc = acc + c.w[k] * v[k];
+      if (DT == DT_FP8) acc = S.scale[l][8] * acc;
+      a[l] = acc;
+      if (idxout) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) idxout[l * 8 + k] = int32_t(c.idx[k]);
+      }
+    }
+  }
+  // softmax across levels (max-subtracted), tree-ordered normaliser
+  float mx = a[0];
+#pragma unroll
+  for (int l = 1; l < LMAX; ++l)
+    if (l < S.L) mx = fmaxf(mx, a[l]);
+  float e[LMAX];
+#pragma unroll
+  for (int l = 0; l < LMAX; ++l) e[l] = (l < S.L) ? exp32(a[l] - mx) : 0.0f;
+  TreeSum<LMAX, 1> ts;
+  Unroll<LMAX, LMAX>::run([&](auto I) {
+    float x[1] = {e[I.value]};
+    ts.template push<I.value>(x);
+  });
+  const float Ssum = ts.s[0][0];
+  float w[LMAX];
+#pragma unroll
+  for (int l = 0; l < LMAX; ++l) w[l] = (l < S.L) ? e[l] / Ssum : 0.0f;
+  if (wout) {
+#pragma unroll
+    for (int l = 0; l < LMAX; ++l)
+      if (l < S.L) wout[l] = w[l];
+  }
+  // pass 2: features of every level, weighted, tree-summed
+  TreeSum<LMAX, 8> fs;
+  Unroll<LMAX, LMAX>::run([&](auto I) {
+    constexpr int l = I.value;
+    float prod[8];
+    if (l < S.L) {
+      Corners c;
+      level_corners(u, S.N[l], S.Nf[l], S.mask, c);
+      const size_t base = size_t(l) << S.log2T;
+      float v[8][8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) Store<DT>::feat(S.feat, base + c.idx[k], v[k]);
+      float acc[8];
+      acc[0] = 0.0f;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) acc[0] = acc[0] + c.w[k] * v[k][0];
+#pragma unroll
+      for (int j = 1; j < 8; ++j) {
+        acc[j] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[j] = __builtin_fmaf(c.w[k], v[k][j], acc[j]);
+      }
+      if (DT == DT_FP8) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[j] = S.scale[l][j] * acc[j];
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) prod[j] = w[l] * acc[j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) prod[j] = 0.0f;
+    }
+    fs.template push<l>(prod);
+  });
+#pragma unroll
+  for (int j = 0; j < 8; ++j) fused[j] = fs.s[0][j];
+}
+
+}  // namespace ngprt

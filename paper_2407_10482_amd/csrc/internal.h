@@ -1,0 +1,86 @@
+// Internal types shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <type_traits>
+
+#include "../../include/ngprt.h"
+
+namespace ngprt {
+
+enum { DT_F32 = 0, DT_BF16 = 1, DT_FP8 = 2 };
+enum { DOM_BOX = 0, DOM_CONTRACT = 1 };
+constexpr int kMaxLevels = NGPRT_MAX_LEVELS;
+constexpr int kMlpParams = 451;
+constexpr int kMaxLattice = 1 << 16;   // hard bound on lattice points per ray
+
+// Scene constants passed by value to kernels (lands in scalar registers).
+struct SceneArgs {
+  int L;
+  int log2T;
+  uint32_t mask;
+  int N[kMaxLevels];
+  float Nf[kMaxLevels];
+  float scale[kMaxLevels][9];     // FP8 dequantisation scales (1 otherwise)
+  const void* feat;               // [L][T][8] storage dtype
+  const void* logit;              // [L][T]    storage dtype
+  const uint16_t* grid;           // [R^3]: low byte G, bit 8 = occupied
+  int R;
+  float Rf;
+  float lo;                       // grid covers [lo, -lo]^3
+  float inv_ext;                  // 1 / (2 * roi_half)
+  float vox;                      // voxel edge (grid-domain units)
+  float v_over_step;              // vox / step
+  float step;
+  float thr;
+  int max_samples;
+};
+
+struct RayOut {
+  float* rgb;
+  float* c_d;
+  float* feat;
+  float* t_final;
+  float* depth;
+  int32_t* n_samples;
+  int32_t* n_reads;
+};
+
+}  // namespace ngprt
+
+struct ngprt_ctx {
+  ngprt_desc desc;
+  int device = 0;
+  int64_t T = 0;
+  void* feat = nullptr;       // [L][T][8]
+  void* logit = nullptr;      // [L][T]
+  float* scales_dev = nullptr;// [L][9]
+  float scales_host[NGPRT_MAX_LEVELS][9];
+  uint16_t* grid = nullptr;   // [R^3]
+  float* mlp = nullptr;       // [451]
+  bool tables_loaded = false;
+  bool occ_loaded = false;
+  bool mlp_loaded = false;
+  std::string last_error;
+};
+
+namespace ngprt {
+int fail(ngprt_ctx* ctx, int code, const std::string& msg);
+int check_launch(ngprt_ctx* ctx, const char* what);
+SceneArgs scene_args(const ngprt_ctx* ctx);
+
+// launchers (defined in the kernel translation units)
+int launch_build_distance(ngprt_ctx* ctx, const uint8_t* occ, const uint8_t* dist, hipStream_t s);
+int launch_export_distance(ngprt_ctx* ctx, uint8_t* out, hipStream_t s);
+int launch_load_tables(ngprt_ctx* ctx, const float* tables, hipStream_t s);
+int launch_export_tables(ngprt_ctx* ctx, void* codes, float* scales, hipStream_t s);
+int launch_render(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const RayOut& out,
+                  hipStream_t s);
+int launch_eval_points(ngprt_ctx* ctx, int64_t n, const float* pos, int32_t* idx, float* fused,
+                       float* weights, hipStream_t s);
+int launch_march(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, int32_t cap,
+                 int32_t* sk, int32_t* ns, int32_t* nr, int naive, hipStream_t s);
+}  // namespace ngprt

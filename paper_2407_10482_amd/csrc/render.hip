@@ -1,0 +1,399 @@
+// Render kernels: occupancy-distance march, hashed lookup + attention,
+// front-to-back compositing, and the deferred MLP on MFMA.
+//
+// One lane owns one ray; a wave owns 64 rays (an 8x8 pixel tile when the
+// caller orders rays tile-major, which keeps the coarse-level gathers of a
+// wave on shared cache lines).  Each iteration every live lane first marches
+// to its next occupied lattice point (divergent but cheap: one 2-byte grid
+// read per marching point, none inside a known-empty region), then all lanes
+// holding a sample evaluate it together (the gather-heavy part runs with the
+// wave converged).  After the last ray of the wave finishes, the wave runs
+// the deferred MLP for its 64 rays with v_mfma_f32_16x16x4_f32.
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+#include "internal.h"
+
+namespace ngprt {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+struct MarchState {
+  float o[3], d[3];
+  float t0, t1;       // box: entry/exit
+  float t;            // contract: current lattice t
+  float rho;          // box: (vox/step)/|d|
+  float dn, dn2;      // |d|, |d|^2
+  int k;              // lattice index of the next point to visit
+  int next_read;      // box: first lattice index not known to be empty
+  bool has_ball;      // contract: known-empty ball
+  float bc[3], br2;
+  bool done;
+};
+
+template <int DOM>
+__device__ __forceinline__ void march_init(const SceneArgs& S, const float* o, const float* d,
+                                           bool in_range, MarchState& m) {
+  bool valid = in_range;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    m.o[a] = in_range ? o[a] : 0.0f;
+    m.d[a] = in_range ? d[a] : 0.0f;
+    valid = valid && isfinite(m.o[a]) && isfinite(m.d[a]);
+  }
+  m.dn2 = (m.d[0] * m.d[0] + m.d[1] * m.d[1]) + m.d[2] * m.d[2];
+  m.dn = sqrtf(m.dn2);
+  m.k = 0;
+  m.next_read = 0;
+  m.has_ball = false;
+  m.t = 0.0f;
+  if (DOM == DOM_BOX) {
+    const float lo = S.lo, hi = -S.lo;
+    float t0 = 0.0f, t1 = __int_as_float(0x7F800000);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (m.d[a] != 0.0f) {
+        float ta = (lo - m.o[a]) / m.d[a];
+        float tb = (hi - m.o[a]) / m.d[a];
+        t0 = fmaxf(t0, fminf(ta, tb));
+        t1 = fminf(t1, fmaxf(ta, tb));
+      } else {
+        valid = valid && (m.o[a] >= lo) && (m.o[a] <= hi);
+      }
+    }
+    valid = valid && (t0 < t1);
+    m.t0 = t0;
+    m.t1 = t1;
+    m.rho = S.v_over_step / m.dn;
+  } else {
+    valid = valid && (m.dn2 > 0.0f);
+  }
+  m.done = !valid;
+}
+
+// Grid-domain position -> grid coordinate u in [0,1]^3 and voxel index.
+__device__ __forceinline__ uint32_t voxel_of(const SceneArgs& S, const float p[3], float u[3]) {
+  int q[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    u[a] = (p[a] - S.lo) * S.inv_ext;
+    int i = (int)floorf(u[a] * S.Rf);
+    q[a] = i < 0 ? 0 : (i > S.R - 1 ? S.R - 1 : i);
+  }
+  return uint32_t(q[0]) + uint32_t(S.R) * (uint32_t(q[1]) + uint32_t(S.R) * uint32_t(q[2]));
+}
+
+// Advance this lane's march to its next occupied lattice point.  Returns
+// true with (u, ts, ks) set when a sample was found; sets m.done when the
+// ray leaves the domain.
+template <int DOM>
+__device__ __forceinline__ bool march_next(const SceneArgs& S, MarchState& m, bool naive,
+                                           int& reads, float u[3], float& ts, int& ks) {
+  while (!m.done) {
+    if (m.k >= kMaxLattice) { m.done = true; break; }
+    float p[3];
+    float tcur;
+    if (DOM == DOM_BOX) {
+      tcur = m.t0 + (float)m.k * S.step;
+      if (!(tcur < m.t1)) { m.done = true; break; }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) p[a] = m.o[a] + tcur * m.d[a];
+    } else {
+      tcur = m.t;
+      float x[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) x[a] = m.o[a] + tcur * m.d[a];
+      float r2 = (x[0] * x[0] + x[1] * x[1]) + x[2] * x[2];
+      if (!isfinite(r2)) { m.done = true; break; }
+      float jn;
+      if (r2 > 1.0f) {
+        float r = sqrtf(r2);
+        float inv_r = 1.0f / r;
+        float s = (2.0f - inv_r) * inv_r;
+        float xd = ((x[0] * m.d[0] + x[1] * m.d[1]) + x[2] * m.d[2]) * inv_r;
+        if (inv_r < S.step && xd >= 0.0f) { m.done = true; break; }
+        float perp2 = fmaxf(m.dn2 - xd * xd, 0.0f);
+        float rad = xd * (inv_r * inv_r);
+        jn = sqrtf((s * s) * perp2 + rad * rad);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) p[a] = s * x[a];
+      } else {
+        jn = m.dn;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) p[a] = x[a];
+      }
+      m.t = tcur + S.step / jn;
+    }
+    const int kcur = m.k;
+    bool need = true;
+    if (!naive && DOM == DOM_CONTRACT && m.has_ball) {
+      float e0 = p[0] - m.bc[0], e1 = p[1] - m.bc[1], e2 = p[2] - m.bc[2];
+      float dd = (e0 * e0 + e1 * e1) + e2 * e2;
+      need = !(dd < m.br2);
+    }
+    m.k = kcur + 1;
+    if (!need) continue;
+    const uint32_t v = voxel_of(S, p, u);
+    const uint32_t word = S.grid[v];
+    ++reads;
+    if (word & 0x100u) {
+      ts = tcur;
+      ks = kcur;
+      if (!naive && DOM == DOM_CONTRACT) m.has_ball = false;
+      return true;
+    }
+    const uint32_t g = word & 0xFFu;
+    if (!naive) {
+      if (DOM == DOM_BOX) {
+        if (g > 0) {
+          int jump = (int)floorf((float)g * m.rho);
+          m.k = kcur + (jump > 1 ? jump : 1);
+        }
+      } else {
+        if (g > 0) {
+          float rb = (float)g * S.vox - S.vox * 0.0009765625f;
+          m.br2 = rb * rb;
+          m.bc[0] = p[0]; m.bc[1] = p[1]; m.bc[2] = p[2];
+          m.has_ball = true;
+        } else {
+          m.has_ball = false;
+        }
+      }
+    }
+  }
+  return false;
+}
+
+enum { MODE_RENDER = 0, MODE_MARCH = 1 };
+
+struct MarchRecord {
+  int32_t* sample_k;
+  int32_t* n_samples;
+  int32_t* n_reads;
+  int cap;
+};
+
+// Deferred MLP of the 64 rays of this wave (Eq. 5), 7 -> 16 -> 16 -> 3 on
+// v_mfma_f32_16x16x4_f32.  xin: this wave's LDS slab [8][64] holding
+// (C_d, F, 0) of every lane's ray.  Layout of the 16x16x4 product D = A B:
+// lane l supplies A[l%16][l/16] and B[l/16][l%16] and receives
+// D[4*(l/16) + r][l%16], r = 0..3.  The hidden index handed from one layer
+// to the next is permuted (k-slot s of chunk c = unit 4s + c) so every layer
+// consumes the previous layer's accumulators in place.
+__device__ __forceinline__ void wave_mlp(const float* __restrict__ P, const float* xin, int lane,
+                                         int64_t ray_base, int64_t n, float* __restrict__ rgb) {
+  const int i = lane & 15, s = lane >> 4;
+  float a1[2], a2[4], a3[4];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    int k = 4 * c + s;
+    a1[c] = (k < 7) ? P[i * 7 + k] : 0.0f;
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    a2[c] = P[128 + i * 16 + 4 * s + c];
+    a3[c] = (i < 3) ? P[400 + i * 16 + 4 * s + c] : 0.0f;
+  }
+  float b0[4], b1[4], b2[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    b0[r] = P[112 + 4 * s + r];
+    b1[r] = P[384 + 4 * s + r];
+    b2[r] = (4 * s + r < 3) ? P[448 + 4 * s + r] : 0.0f;
+  }
+#pragma unroll
+  for (int blk = 0; blk < 4; ++blk) {
+    const int ray = blk * 16 + i;
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[c], xin[(4 * c + s) * 64 + ray], acc, 0, 0, 0);
+    float h[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) h[r] = fmaxf(acc[r] + b0[r], 0.0f);
+    acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[c], h[c], acc, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) h[r] = fmaxf(acc[r] + b1[r], 0.0f);
+    acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a3[c], h[c], acc, 0, 0, 0);
+    if (s == 0) {
+      const int64_t gr = ray_base + ray;
+      if (gr < n) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          float z = xin[j * 64 + ray] + (acc[j] + b2[j]);
+          rgb[gr * 3 + j] = 1.0f / (1.0f + __expf(-z));
+        }
+      }
+    }
+  }
+}
+
+template <int DOM, int DT, int LMAX, int MODE>
+__global__ void __launch_bounds__(256) render_kernel(SceneArgs S, int64_t n, const float* __restrict__ O,
+                                                     const float* __restrict__ D, RayOut out,
+                                                     MarchRecord rec, const float* __restrict__ mlp,
+                                                     int naive) {
+  __shared__ float xin_all[4][8 * 64];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t ray_base = (int64_t(blockIdx.x) * 4 + wave) * 64;
+  const int64_t ray = ray_base + lane;
+  const bool in_range = ray < n;
+
+  MarchState m;
+  march_init<DOM>(S, O + 3 * (in_range ? ray : 0), D + 3 * (in_range ? ray : 0), in_range, m);
+  float T = 1.0f, cd[3] = {0.f, 0.f, 0.f}, fv[4] = {0.f, 0.f, 0.f, 0.f}, depth = 0.0f;
+  int ns = 0, reads = 0;
+
+  for (;;) {
+    float u[3], ts;
+    int ks;
+    bool have = march_next<DOM>(S, m, naive != 0, reads, u, ts, ks);
+    if (__ballot(have) == 0) break;
+    if (have) {
+      float f[8];
+      eval_fused<DT, LMAX>(S, u, f);
+      const float sigma = exp32(f[0]);
+      const float e = exp32(-(sigma * S.step));
+      const float alpha = 1.0f - e;
+      const float w = T * alpha;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) cd[j] = __builtin_fmaf(w, f[1 + j], cd[j]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) fv[j] = __builtin_fmaf(w, f[4 + j], fv[j]);
+      depth = __builtin_fmaf(w, ts, depth);
+      if (MODE == MODE_MARCH && ns < rec.cap) rec.sample_k[ray * rec.cap + ns] = ks;
+      T = T * e;
+      ++ns;
+      if (T < S.thr || ns >= S.max_samples) m.done = true;
+    }
+  }
+
+  if (MODE == MODE_MARCH) {
+    if (in_range) {
+      for (int j = ns; j < rec.cap; ++j) rec.sample_k[ray * rec.cap + j] = -1;
+      if (rec.n_samples) rec.n_samples[ray] = ns;
+      if (rec.n_reads) rec.n_reads[ray] = reads;
+    }
+    return;
+  }
+  if (in_range) {
+    if (out.c_d) { for (int j = 0; j < 3; ++j) out.c_d[ray * 3 + j] = cd[j]; }
+    if (out.feat) { for (int j = 0; j < 4; ++j) out.feat[ray * 4 + j] = fv[j]; }
+    if (out.t_final) out.t_final[ray] = T;
+    if (out.depth) out.depth[ray] = depth;
+    if (out.n_samples) out.n_samples[ray] = ns;
+    if (out.n_reads) out.n_reads[ray] = reads;
+  }
+  float* xin = xin_all[wave];
+  xin[0 * 64 + lane] = cd[0];
+  xin[1 * 64 + lane] = cd[1];
+  xin[2 * 64 + lane] = cd[2];
+  xin[3 * 64 + lane] = fv[0];
+  xin[4 * 64 + lane] = fv[1];
+  xin[5 * 64 + lane] = fv[2];
+  xin[6 * 64 + lane] = fv[3];
+  xin[7 * 64 + lane] = 0.0f;
+  __syncthreads();
+  wave_mlp(mlp, xin, lane, ray_base, n, out.rgb);
+}
+
+template <int DT, int LMAX>
+__global__ void __launch_bounds__(256) eval_points_kernel(SceneArgs S, int64_t n,
+                                                          const float* __restrict__ pos,
+                                                          int32_t* idx, float* fused, float* weights) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float p[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+  float u[3];
+  for (int a = 0; a < 3; ++a) u[a] = (p[a] - S.lo) * S.inv_ext;
+  float f[8], w[LMAX];
+  int32_t id[LMAX * 8];
+  eval_fused<DT, LMAX>(S, u, f, w, id);
+  if (fused)
+    for (int j = 0; j < 8; ++j) fused[i * 8 + j] = f[j];
+  if (weights)
+    for (int l = 0; l < S.L; ++l) weights[i * S.L + l] = w[l];
+  if (idx)
+    for (int l = 0; l < S.L; ++l)
+      for (int k = 0; k < 8; ++k) idx[(i * S.L + l) * 8 + k] = id[l * 8 + k];
+}
+
+// ---------------------------------------------------------------------------
+// dispatch
+
+template <int MODE, int DOM, int DT>
+static void dispatch_l(const SceneArgs& S, dim3 g, hipStream_t st, int64_t n, const float* o,
+                       const float* d, const RayOut& out, const MarchRecord& rec,
+                       const float* mlp, int naive) {
+  if (S.L <= 8)
+    hipLaunchKernelGGL((render_kernel<DOM, DT, 8, MODE>), g, dim3(256), 0, st, S, n, o, d, out, rec,
+                       mlp, naive);
+  else
+    hipLaunchKernelGGL((render_kernel<DOM, DT, 16, MODE>), g, dim3(256), 0, st, S, n, o, d, out, rec,
+                       mlp, naive);
+}
+
+template <int MODE>
+static void dispatch(const SceneArgs& S, int dom, int dt, dim3 g, hipStream_t st, int64_t n,
+                     const float* o, const float* d, const RayOut& out, const MarchRecord& rec,
+                     const float* mlp, int naive) {
+#define NGPRT_CASE(DOMV, DTV)                                                       \
+  if (dom == DOMV && dt == DTV) {                                                   \
+    dispatch_l<MODE, DOMV, DTV>(S, g, st, n, o, d, out, rec, mlp, naive);           \
+    return;                                                                         \
+  }
+  NGPRT_CASE(DOM_BOX, DT_F32)
+  NGPRT_CASE(DOM_BOX, DT_BF16)
+  NGPRT_CASE(DOM_BOX, DT_FP8)
+  NGPRT_CASE(DOM_CONTRACT, DT_F32)
+  NGPRT_CASE(DOM_CONTRACT, DT_BF16)
+  NGPRT_CASE(DOM_CONTRACT, DT_FP8)
+#undef NGPRT_CASE
+}
+
+int launch_render(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const RayOut& out,
+                  hipStream_t st) {
+  SceneArgs S = scene_args(ctx);
+  const int64_t blocks = (n + 255) / 256;
+  if (blocks > 0x7FFFFFFF) return fail(ctx, NGPRT_E_SHAPE, "too many rays for one launch");
+  MarchRecord rec{nullptr, nullptr, nullptr, 0};
+  dispatch<MODE_RENDER>(S, ctx->desc.domain, ctx->desc.table_dtype, dim3(unsigned(blocks)), st, n, o,
+                        d, out, rec, ctx->mlp, 0);
+  return check_launch(ctx, "render_kernel");
+}
+
+int launch_march(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, int32_t cap,
+                 int32_t* sk, int32_t* ns, int32_t* nr, int naive, hipStream_t st) {
+  SceneArgs S = scene_args(ctx);
+  const int64_t blocks = (n + 255) / 256;
+  if (blocks > 0x7FFFFFFF) return fail(ctx, NGPRT_E_SHAPE, "too many rays for one launch");
+  MarchRecord rec{sk, ns, nr, cap};
+  RayOut out{};
+  dispatch<MODE_MARCH>(S, ctx->desc.domain, ctx->desc.table_dtype, dim3(unsigned(blocks)), st, n, o,
+                       d, out, rec, ctx->mlp, naive);
+  return check_launch(ctx, "march_kernel");
+}
+
+int launch_eval_points(ngprt_ctx* ctx, int64_t n, const float* pos, int32_t* idx, float* fused,
+                       float* weights, hipStream_t st) {
+  SceneArgs S = scene_args(ctx);
+  const int64_t blocks = (n + 255) / 256;
+  if (blocks > 0x7FFFFFFF) return fail(ctx, NGPRT_E_SHAPE, "too many points for one launch");
+  dim3 g = dim3(unsigned(blocks));
+  const int dt = ctx->desc.table_dtype;
+#define NGPRT_EV(DTV, LM)                                                                   \
+  hipLaunchKernelGGL((eval_points_kernel<DTV, LM>), g, dim3(256), 0, st, S, n, pos, idx, fused, \
+                     weights)
+  if (dt == DT_F32) { if (S.L <= 8) NGPRT_EV(DT_F32, 8); else NGPRT_EV(DT_F32, 16); }
+  if (dt == DT_BF16) { if (S.L <= 8) NGPRT_EV(DT_BF16, 8); else NGPRT_EV(DT_BF16, 16); }
+  if (dt == DT_FP8) { if (S.L <= 8) NGPRT_EV(DT_FP8, 8); else NGPRT_EV(DT_FP8, 16); }
+#undef NGPRT_EV
+  return check_launch(ctx, "eval_points_kernel");
+}
+
+}  // namespace ngprt

@@ -1,0 +1,144 @@
+"""PyTorch-facing wrapper of the C ABI.  PyTorch supplies device memory and
+the current stream; every step of the render path runs in libngprt.so."""
+from __future__ import annotations
+
+import ctypes
+from typing import Dict, Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import F32, BF16, FP8E4M3, ROI_BOX, ROI_CONTRACT, NgprtOutputs, check, load_library
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype, shape=None, name="tensor") -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+class Renderer:
+    """One library context (one scene) on the current device."""
+
+    def __init__(self, resolutions: Sequence[int], log2_table_size: int, table_dtype: int = F32,
+                 domain: int = ROI_BOX, roi_half: float = 1.0, occ_res: int = 64,
+                 step: float = 1.0 / 256.0, max_samples: int = 1024, t_threshold: float = 1e-4):
+        self.lib = load_library()
+        self.resolutions = list(resolutions)
+        self.L = len(self.resolutions)
+        self.T = 1 << log2_table_size
+        self.R = occ_res
+        self.table_dtype = table_dtype
+        self.desc = _lib.make_desc(resolutions, log2_table_size, table_dtype, domain, roi_half,
+                                   occ_res, step, max_samples, t_threshold)
+        ctx = ctypes.c_void_p()
+        check(self.lib.ngprt_create(ctypes.byref(self.desc), ctypes.byref(ctx)))
+        self.ctx = ctx
+
+    @classmethod
+    def from_config(cls, cfg, table_dtype: Optional[int] = None) -> "Renderer":
+        return cls(cfg.resolutions, cfg.log2_table, cfg.table_dtype if table_dtype is None else table_dtype,
+                   cfg.domain, cfg.roi_half, cfg.occ_res, cfg.step, cfg.max_samples, cfg.t_threshold)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.ngprt_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- loading
+    def load_tables(self, tables: torch.Tensor):
+        _dev(tables, torch.float32, (self.L, self.T, 9), "tables")
+        check(self.lib.ngprt_load_tables(self.ctx, _ptr(tables), _stream()), self.ctx)
+
+    def load_occupancy(self, occ: torch.Tensor, dist: Optional[torch.Tensor] = None):
+        _dev(occ, torch.uint8, (self.R, self.R, self.R), "occ")
+        if dist is not None:
+            _dev(dist, torch.uint8, (self.R, self.R, self.R), "dist")
+        check(self.lib.ngprt_load_occupancy(self.ctx, _ptr(occ), _ptr(dist), _stream()), self.ctx)
+
+    def load_mlp(self, params: torch.Tensor):
+        _dev(params, torch.float32, (451,), "mlp params")
+        check(self.lib.ngprt_load_mlp(self.ctx, _ptr(params), _stream()), self.ctx)
+
+    def load_scene(self, tables, occ, mlp, dist=None):
+        self.load_tables(tables)
+        self.load_occupancy(occ, dist)
+        self.load_mlp(mlp)
+
+    # ---------------------------------------------------------------- export
+    def export_tables(self):
+        dt = {F32: torch.float32, BF16: torch.int16, FP8E4M3: torch.uint8}[self.table_dtype]
+        codes = torch.empty((self.L, self.T, 9), dtype=dt, device="cuda")
+        scales = torch.empty((self.L, 9), dtype=torch.float32, device="cuda")
+        check(self.lib.ngprt_export_tables(self.ctx, _ptr(codes), _ptr(scales), _stream()), self.ctx)
+        return codes, scales
+
+    def export_distance(self) -> torch.Tensor:
+        out = torch.empty((self.R, self.R, self.R), dtype=torch.uint8, device="cuda")
+        check(self.lib.ngprt_export_distance(self.ctx, _ptr(out), _stream()), self.ctx)
+        return out
+
+    # ---------------------------------------------------------------- render
+    def render(self, origins: torch.Tensor, dirs: torch.Tensor, aux: bool = True,
+               out: Optional[Dict[str, torch.Tensor]] = None) -> Dict[str, torch.Tensor]:
+        n = origins.shape[0]
+        _dev(origins, torch.float32, (n, 3), "origins")
+        _dev(dirs, torch.float32, (n, 3), "dirs")
+        if out is None:
+            out = {"rgb": torch.empty((n, 3), dtype=torch.float32, device="cuda")}
+            if aux:
+                out.update(
+                    c_d=torch.empty((n, 3), dtype=torch.float32, device="cuda"),
+                    feat=torch.empty((n, 4), dtype=torch.float32, device="cuda"),
+                    t_final=torch.empty((n,), dtype=torch.float32, device="cuda"),
+                    depth=torch.empty((n,), dtype=torch.float32, device="cuda"),
+                    n_samples=torch.empty((n,), dtype=torch.int32, device="cuda"),
+                    n_reads=torch.empty((n,), dtype=torch.int32, device="cuda"))
+        o = NgprtOutputs()
+        for k in ("rgb", "c_d", "feat", "t_final", "depth", "n_samples", "n_reads"):
+            setattr(o, k, out[k].data_ptr() if k in out else None)
+        check(self.lib.ngprt_render(self.ctx, n, _ptr(origins), _ptr(dirs), ctypes.byref(o),
+                                    _stream()), self.ctx)
+        return out
+
+    # ---------------------------------------------------------------- debug
+    def eval_points(self, pos: torch.Tensor):
+        n = pos.shape[0]
+        _dev(pos, torch.float32, (n, 3), "pos")
+        idx = torch.empty((n, self.L, 8), dtype=torch.int32, device="cuda")
+        fused = torch.empty((n, 8), dtype=torch.float32, device="cuda")
+        w = torch.empty((n, self.L), dtype=torch.float32, device="cuda")
+        check(self.lib.ngprt_debug_eval_points(self.ctx, n, _ptr(pos), _ptr(idx), _ptr(fused), _ptr(w),
+                                               _stream()), self.ctx)
+        return idx, fused, w
+
+    def march(self, origins: torch.Tensor, dirs: torch.Tensor, cap: int = 64, naive: bool = False):
+        n = origins.shape[0]
+        _dev(origins, torch.float32, (n, 3), "origins")
+        _dev(dirs, torch.float32, (n, 3), "dirs")
+        sk = torch.empty((n, cap), dtype=torch.int32, device="cuda")
+        ns = torch.empty((n,), dtype=torch.int32, device="cuda")
+        nr = torch.empty((n,), dtype=torch.int32, device="cuda")
+        check(self.lib.ngprt_debug_march(self.ctx, n, _ptr(origins), _ptr(dirs), cap, _ptr(sk), _ptr(ns),
+                                         _ptr(nr), 1 if naive else 0, _stream()), self.ctx)
+        return sk, ns, nr

@@ -1,0 +1,42 @@
+"""Shared test helpers: seeded scenes on the GPU and the oracle beside them."""
+import functools
+
+import numpy as np
+
+import synth
+from oracle.distgrid import distance_grid_edt
+from oracle.render import inputs_from_scene
+
+
+@functools.lru_cache(maxsize=4)
+def scene_and_dist(name: str, dtype: int = 0):
+    cfg = synth.CONFIGS[name](table_dtype=dtype)
+    sc = synth.make_scene(cfg)
+    dist = distance_grid_edt(sc.occ)
+    return sc, dist
+
+
+def oracle_inputs(name: str, dtype: int = 0):
+    sc, dist = scene_and_dist(name, dtype)
+    return inputs_from_scene(sc, dist, dtype)
+
+
+def gpu_renderer(name: str, dtype: int = 0, **overrides):
+    import torch
+    from paper_2407_10482_amd.renderer import Renderer
+    sc, _ = scene_and_dist(name, dtype)
+    cfg = sc.cfg
+    kw = dict(resolutions=cfg.resolutions, log2_table_size=cfg.log2_table, table_dtype=dtype,
+              domain=cfg.domain, roi_half=cfg.roi_half, occ_res=cfg.occ_res, step=cfg.step,
+              max_samples=cfg.max_samples, t_threshold=cfg.t_threshold)
+    kw.update(overrides)
+    r = Renderer(**kw)
+    r.load_scene(torch.from_numpy(sc.tables).cuda(), torch.from_numpy(sc.occ).cuda(),
+                 torch.from_numpy(sc.mlp).cuda())
+    torch.cuda.synchronize()
+    return r
+
+
+def to_gpu(*arrays):
+    import torch
+    return [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrays]

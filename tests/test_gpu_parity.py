@@ -1,0 +1,224 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Integer outputs bit-exact; the float32 decision chain (fused density,
+attention weights, transmittance) bit-exact against the oracle's float32
+mirror; colours within 1e-5 of the float64 oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import quant
+from oracle.distgrid import distance_grid_edt
+from oracle.exact32 import F32
+from oracle.hashgrid import corners32
+from oracle.render import OracleInputs, fused32, fused64, grid_coords32, grid_coords64, render
+
+from helpers import gpu_renderer, oracle_inputs, scene_and_dist, to_gpu
+
+pytestmark = pytest.mark.gpu
+COLOUR_TOL = 1e-5
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+# ---------------------------------------------------------------- distance grid
+
+@pytest.mark.parametrize("name", ["tiny", "hd"])
+def test_distance_grid_bit_exact(name):
+    print(f"[distance grid {name}]", flush=True)
+    sc, dist = scene_and_dist(name)
+    r = gpu_renderer(name)
+    g = _np(r.export_distance())
+    assert np.array_equal(g, dist)
+
+
+def test_distance_grid_random_and_empty():
+    import torch
+    from paper_2407_10482_amd.renderer import Renderer
+    rng = np.random.default_rng(9)
+    for R, dens in ((24, 0.01), (37, 0.002), (16, 0.0), (8, 1.0)):
+        occ = (rng.uniform(size=(R, R, R)) < dens).astype(np.uint8)
+        r = Renderer([16], 10, occ_res=R)
+        (o,) = to_gpu(occ)
+        r.load_occupancy(o)
+        assert np.array_equal(_np(r.export_distance()), distance_grid_edt(occ)), (R, dens)
+
+
+# ---------------------------------------------------------------- tables
+
+@pytest.mark.parametrize("dtype", [0, 1, 2])
+def test_table_storage_bit_exact(dtype):
+    print(f"[tables dtype {dtype}]", flush=True)
+    inp = oracle_inputs("tiny", dtype)
+    r = gpu_renderer("tiny", dtype)
+    codes, scales = r.export_tables()
+    c = _np(codes)
+    if dtype == 0:
+        assert np.array_equal(c.view(np.uint32), inp.stored.view(np.uint32))
+    elif dtype == 1:
+        assert np.array_equal(c.view(np.uint16), inp.stored)
+    else:
+        assert np.array_equal(c, inp.stored)
+        assert np.array_equal(_np(scales).view(np.uint32), inp.scales.view(np.uint32))
+
+
+def test_fp8_encoder_edge_values():
+    """Halfway values, subnormals, saturation and signed zero through the
+    GPU encoder, against the oracle's table-search encoder."""
+    import torch
+    from paper_2407_10482_amd.renderer import Renderer
+    # amax of channels 0 and 8 is exactly 448, so their scale is 1 and the
+    # codes below are encoded unscaled
+    vals = [0.0, -0.0, 448.0, -448.0, 447.0, 2.0 ** -9, 2.0 ** -10, 3 * 2.0 ** -11,
+            2.0 ** -6, 2.0 ** -6 * 0.99, 1.0625, 1.1875, 240.0, 232.0, 248.0, 0.1, -0.3]
+    t = np.asarray(vals + list(quant.FP8_TABLE[np.isfinite(quant.FP8_TABLE)]), dtype=F32)
+    T = 1 << 10
+    tab = np.zeros((1, T, 9), F32)
+    tab[0, :len(t), 0] = t
+    tab[0, :len(t), 8] = -t
+    tab[0, :, 1:8] = rng_vals = np.random.default_rng(4).normal(0, 3, size=(T, 7)).astype(F32)
+    r = Renderer([16], 10, table_dtype=2)
+    (g,) = to_gpu(tab)
+    r.load_tables(g)
+    codes, scales = r.export_tables()
+    q, s = quant.quantize_tables_fp8(tab)
+    assert s[0, 0] == 1.0 and s[0, 8] == 1.0
+    assert np.array_equal(_np(codes), q)
+    assert np.array_equal(_np(scales), s)
+
+
+# ---------------------------------------------------------------- lookup + attention
+
+@pytest.mark.parametrize("dtype", [0, 1, 2])
+def test_eval_points_parity(dtype):
+    print(f"[eval points dtype {dtype}]", flush=True)
+    inp = oracle_inputs("tiny", dtype)
+    r = gpu_renderer("tiny", dtype)
+    rng = np.random.default_rng(dtype)
+    n = 3000
+    pos = rng.uniform(-1.0, 1.0, size=(n, 3)).astype(F32)
+    pos[:20] = np.array([[-1, -1, -1], [1, 1, 1], [1, -1, 0.5], [0, 0, 0]] * 5, F32)  # faces / corners
+    (p,) = to_gpu(pos)
+    idx, fused, w = (_np(x) for x in r.eval_points(p))
+    u = grid_coords32(inp, pos)
+    f32, w32, idx32 = fused32(inp, u)
+    assert np.array_equal(idx, idx32.astype(np.int32))
+    assert np.array_equal(w.view(np.uint32), w32.view(np.uint32))
+    assert np.array_equal(fused[:, 0].view(np.uint32), f32[:, 0].view(np.uint32))
+    f64, _ = fused64(inp, grid_coords64(inp, pos))
+    assert np.abs(fused - f64).max() < COLOUR_TOL
+
+
+# ---------------------------------------------------------------- march
+
+@pytest.mark.parametrize("naive", [False, True])
+def test_march_bit_exact_tiny(naive):
+    print(f"[march tiny naive={naive}]", flush=True)
+    inp = oracle_inputs("tiny")
+    sc, _ = scene_and_dist("tiny")
+    o, d, _ = synth.scene_rays(sc.cfg)
+    r = gpu_renderer("tiny")
+    go, gd = to_gpu(o, d)
+    cap = 64
+    sk, ns, nr = (_np(x) for x in r.march(go, gd, cap=cap, naive=naive))
+    ref = render(inp, o, d, naive=naive)
+    assert np.array_equal(ns, ref.n_samples)
+    assert np.array_equal(nr, ref.n_reads)
+    assert ref.n_samples.max() <= cap
+    exp = np.full((len(o), cap), -1, np.int32)
+    starts = np.r_[0, np.cumsum(ref.n_samples)[:-1]]
+    for i in range(len(o)):
+        exp[i, :ref.n_samples[i]] = ref.s_k[starts[i]:starts[i] + ref.n_samples[i]]
+    assert np.array_equal(sk, exp)
+
+
+# ---------------------------------------------------------------- render
+
+def _check_render(out, ref, tol=COLOUR_TOL):
+    assert np.array_equal(_np(out["n_samples"]), ref.n_samples)
+    assert np.array_equal(_np(out["n_reads"]), ref.n_reads)
+    assert np.array_equal(_np(out["t_final"]).view(np.uint32), ref.t_final32.view(np.uint32))
+    for k, v in (("rgb", ref.rgb), ("c_d", ref.c_d), ("feat", ref.feat)):
+        err = np.abs(_np(out[k]).astype(np.float64) - v).max()
+        assert err < tol, (k, err)
+    assert np.abs(_np(out["depth"]) - ref.depth).max() < 1e-4
+
+
+@pytest.mark.parametrize("dtype", [0, 1, 2])
+def test_render_parity_tiny(dtype):
+    print(f"[render tiny dtype {dtype}]", flush=True)
+    inp = oracle_inputs("tiny", dtype)
+    sc, _ = scene_and_dist("tiny")
+    o, d, _ = synth.scene_rays(sc.cfg)
+    r = gpu_renderer("tiny", dtype)
+    go, gd = to_gpu(o, d)
+    out = r.render(go, gd)
+    _check_render(out, render(inp, o, d))
+
+
+def test_render_edge_rays_and_ragged_batches():
+    print("[render edge rays]", flush=True)
+    inp = oracle_inputs("tiny")
+    sc, _ = scene_and_dist("tiny")
+    o, d, _ = synth.scene_rays(sc.cfg)
+    rng = np.random.default_rng(3)
+    extra_o = np.array([[np.nan, 0, 0], [0, 0, 0], [5, 5, 5], [0.2, 0.1, -3.0], [0.3, 0.3, 0.3],
+                        [0.0, 0.0, 0.0], [1.0, 1.0, 1.0], [-1.0, 0.5, 0.25]], F32)
+    extra_d = np.array([[0, 0, 1], [0, 0, 0], [1, 0, 0], [0, 0, 1], [0, np.inf, 0],
+                        [1, 0, 0], [-0.57735026, -0.57735026, -0.57735026], [1, 0, 0]], F32)
+    for n in (1, 63, 65, 257, 1000):
+        sel = rng.choice(len(o), size=n, replace=False)
+        oo = np.concatenate([extra_o, o[sel]])
+        dd = np.concatenate([extra_d, d[sel]])
+        r = gpu_renderer("tiny")
+        go, gd = to_gpu(oo, dd)
+        out = r.render(go, gd)
+        _check_render(out, render(inp, oo, dd))
+
+
+def test_render_zero_rays_is_noop():
+    import torch
+    r = gpu_renderer("tiny")
+    e = torch.empty((0, 3), dtype=torch.float32, device="cuda")
+    out = r.render(e, e)
+    assert out["rgb"].shape == (0, 3)
+
+
+@pytest.mark.parametrize("max_samples,thr", [(1, 1e-4), (3, 1e-4), (1024, 0.0)])
+def test_render_caps_and_no_termination(max_samples, thr):
+    print(f"[render cap {max_samples} thr {thr}]", flush=True)
+    sc, dist = scene_and_dist("tiny")
+    cfg = sc.cfg
+    inp = OracleInputs(tables=sc.tables, occ=sc.occ, dist=dist, mlp=sc.mlp, resolutions=cfg.resolutions,
+                       domain=cfg.domain, roi_half=cfg.roi_half, step=cfg.step, max_samples=max_samples,
+                       t_threshold=thr)
+    o, d, _ = synth.scene_rays(cfg)
+    o, d = o[::5], d[::5]
+    r = gpu_renderer("tiny", max_samples=max_samples, t_threshold=thr)
+    go, gd = to_gpu(o, d)
+    _check_render(r.render(go, gd), render(inp, o, d, terminate=thr > 0))
+
+
+def test_render_hd_full_frame_sampled():
+    """All 8 views at 1920x1080 in the benchmark's launch configuration;
+    a seeded sample of rays checked against the oracle one by one."""
+    import torch
+    print("[render hd full]", flush=True)
+    inp = oracle_inputs("hd")
+    sc, _ = scene_and_dist("hd")
+    o, d, _ = synth.scene_rays(sc.cfg)
+    r = gpu_renderer("hd")
+    go, gd = to_gpu(o, d)
+    out = r.render(go, gd)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    sel = np.sort(rng.choice(len(o), size=1200, replace=False))
+    ref = render(inp, o[sel], d[sel])
+    sub = {k: v[torch.from_numpy(sel).cuda()] for k, v in out.items()}
+    _check_render(sub, ref)
+    ns = _np(out["n_samples"])
+    print(f"hd: samples/ray {ns.mean():.2f} reads/ray {_np(out['n_reads']).mean():.2f}", flush=True)
