@@ -48,6 +48,13 @@ def frozen_samples(inp: OracleInputs, o, d):
     return m["s_ray"], m["s_pos"], m["s_t"]
 
 
+def grid_u(s_pos, roi_half):
+    """Float32 grid coordinates of sample positions, as float64."""
+    lo = np.float32(-roi_half)
+    inv = np.float32(1.0) / (np.float32(roi_half) - lo)
+    return ((np.asarray(s_pos, np.float32) - lo) * inv).astype(np.float64)
+
+
 def _levels64(tables64, resolutions, T, u):
     """Per-level interpolated values [m, L, 9], corner indices and weights."""
     vals, idxs, ws = [], [], []
@@ -62,7 +69,7 @@ def _levels64(tables64, resolutions, T, u):
 def forward64(tables64, mlp, resolutions, step, n_rays, s_ray, s_pos, roi_half=1.0):
     """Float64 forward on a frozen sample list; returns rgb and intermediates."""
     T = tables64.shape[1]
-    u = (np.asarray(s_pos, np.float64) + roi_half) / (2.0 * roi_half)
+    u = grid_u(s_pos, roi_half)
     lv, idx, wc = _levels64(tables64, resolutions, T, u)
     a = lv[:, :, 8]
     a = a - a.max(axis=1, keepdims=True)
@@ -173,7 +180,7 @@ def fd_table_grad(tables64, mlp, resolutions, step, n_rays, s_ray, s_pos, target
     Only rays with a sample touching the entry change, so the loss
     difference is summed over those rays alone (same value, less work)."""
     T = tables64.shape[1]
-    u = (np.asarray(s_pos, np.float64) + roi_half) / (2.0 * roi_half)
+    u = grid_u(s_pos, roi_half)
     idx = np.stack([corners64(u, N, T)[0] for N in resolutions], axis=1)   # [m, L, 8]
     out = []
     for (l, t, ch) in entries:

@@ -6,7 +6,7 @@ features, supplement "Multi-level Hash Features"):
 
 * grid coordinate u = (x - lo) * inv_extent in [0, 1]^3;
 * level l of resolution N_l: p = u * N_l, i0 = clamp(floor(p), 0, N_l - 1),
-  f = p - i0, corners i0 + b for b in {0,1}^3 (bit 0 -> x, 1 -> y, 2 -> z);
+  f = u * N_l - i0, corners i0 + b for b in {0,1}^3 (bit 0 -> x, 1 -> y, 2 -> z);
 * spatial hash h = (cx * 1) xor (cy * 2654435761) xor (cz * 805459861),
   each product taken modulo 2^32, then h mod T (T a power of two);
 * trilinear weight of corner b: prod over axes of (f if b else 1 - f).
@@ -42,13 +42,17 @@ def spatial_hash_py(cx: int, cy: int, cz: int, table_size: int) -> int:
 def corners32(u: np.ndarray, N: int, table_size: int):
     """Corner indices [m, 8] and float32 trilinear weights [m, 8] of one level.
 
-    u is float32 [m, 3]; the weights follow the float32 op order
-    w = (wx * wy) * wz.
+    u is float32 [m, 3].  p = fl32(u N) picks the cell; the fraction
+    f = fl32(u N - i0) is rounded once (a fused multiply-add), so it is
+    accurate to half an ulp of f even where u N is large; the weights follow
+    the float32 op order w = (wx * wy) * wz.
     """
     u = np.asarray(u, dtype=F32)
     p = u * F32(N)
     i0 = np.clip(np.floor(p), 0, N - 1).astype(np.int64)
-    f = p - i0.astype(F32)
+    # f = u*N - i0 rounded once (a fused multiply-add): the product of a
+    # float32 and an integer below 2^20 and the difference are exact in float64
+    f = (u.astype(np.float64) * N - i0).astype(F32)
     g = F32(1.0) - f
     idx = np.empty((u.shape[0], 8), dtype=np.int64)
     w = np.empty((u.shape[0], 8), dtype=F32)

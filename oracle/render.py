@@ -32,7 +32,9 @@ What one ray computes (paper sections in brackets):
 
 Decisions (steps 1-2 and the termination test) are taken in the float32
 mirror of exact32; all reported values are recomputed in float64 on the
-decided sample list.
+decided sample list, at the float32 grid coordinates u = fl32((x - lo) *
+inv_extent) of the decided lattice points (a sample's position is part of
+what the float32 lattice defines, like its index).
 """
 from __future__ import annotations
 
@@ -380,7 +382,7 @@ def render(inp: OracleInputs, o: np.ndarray, d: np.ndarray, naive: bool = False,
     n = o.shape[0]
     m = march(inp, o, d, naive=naive, terminate=terminate)
     if len(m["s_ray"]):
-        fz, _ = fused64(inp, grid_coords64(inp, m["s_pos"]))
+        fz, _ = fused64(inp, grid_coords32(inp, m["s_pos"]).astype(np.float64))
     else:
         fz = np.zeros((0, 8))
     c_d, feat, depth, T = composite64(inp, n, m["s_ray"], m["s_t"], fz)

@@ -109,7 +109,7 @@ def test_eval_points_parity(dtype):
     assert np.array_equal(idx, idx32.astype(np.int32))
     assert np.array_equal(w.view(np.uint32), w32.view(np.uint32))
     assert np.array_equal(fused[:, 0].view(np.uint32), f32[:, 0].view(np.uint32))
-    f64, _ = fused64(inp, grid_coords64(inp, pos))
+    f64, _ = fused64(inp, u.astype(np.float64))
     assert np.abs(fused - f64).max() < COLOUR_TOL
 
 
