@@ -160,6 +160,25 @@ int ngprt_debug_march(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins,
                       const float* dev_dirs, int32_t cap, int32_t* dev_sample_k,
                       int32_t* dev_n_samples, int32_t* dev_n_reads, int32_t naive, void* stream);
 
+/* Gradients of a loss through ngprt_render (a training extension).
+ * dev_grad_rgb: float32 [n][3] dL/drgb.  Accumulates (+=) dL/dtables into
+ * dev_grad_tables, float32 [L][T][9] in the layout ngprt_load_tables takes,
+ * and dL/dmlp into dev_grad_mlp, float32 [451]; the caller zeroes them.
+ * The forward is recomputed per ray (two re-marches, no per-sample state);
+ * table gradients are summed with float atomics, so their low bits depend
+ * on execution order.  Needs float32 tables (NGPRT_E_DTYPE otherwise).  May
+ * grow a library-owned workspace (stream-ordered allocation). */
+int ngprt_render_backward(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins,
+                          const float* dev_dirs, const float* dev_grad_rgb, float* dev_grad_tables,
+                          float* dev_grad_mlp, void* stream);
+
+/* One Adam update (Kingma & Ba; the paper's training uses beta1 = 0.9,
+ * beta2 = 0.99, eps = 1e-8, supplement "Optimization") over n float32
+ * parameters in place: m, v are the moment buffers (caller-owned, zero
+ * before step 1), step >= 1 the 1-based step for bias correction. */
+int ngprt_adam_step(int64_t n, float* dev_param, const float* dev_grad, float* dev_m, float* dev_v,
+                    int32_t step, float lr, float beta1, float beta2, float eps, void* stream);
+
 /* Human-readable name of a status code (static storage). */
 const char* ngprt_status_string(int status);
 

@@ -2,7 +2,8 @@
 
 What one ray computes (paper sections in brackets):
 
-1. Ray setup.  Box scenes: the ray enters and leaves the cube ROI at
+1. Ray setup (a ray with a non-finite component or a zero direction has no
+   samples).  Box scenes: the ray enters and leaves the cube ROI at
    [t0, t1) by the slab test; lattice t_k = t0 + k * step.  Contracted scenes:
    the scene lives in the image of x -> x (|x| <= 1), (2 - 1/|x|) x/|x|
    (|x| > 1); the ray starts at t = 0 and advances by equal contracted arc
@@ -13,7 +14,8 @@ What one ray computes (paper sections in brackets):
    skip march reads the distance grid G (Eq. 9): after reading G = g > 0 at a
    lattice point, points within g voxels of it (less a margin) are known to be
    empty and are not read.  Box scenes turn that into a jump of
-   floor(g * (voxel / step) / |d|) lattice points; contracted scenes keep a
+   floor(g * (voxel / step) / |d|) lattice points (at most 2^16, the
+   lattice bound); contracted scenes keep a
    ball of radius g * voxel - voxel/1024 around the read point.  The naive
    march reads every lattice point; both must yield the same samples
    (the paper's Table 4: the occupied-point count is unchanged by G).
@@ -234,6 +236,7 @@ def march(inp: OracleInputs, o: np.ndarray, d: np.ndarray, naive: bool = False,
     dn = sqrt32(dn2)
     if inp.domain == BOX:
         t0, t1, alive = ray_box32(o, d, inp.roi_half)
+        alive &= dn2 > 0
         with np.errstate(divide="ignore", invalid="ignore"):
             rho = (vox / step) / dn
         next_read = np.zeros(n, dtype=np.int64)
@@ -292,7 +295,8 @@ def march(inp: OracleInputs, o: np.ndarray, d: np.ndarray, naive: bool = False,
         g = inp.dist_flat[vflat[need]].astype(np.int64)
         if not naive:
             if inp.domain == BOX:
-                jump = np.floor(g.astype(F32) * rho[rd]).astype(np.int64)
+                jf = np.floor(g.astype(F32) * rho[rd])
+                jump = np.where(jf < F32(MAX_LATTICE), jf, F32(MAX_LATTICE)).astype(np.int64)
                 upd = (~occv) & (g > 0)
                 next_read[rd[upd]] = k + np.maximum(jump[upd], 1)
             else:

@@ -56,6 +56,9 @@ SIGNATURES = [
     ("ngprt_render", ctypes.c_int, [_P, _I64, _P, _P, ctypes.POINTER(NgprtOutputs), _P]),
     ("ngprt_debug_eval_points", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P]),
     ("ngprt_debug_march", ctypes.c_int, [_P, _I64, _P, _P, _I32, _P, _P, _P, _I32, _P]),
+    ("ngprt_render_backward", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P]),
+    ("ngprt_adam_step", ctypes.c_int, [_I64, _P, _P, _P, _P, _I32, ctypes.c_float, ctypes.c_float,
+                                       ctypes.c_float, ctypes.c_float, _P]),
     ("ngprt_status_string", ctypes.c_char_p, [ctypes.c_int]),
     ("ngprt_last_error", ctypes.c_char_p, [_P]),
 ]

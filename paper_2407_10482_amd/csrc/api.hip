@@ -113,6 +113,7 @@ void ngprt_destroy(ngprt_ctx* ctx) {
   if (ctx->scales_dev) (void)hipFree(ctx->scales_dev);
   if (ctx->grid) (void)hipFree(ctx->grid);
   if (ctx->mlp) (void)hipFree(ctx->mlp);
+  if (ctx->ws) (void)hipFree(ctx->ws);
   if (switched) (void)hipSetDevice(cur);
   delete ctx;
 }
@@ -202,8 +203,8 @@ int ngprt_render(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins, const
                  const ngprt_outputs* out, void* stream) {
   if (!ctx) return NGPRT_E_INVALID_ARG;
   if (n_rays < 0) return fail(ctx, NGPRT_E_INVALID_ARG, "n_rays < 0");
-  if (!out || !out->rgb) return fail(ctx, NGPRT_E_INVALID_ARG, "out->rgb is required");
   if (n_rays == 0) return NGPRT_OK;
+  if (!out || !out->rgb) return fail(ctx, NGPRT_E_INVALID_ARG, "out->rgb is required");
   if (!dev_origins || !dev_dirs) return fail(ctx, NGPRT_E_INVALID_ARG, "ray pointers are NULL");
   int rc = check_ready(ctx);
   if (rc) return rc;
@@ -234,6 +235,35 @@ int ngprt_debug_march(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins, 
   if (rc) return rc;
   return launch_march(ctx, n_rays, dev_origins, dev_dirs, cap, dev_sample_k, dev_n_samples,
                       dev_n_reads, naive, (hipStream_t)stream);
+}
+
+int ngprt_render_backward(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins, const float* dev_dirs,
+                          const float* dev_grad_rgb, float* dev_grad_tables, float* dev_grad_mlp,
+                          void* stream) {
+  if (!ctx) return NGPRT_E_INVALID_ARG;
+  if (n_rays < 0) return fail(ctx, NGPRT_E_INVALID_ARG, "n_rays < 0");
+  if (n_rays == 0) return NGPRT_OK;
+  if (!dev_origins || !dev_dirs || !dev_grad_rgb || !dev_grad_tables || !dev_grad_mlp)
+    return fail(ctx, NGPRT_E_INVALID_ARG, "NULL pointer");
+  if (ctx->desc.table_dtype != NGPRT_F32)
+    return fail(ctx, NGPRT_E_DTYPE, "backward needs float32 tables");
+  int rc = check_ready(ctx);
+  if (rc) return rc;
+  if (!ctx->mlp_loaded) return fail(ctx, NGPRT_E_NOT_LOADED, "mlp not loaded");
+  return launch_backward(ctx, n_rays, dev_origins, dev_dirs, dev_grad_rgb, dev_grad_tables, dev_grad_mlp,
+                         (hipStream_t)stream);
+}
+
+int ngprt_adam_step(int64_t n, float* dev_param, const float* dev_grad, float* dev_m, float* dev_v,
+                    int32_t step, float lr, float beta1, float beta2, float eps, void* stream) {
+  if (n < 0 || step < 1) return NGPRT_E_INVALID_ARG;
+  if (n == 0) return NGPRT_OK;
+  if (!dev_param || !dev_grad || !dev_m || !dev_v) return NGPRT_E_INVALID_ARG;
+  if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f) ||
+      !std::isfinite(lr))
+    return NGPRT_E_INVALID_ARG;
+  return launch_adam(n, dev_param, dev_grad, dev_m, dev_v, step, lr, beta1, beta2, eps,
+                     (hipStream_t)stream);
 }
 
 }  // extern "C"

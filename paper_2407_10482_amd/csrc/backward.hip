@@ -1,0 +1,333 @@
+// Backward of the render path (a training extension; the paper trains its
+// model but states no gradient code).  FP32 tables only.
+//
+// Forward state is recomputed per ray instead of stored per sample:
+//  pass 1  re-march the ray: composited C_d and F (Eq. 2, Eq. 5); then, per
+//          lane, the deferred MLP forward and backward give dL/dC_d, dL/dF,
+//          and per-ray outer products whose sum over the wave's 64 rays is
+//          taken on v_mfma_f32_16x16x4_f32 (K = rays) and written as one
+//          451-float partial per wave;
+//  pass 2  re-march again with the same decisions; at each sample
+//          dL/dsigma_i = delta (T_{i+1} s_i - (S - P_i)) with
+//          s_i = dL/dC_d . c_i + dL/dF . v_i, S = dL/dC_d . C_d + dL/dF . F and
+//          P_i the running sum of w_j s_j; then the softmax adjoint
+//          dL/da_l = w_l (dL/df . v_l - dL/df . f) and the trilinear scatter of
+//          every level's 9-channel gradient into its 8 corner entries with
+//          hardware float atomics (order-nondeterministic sums).
+// A second kernel reduces the per-wave MLP partials in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "device.h"
+#include "internal.h"
+#include "march.h"
+
+namespace ngprt {
+
+typedef float bf32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kPad = 17;   // LDS row pitch of the per-wave staging (bank spread)
+
+// D[i][j] = sum over the wave's 64 rays r of A_r[i] * B_r[j] (i, j < 16).
+// sA, sB: [64][kPad].  Lane l returns D[4*(l/16) + q][l%16], q = 0..3.
+__device__ __forceinline__ bf32x4 wave_outer_sum(const float* sA, const float* sB, int lane) {
+  const int i = lane & 15, s = lane >> 4;
+  bf32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    const int r = 4 * c + s;
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(sA[r * kPad + i], sB[r * kPad + i], acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+template <int DOM, int LMAX>
+__global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, const float* __restrict__ O,
+                                                       const float* __restrict__ D,
+                                                       const float* __restrict__ grad_rgb,
+                                                       float* __restrict__ gtab, float* __restrict__ partial,
+                                                       const float* __restrict__ P) {
+  __shared__ float sA_all[4][64 * kPad];
+  __shared__ float sB_all[4][64 * kPad];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t ray = (int64_t(blockIdx.x) * 4 + wave) * 64 + lane;
+  const bool in_range = ray < n;
+  const float* o = O + 3 * (in_range ? ray : 0);
+  const float* d = D + 3 * (in_range ? ray : 0);
+
+  // ---------------- pass 1: forward
+  MarchState m;
+  march_init<DOM>(S, o, d, in_range, m);
+  float T = 1.0f, cd[3] = {0.f, 0.f, 0.f}, fv[4] = {0.f, 0.f, 0.f, 0.f};
+  int ns = 0, reads = 0;
+  for (;;) {
+    float u[3], ts;
+    int ks;
+    bool have = march_next<DOM>(S, m, false, reads, u, ts, ks);
+    if (__ballot(have) == 0) break;
+    if (have) {
+      float f[8];
+      eval_fused<DT_F32, LMAX>(S, u, f);
+      const float sigma = exp32(f[0]);
+      const float e = exp32(-(sigma * S.step));
+      const float w = T * (1.0f - e);
+      for (int j = 0; j < 3; ++j) cd[j] = __builtin_fmaf(w, f[1 + j], cd[j]);
+      for (int j = 0; j < 4; ++j) fv[j] = __builtin_fmaf(w, f[4 + j], fv[j]);
+      T = T * e;
+      ++ns;
+      if (T < S.thr || ns >= S.max_samples) m.done = true;
+    }
+  }
+
+  // ---------------- deferred MLP forward + backward (per lane)
+  float x[8] = {cd[0], cd[1], cd[2], fv[0], fv[1], fv[2], fv[3], 1.0f};
+  float z1[16], h1[16], z2[16], h2[16], oo[3];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    float a = P[112 + i];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) a = __builtin_fmaf(P[i * 7 + k], x[k], a);
+    z1[i] = a;
+    h1[i] = fmaxf(a, 0.0f);
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    float a = P[384 + i];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) a = __builtin_fmaf(P[128 + i * 16 + k], h1[k], a);
+    z2[i] = a;
+    h2[i] = fmaxf(a, 0.0f);
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    float a = P[448 + i];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) a = __builtin_fmaf(P[400 + i * 16 + k], h2[k], a);
+    oo[i] = a;
+  }
+  float gz[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const float C = 1.0f / (1.0f + __expf(-(cd[j] + oo[j])));
+    const float g = in_range ? grad_rgb[ray * 3 + j] : 0.0f;
+    gz[j] = g * C * (1.0f - C);
+  }
+  float gz2[16], gz1[16], gx[7];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    float a = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) a = __builtin_fmaf(P[400 + i * 16 + k], gz[i], a);
+    gz2[k] = z2[k] > 0.0f ? a : 0.0f;
+  }
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    float a = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) a = __builtin_fmaf(P[128 + i * 16 + k], gz2[i], a);
+    gz1[k] = z1[k] > 0.0f ? a : 0.0f;
+  }
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    float a = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) a = __builtin_fmaf(P[i * 7 + k], gz1[i], a);
+    gx[k] = a;
+  }
+  float gcd[3] = {gz[0] + gx[0], gz[1] + gx[1], gz[2] + gx[2]};
+  float gfv[4] = {gx[3], gx[4], gx[5], gx[6]};
+  const float Stot = (gcd[0] * cd[0] + gcd[1] * cd[1] + gcd[2] * cd[2]) +
+                     (gfv[0] * fv[0] + gfv[1] * fv[1] + gfv[2] * fv[2] + gfv[3] * fv[3]);
+
+  // ---------------- MLP weight gradients: sums over the wave on MFMA
+  float* sA = sA_all[wave];
+  float* sB = sB_all[wave];
+  float* part = partial + (int64_t(blockIdx.x) * 4 + wave) * kMlpParams;
+  const int qi = lane >> 4, col = lane & 15;
+  // W0 (16 x 7) and b0 (column 7 of x is 1)
+#pragma unroll
+  for (int i = 0; i < 16; ++i) sA[lane * kPad + i] = gz1[i];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) sB[lane * kPad + j] = j < 8 ? x[j < 8 ? j : 0] : 0.0f;
+  __syncthreads();
+  {
+    bf32x4 r = wave_outer_sum(sA, sB, lane);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = 4 * qi + q;
+      if (col < 7) part[i * 7 + col] = r[q];
+      else if (col == 7) part[112 + i] = r[q];
+    }
+  }
+  __syncthreads();
+  // W1 (16 x 16) and b1
+#pragma unroll
+  for (int i = 0; i < 16; ++i) sA[lane * kPad + i] = gz2[i];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) sB[lane * kPad + j] = h1[j];
+  __syncthreads();
+  {
+    bf32x4 r = wave_outer_sum(sA, sB, lane);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) part[128 + (4 * qi + q) * 16 + col] = r[q];
+    if (lane < 16) {
+      float a = 0.0f;
+      for (int rr = 0; rr < 64; ++rr) a += sA[rr * kPad + lane];
+      part[384 + lane] = a;
+    }
+  }
+  __syncthreads();
+  // W2 (3 x 16) and b2
+#pragma unroll
+  for (int i = 0; i < 16; ++i) sA[lane * kPad + i] = i < 3 ? gz[i < 3 ? i : 0] : 0.0f;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) sB[lane * kPad + j] = h2[j];
+  __syncthreads();
+  {
+    bf32x4 r = wave_outer_sum(sA, sB, lane);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = 4 * qi + q;
+      if (i < 3) part[400 + i * 16 + col] = r[q];
+    }
+    if (lane < 3) {
+      float a = 0.0f;
+      for (int rr = 0; rr < 64; ++rr) a += sA[rr * kPad + lane];
+      part[448 + lane] = a;
+    }
+  }
+
+  // ---------------- pass 2: re-march and scatter
+  march_init<DOM>(S, o, d, in_range, m);
+  T = 1.0f;
+  ns = 0;
+  float Pc = 0.0f;
+  const size_t T_entries = size_t(1) << S.log2T;
+  for (;;) {
+    float u[3], ts;
+    int ks;
+    bool have = march_next<DOM>(S, m, false, reads, u, ts, ks);
+    if (__ballot(have) == 0) break;
+    if (have) {
+      float f[8], wl[LMAX];
+      eval_fused<DT_F32, LMAX>(S, u, f, wl);
+      const float sigma = exp32(f[0]);
+      const float e = exp32(-(sigma * S.step));
+      const float w = T * (1.0f - e);
+      const float s = (gcd[0] * f[1] + gcd[1] * f[2] + gcd[2] * f[3]) +
+                      (gfv[0] * f[4] + gfv[1] * f[5] + gfv[2] * f[6] + gfv[3] * f[7]);
+      Pc = __builtin_fmaf(w, s, Pc);
+      const float Tn = T * e;
+      const float gsig = S.step * (Tn * s - (Stot - Pc));
+      float gf[8];
+      gf[0] = sigma * gsig;
+      for (int j = 0; j < 3; ++j) gf[1 + j] = w * gcd[j];
+      for (int j = 0; j < 4; ++j) gf[4 + j] = w * gfv[j];
+      float gff = 0.0f;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) gff = __builtin_fmaf(gf[j], f[j], gff);
+#pragma unroll
+      for (int l = 0; l < LMAX; ++l) {
+        if (l >= S.L) break;
+        Corners c;
+        level_corners(u, S.N[l], S.Nf[l], S.mask, c);
+        const size_t base = size_t(l) << S.log2T;
+        float v[8][8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) Store<DT_F32>::feat(S.feat, base + c.idx[k], v[k]);
+        float gw = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          float acc = 0.0f;
+#pragma unroll
+          for (int k = 0; k < 8; ++k) acc = __builtin_fmaf(c.w[k], v[k][j], acc);
+          gw = __builtin_fmaf(gf[j], acc, gw);
+        }
+        const float ga = wl[l] * (gw - gff);
+        float gv[9];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) gv[j] = wl[l] * gf[j];
+        gv[8] = ga;
+        float* gbase = gtab + (size_t(l) * T_entries) * 9;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          float* dst = gbase + size_t(c.idx[k]) * 9;
+#pragma unroll
+          for (int j = 0; j < 9; ++j) unsafeAtomicAdd(dst + j, c.w[k] * gv[j]);
+        }
+      }
+      T = Tn;
+      ++ns;
+      if (T < S.thr || ns >= S.max_samples) m.done = true;
+    }
+  }
+}
+
+__global__ void reduce_partials_kernel(const float* __restrict__ partial, int64_t n_waves,
+                                       float* __restrict__ out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= kMlpParams) return;
+  float a = 0.0f;
+  for (int64_t w = 0; w < n_waves; ++w) a += partial[w * kMlpParams + p];
+  out[p] += a;
+}
+
+__global__ void adam_kernel(int64_t n, float* __restrict__ p, const float* __restrict__ g,
+                            float* __restrict__ m, float* __restrict__ v, float lr, float b1, float b2,
+                            float eps, float c1, float c2) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+int launch_backward(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const float* grad_rgb,
+                    float* gtab, float* gmlp, hipStream_t st) {
+  SceneArgs S = scene_args(ctx);
+  const int64_t blocks = (n + 255) / 256;
+  if (blocks > 0x7FFFFFFF) return fail(ctx, NGPRT_E_SHAPE, "too many rays for one launch");
+  const int64_t n_waves = blocks * 4;
+  const size_t need = size_t(n_waves) * kMlpParams * sizeof(float);
+  if (need > ctx->ws_bytes) {
+    if (ctx->ws) (void)hipFreeAsync(ctx->ws, st);
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+    if (hipMallocAsync(&ctx->ws, need, st) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(ctx, NGPRT_E_ALLOC, "backward workspace allocation failed");
+    }
+    ctx->ws_bytes = need;
+  }
+  float* partial = reinterpret_cast<float*>(ctx->ws);
+  dim3 g = dim3(unsigned(blocks));
+  const bool box = ctx->desc.domain == DOM_BOX;
+  if (S.L <= 8) {
+    if (box) hipLaunchKernelGGL((backward_kernel<DOM_BOX, 8>), g, dim3(256), 0, st, S, n, o, d, grad_rgb, gtab, partial, ctx->mlp);
+    else hipLaunchKernelGGL((backward_kernel<DOM_CONTRACT, 8>), g, dim3(256), 0, st, S, n, o, d, grad_rgb, gtab, partial, ctx->mlp);
+  } else {
+    if (box) hipLaunchKernelGGL((backward_kernel<DOM_BOX, 16>), g, dim3(256), 0, st, S, n, o, d, grad_rgb, gtab, partial, ctx->mlp);
+    else hipLaunchKernelGGL((backward_kernel<DOM_CONTRACT, 16>), g, dim3(256), 0, st, S, n, o, d, grad_rgb, gtab, partial, ctx->mlp);
+  }
+  int rc = check_launch(ctx, "backward_kernel");
+  if (rc) return rc;
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(2), dim3(256), 0, st, partial, n_waves, gmlp);
+  return check_launch(ctx, "reduce_partials_kernel");
+}
+
+int launch_adam(int64_t n, float* p, const float* g, float* m, float* v, int32_t step, float lr, float b1,
+                float b2, float eps, hipStream_t st) {
+  const double c1 = 1.0 / (1.0 - std::pow(double(b1), double(step)));
+  const double c2 = 1.0 / (1.0 - std::pow(double(b2), double(step)));
+  const int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(adam_kernel, dim3(unsigned(blocks)), dim3(256), 0, st, n, p, g, m, v, lr, b1, b2, eps,
+                     float(c1), float(c2));
+  return hipGetLastError() == hipSuccess ? NGPRT_OK : NGPRT_E_HIP;
+}
+
+}  // namespace ngprt

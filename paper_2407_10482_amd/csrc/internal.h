@@ -61,6 +61,8 @@ struct ngprt_ctx {
   float scales_host[NGPRT_MAX_LEVELS][9];
   uint16_t* grid = nullptr;   // [R^3]
   float* mlp = nullptr;       // [451]
+  void* ws = nullptr;         // backward workspace (per-wave MLP gradient partials)
+  size_t ws_bytes = 0;
   bool tables_loaded = false;
   bool occ_loaded = false;
   bool mlp_loaded = false;
@@ -83,4 +85,8 @@ int launch_eval_points(ngprt_ctx* ctx, int64_t n, const float* pos, int32_t* idx
                        float* weights, hipStream_t s);
 int launch_march(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, int32_t cap,
                  int32_t* sk, int32_t* ns, int32_t* nr, int naive, hipStream_t s);
+int launch_backward(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const float* grad_rgb,
+                    float* gtab, float* gmlp, hipStream_t s);
+int launch_adam(int64_t n, float* p, const float* g, float* m, float* v, int32_t step, float lr,
+                float b1, float b2, float eps, hipStream_t s);
 }  // namespace ngprt

@@ -60,7 +60,7 @@ __device__ __forceinline__ void march_init(const SceneArgs& S, const float* o, c
         valid = valid && (m.o[a] >= lo) && (m.o[a] <= hi);
       }
     }
-    valid = valid && (t0 < t1);
+    valid = valid && (t0 < t1) && (m.dn2 > 0.0f);
     m.t0 = t0;
     m.t1 = t1;
     m.rho = S.v_over_step / m.dn;
@@ -145,7 +145,8 @@ __device__ __forceinline__ bool march_next(const SceneArgs& S, MarchState& m, bo
     if (!naive) {
       if (DOM == DOM_BOX) {
         if (g > 0) {
-          int jump = (int)floorf((float)g * m.rho);
+          const float jf = floorf((float)g * m.rho);
+          const int jump = jf < (float)kMaxLattice ? (int)jf : kMaxLattice;
           m.k = kcur + (jump > 1 ? jump : 1);
         }
       } else {

@@ -142,3 +142,55 @@ class Renderer:
         check(self.lib.ngprt_debug_march(self.ctx, n, _ptr(origins), _ptr(dirs), cap, _ptr(sk), _ptr(ns),
                                          _ptr(nr), 1 if naive else 0, _stream()), self.ctx)
         return sk, ns, nr
+
+
+def _renderer_backward(self: Renderer, origins, dirs, grad_rgb, grad_tables, grad_mlp):
+    """Accumulate dL/dtables [L, T, 9] and dL/dmlp [451] for dL/drgb."""
+    n = origins.shape[0]
+    _dev(grad_rgb, torch.float32, (n, 3), "grad_rgb")
+    _dev(grad_tables, torch.float32, (self.L, self.T, 9), "grad_tables")
+    _dev(grad_mlp, torch.float32, (451,), "grad_mlp")
+    check(self.lib.ngprt_render_backward(self.ctx, n, _ptr(origins), _ptr(dirs), _ptr(grad_rgb),
+                                         _ptr(grad_tables), _ptr(grad_mlp), _stream()), self.ctx)
+
+
+Renderer.backward = _renderer_backward
+
+
+def adam_step(param: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int,
+              lr: float, beta1: float = 0.9, beta2: float = 0.99, eps: float = 1e-8):
+    """In-place Adam update on the GPU (library kernel)."""
+    for t, name in ((param, "param"), (grad, "grad"), (m, "m"), (v, "v")):
+        _dev(t, torch.float32, param.shape, name)
+    check(load_library().ngprt_adam_step(param.numel(), _ptr(param), _ptr(grad), _ptr(m), _ptr(v), int(step),
+                                         float(lr), float(beta1), float(beta2), float(eps), _stream()))
+
+
+class RenderFunction(torch.autograd.Function):
+    """rgb = render(tables, mlp; rays) with the library's hand-written backward.
+
+    forward loads `tables` (float32 [L, T, 9]) and `mlp` (float32 [451]) into
+    the renderer and renders; backward recomputes the forward per ray inside
+    the library and returns dL/dtables and dL/dmlp."""
+
+    @staticmethod
+    def forward(ctx, tables, mlp, origins, dirs, renderer):
+        renderer.load_tables(tables.detach().contiguous())
+        renderer.load_mlp(mlp.detach().contiguous())
+        out = renderer.render(origins, dirs, aux=False)
+        ctx.renderer = renderer
+        ctx.save_for_backward(origins, dirs)
+        return out["rgb"]
+
+    @staticmethod
+    def backward(ctx, grad_rgb):
+        origins, dirs = ctx.saved_tensors
+        r = ctx.renderer
+        gt = torch.zeros((r.L, r.T, 9), dtype=torch.float32, device=origins.device)
+        gm = torch.zeros((451,), dtype=torch.float32, device=origins.device)
+        r.backward(origins, dirs, grad_rgb.contiguous().float(), gt, gm)
+        return gt, gm, None, None, None
+
+
+def render_differentiable(renderer: Renderer, tables, mlp, origins, dirs):
+    return RenderFunction.apply(tables, mlp, origins, dirs, renderer)

@@ -332,8 +332,8 @@ def test_empty_rays_get_sigmoid_of_mlp_of_zero():
     tab = rng.normal(size=(3, 1 << 10, 9)).astype(F32)
     mlp = rng.normal(0, 0.3, size=451).astype(F32)
     inp = _tiny_inputs(tab, res=(16, 23, 35), mlp=mlp)
-    o = np.array([[3.0, 3.0, 3.0], [0.0, 0.0, 0.0], [np.nan, 0, 0]], F32)
-    d = np.array([[1.0, 0.0, 0.0], [0.0, 0.0, 1.0], [0, 0, 1]], F32)
+    o = np.array([[3.0, 3.0, 3.0], [0.0, 0.0, 0.0], [np.nan, 0, 0], [0.1, 0.1, 0.1]], F32)
+    d = np.array([[1.0, 0.0, 0.0], [0.0, 0.0, 1.0], [0, 0, 1], [0, 0, 0]], F32)
     r = render(inp, o, d)
     ref = 1.0 / (1.0 + np.exp(-mlp64(mlp, np.zeros((1, 7)))))
     assert (r.n_samples == 0).all()
