@@ -247,7 +247,7 @@ def march(inp: OracleInputs, o: np.ndarray, d: np.ndarray, naive: bool = False,
         ball_c = np.zeros((n, 3), dtype=F32)
         ball_r2 = np.zeros(n, dtype=F32)
         margin = vox * F32(1.0 / 1024.0)
-    rec_ray, rec_k, rec_t, rec_pos = [], [], [], []
+    rec_ray, rec_k, rec_t, rec_pos, rec_T = [], [], [], [], []
     k = 0
     while alive.any() and k < MAX_LATTICE:
         ids = np.nonzero(alive)[0]
@@ -319,6 +319,7 @@ def march(inp: OracleInputs, o: np.ndarray, d: np.ndarray, naive: bool = False,
             rec_k.append(np.full(len(smp), k, dtype=np.int64))
             rec_t.append(tk[need][occv])
             rec_pos.append(spos)
+            rec_T.append(T[smp].copy())
             stop = (T[smp] < thr) | (nsamp[smp] >= inp.max_samples)
             alive[smp[stop]] = False
         if inp.domain == CONTRACT:
@@ -330,15 +331,17 @@ def march(inp: OracleInputs, o: np.ndarray, d: np.ndarray, naive: bool = False,
         s_k = np.concatenate(rec_k)
         s_t = np.concatenate(rec_t).astype(F32)
         s_pos = np.concatenate(rec_pos).astype(F32)
+        s_T = np.concatenate(rec_T).astype(F32)
         order = np.lexsort((s_k, s_ray))
-        s_ray, s_k, s_t, s_pos = s_ray[order], s_k[order], s_t[order], s_pos[order]
+        s_ray, s_k, s_t, s_pos, s_T = s_ray[order], s_k[order], s_t[order], s_pos[order], s_T[order]
     else:
         s_ray = np.zeros(0, np.int64)
         s_k = np.zeros(0, np.int64)
         s_t = np.zeros(0, F32)
         s_pos = np.zeros((0, 3), F32)
+        s_T = np.zeros(0, F32)
     return dict(n_samples=nsamp.astype(np.int32), n_reads=nreads.astype(np.int32),
-                t_final32=T, s_ray=s_ray, s_k=s_k, s_t=s_t, s_pos=s_pos)
+                t_final32=T, s_ray=s_ray, s_k=s_k, s_t=s_t, s_pos=s_pos, s_T=s_T)
 
 
 def mlp64(params: np.ndarray, x: np.ndarray, dims=(7, 16, 16, 3)) -> np.ndarray:
@@ -395,7 +398,7 @@ def render(inp: OracleInputs, o: np.ndarray, d: np.ndarray, naive: bool = False,
     return RenderResult(n_samples=m["n_samples"], n_reads=m["n_reads"],
                         t_final32=m["t_final32"], t_final=T, c_d=c_d, feat=feat,
                         depth=depth, rgb=rgb, s_ray=m["s_ray"], s_k=m["s_k"],
-                        s_t=m["s_t"], s_pos=m["s_pos"])
+                        s_t=m["s_t"], s_pos=m["s_pos"], extra={"s_T": m["s_T"]})
 
 
 def inputs_from_scene(scene, dist: np.ndarray, dtype: int = DT_F32) -> OracleInputs:

@@ -1,0 +1,68 @@
+"""Pins of the proposal-network oracle: Fourier features in closed form,
+gradients against central finite differences, labels on a closed-form slab."""
+import math
+
+import numpy as np
+
+from oracle import proposal as P
+from oracle.exact32 import F32
+
+
+def test_fourier_closed_form():
+    o = np.array([[0.5, 0.0, 0.25]])
+    d = np.array([[1.0, -0.5, 0.125]])
+    enc = P.fourier(o, d)
+    r = [0.5, 0.0, 0.25, 1.0, -0.5, 0.125]
+    for j in range(6):
+        for k in range(4):
+            assert math.isclose(enc[0, 8 * j + 2 * k], math.sin(2 ** k * math.pi * r[j]), abs_tol=1e-12)
+            assert math.isclose(enc[0, 8 * j + 2 * k + 1], math.cos(2 ** k * math.pi * r[j]), abs_tol=1e-12)
+    assert enc[0, 0] == 1.0 and abs(enc[0, 1]) < 1e-15          # sin(pi/2), cos(pi/2)
+    assert P.N_PARAMS == 7556 and P.init_params(0).size == 7556
+
+
+def test_proposal_gradient_matches_finite_differences():
+    rng = np.random.default_rng(0)
+    n = 40
+    o = rng.normal(size=(n, 3)) * 0.3
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    enc = P.fourier(o, d)
+    p = P.init_params(1).astype(np.float64)
+    p[3072:3136] = rng.normal(size=64) * 0.1
+    labels = rng.uniform(0, 2, size=(n, 4))
+    valid = rng.uniform(size=n) < 0.8
+    for phase in (1, 2):
+        f = P.forward(p, enc, bf16_operands=False)
+        loss, g = P.loss_and_grad_out(f["out"], labels, valid, phase, 0.05)
+        grad = P.backward(p, f, g, bf16_operands=False)
+        # finite differences with the confidence target held fixed (it is a
+        # non-differentiable function of the outputs)
+        tgt_valid = valid
+        idx = list(range(0, P.N_PARAMS, 97)) + [P.N_PARAMS - 1, 7296, 7552]
+        h = 1e-6
+        for i in idx:
+            def L(pp):
+                ff = P.forward(pp, enc, bf16_operands=False)
+                out = ff["out"]
+                v = tgt_valid.astype(np.float64)
+                val = np.sum(((out[:, :3] - labels[:, :3]) * v[:, None]) ** 2) / n
+                if phase >= 2:
+                    tgt = P.conf_target(f["out"], labels, valid, 0.05)
+                    s = 1 / (1 + np.exp(-out[:, 3]))
+                    val += -np.sum(tgt * np.log(s + 1e-12) + (1 - tgt) * np.log(1 - s + 1e-12)) / n
+                return val
+            pp = p.copy(); pp[i] += h
+            pm = p.copy(); pm[i] -= h
+            fd = (L(pp) - L(pm)) / (2 * h)
+            assert abs(fd - grad[i]) <= 1e-6 * max(1.0, abs(fd)), (phase, i, fd, grad[i])
+
+
+def test_labels_from_decided_samples():
+    s_ray = np.array([0, 0, 0, 2, 2])
+    s_t = np.array([0.1, 0.2, 0.3, 1.0, 1.5], F32)
+    s_T = np.array([0.9, 0.4, 0.1, 0.8, 0.7], F32)
+    lab, valid = P.labels_from_march(3, s_ray, s_t, s_T)
+    assert valid.tolist() == [True, False, True]
+    assert np.allclose(lab[0], [0.1, 0.3, 0.2, 1]) and np.allclose(lab[2], [1.0, 1.5, 1.5, 1])
+    assert np.all(lab[1] == 0)
