@@ -37,6 +37,8 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="approximate CPU time for the oracle baseline (0 skips it)")
     p.add_argument("--views", type=int, default=8)
+    p.add_argument("--copy-probe-mb", type=int, default=0,
+                   help="run one device copy of this many MiB first (hardware-counter calibration)")
     return p.parse_args()
 
 
@@ -45,18 +47,18 @@ def cpu_baseline(sc, dist, o, d, dtype, seconds):
     from oracle.render import inputs_from_scene, render
     inp = inputs_from_scene(sc, dist, dtype)
     n_total = len(o)
-    n = 256
-    t0 = time.perf_counter()
-    stride = max(1, n_total // n)
-    render(inp, o[::stride][:n], d[::stride][:n])
-    dt = time.perf_counter() - t0
-    # scale the sample to the requested budget
-    n2 = int(min(max(n * seconds / max(dt, 1e-3), n), 200_000))
-    stride = max(1, n_total // n2)
-    so, sd = o[::stride][:n2], d[::stride][:n2]
-    t0 = time.perf_counter()
-    res = render(inp, so, sd)
-    dt = time.perf_counter() - t0
+    # grow a deterministic strided sample until one oracle run takes about
+    # half the budget or more (its cost is not linear in the ray count)
+    n2 = 2048
+    while True:
+        stride = max(1, n_total // n2)
+        so, sd = o[::stride][:n2], d[::stride][:n2]
+        t0 = time.perf_counter()
+        res = render(inp, so, sd)
+        dt = time.perf_counter() - t0
+        if dt >= 0.5 * seconds or n2 >= 400_000:
+            break
+        n2 = int(n2 * min(8.0, max(2.0, seconds / max(dt, 1e-3))))
     rays_per_s = len(so) / dt
     return {
         "value": rays_per_s / (1920 * 1080),
@@ -88,6 +90,14 @@ def main():
     print(f"# scene + rays generated in {time.time() - t0:.1f} s ({len(o)} rays)", file=sys.stderr,
           flush=True)
     torch.cuda.set_device(0)
+    if args.copy_probe_mb > 0:
+        nbytes = args.copy_probe_mb << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# copy probe: {nbytes} bytes read + {nbytes} bytes written", file=sys.stderr, flush=True)
+        del src, dst
     r = Renderer.from_config(cfg, dtype)
     r.load_scene(torch.from_numpy(sc.tables).cuda(), torch.from_numpy(sc.occ).cuda(),
                  torch.from_numpy(sc.mlp).cuda())

@@ -95,6 +95,9 @@ typedef struct ngprt_outputs {
   float* depth;      /* [n]    sum_i w_i t_i */
   int32_t* n_samples;/* [n]    evaluated (occupied) samples */
   int32_t* n_reads;  /* [n]    occupancy/distance grid reads (marching points) */
+  float* t_first;    /* [n]    t of the first evaluated sample (0 if none) */
+  float* t_last;     /* [n]    t of the last evaluated sample (0 if none) */
+  float* t_half;     /* [n]    t of the sample after which T < 0.5 (t_last if never) */
 } ngprt_outputs;
 
 /* Create a context on the current HIP device.  Validates the descriptor
@@ -143,6 +146,18 @@ int ngprt_load_mlp(ngprt_ctx* ctx, const float* dev_params, void* stream);
  * n_rays = 0 is a no-op. */
 int ngprt_render(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins,
                  const float* dev_dirs, const ngprt_outputs* out, void* stream);
+
+/* Render with a per-ray sample-interval proposal (an extension; see
+ * ngprt_proposal_infer).  dev_proposal: float32 [n][4] = t_near, t_far,
+ * t_term, confidence.  Rays with confidence >= conf_threshold march only the
+ * lattice points with t in [t_near - margin, t_far + margin]; when that
+ * yields no sample (the interval misses the occupied space) the ray falls
+ * back to the plain march.  Other rays march plainly.  dev_fallback: int32
+ * [n] (NULL-able), 1 where the fallback ran.  A correct interval gives the
+ * plain render's samples bit for bit. */
+int ngprt_render_proposal(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins,
+                          const float* dev_dirs, const float* dev_proposal, float conf_threshold,
+                          float margin, const ngprt_outputs* out, int32_t* dev_fallback, void* stream);
 
 /* Parity helpers.  Evaluate the lookup + attention chain at n positions in
  * the grid's domain (box: world coordinates; contract: contracted

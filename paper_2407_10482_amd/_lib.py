@@ -37,7 +37,8 @@ class NgprtDesc(ctypes.Structure):
 
 class NgprtOutputs(ctypes.Structure):
     _fields_ = [(name, ctypes.c_void_p) for name in
-                ("rgb", "c_d", "feat", "t_final", "depth", "n_samples", "n_reads")]
+                ("rgb", "c_d", "feat", "t_final", "depth", "n_samples", "n_reads", "t_first",
+                 "t_last", "t_half")]
 
 
 # (name, restype, argtypes)
@@ -56,6 +57,8 @@ SIGNATURES = [
     ("ngprt_render", ctypes.c_int, [_P, _I64, _P, _P, ctypes.POINTER(NgprtOutputs), _P]),
     ("ngprt_debug_eval_points", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P]),
     ("ngprt_debug_march", ctypes.c_int, [_P, _I64, _P, _P, _I32, _P, _P, _P, _I32, _P]),
+    ("ngprt_render_proposal", ctypes.c_int, [_P, _I64, _P, _P, _P, ctypes.c_float, ctypes.c_float,
+                                             ctypes.POINTER(NgprtOutputs), _P, _P]),
     ("ngprt_render_backward", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P]),
     ("ngprt_adam_step", ctypes.c_int, [_I64, _P, _P, _P, _P, _I32, ctypes.c_float, ctypes.c_float,
                                        ctypes.c_float, ctypes.c_float, _P]),

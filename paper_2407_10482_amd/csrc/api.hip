@@ -209,8 +209,29 @@ int ngprt_render(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins, const
   int rc = check_ready(ctx);
   if (rc) return rc;
   if (!ctx->mlp_loaded) return fail(ctx, NGPRT_E_NOT_LOADED, "mlp not loaded");
-  RayOut o{out->rgb, out->c_d, out->feat, out->t_final, out->depth, out->n_samples, out->n_reads};
-  return launch_render(ctx, n_rays, dev_origins, dev_dirs, o, (hipStream_t)stream);
+  RayOut o{out->rgb,       out->c_d,     out->feat,   out->t_final, out->depth,
+           out->n_samples, out->n_reads, out->t_first, out->t_last,  out->t_half};
+  return launch_render(ctx, n_rays, dev_origins, dev_dirs, o, nullptr, 0.0f, 0.0f, nullptr,
+                       (hipStream_t)stream);
+}
+
+int ngprt_render_proposal(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins, const float* dev_dirs,
+                          const float* dev_proposal, float conf_threshold, float margin,
+                          const ngprt_outputs* out, int32_t* dev_fallback, void* stream) {
+  if (!ctx) return NGPRT_E_INVALID_ARG;
+  if (n_rays < 0) return fail(ctx, NGPRT_E_INVALID_ARG, "n_rays < 0");
+  if (n_rays == 0) return NGPRT_OK;
+  if (!out || !out->rgb) return fail(ctx, NGPRT_E_INVALID_ARG, "out->rgb is required");
+  if (!dev_origins || !dev_dirs || !dev_proposal)
+    return fail(ctx, NGPRT_E_INVALID_ARG, "ray or proposal pointers are NULL");
+  if (!std::isfinite(margin) || margin < 0.0f) return fail(ctx, NGPRT_E_INVALID_ARG, "bad margin");
+  int rc = check_ready(ctx);
+  if (rc) return rc;
+  if (!ctx->mlp_loaded) return fail(ctx, NGPRT_E_NOT_LOADED, "mlp not loaded");
+  RayOut o{out->rgb,       out->c_d,     out->feat,   out->t_final, out->depth,
+           out->n_samples, out->n_reads, out->t_first, out->t_last,  out->t_half};
+  return launch_render(ctx, n_rays, dev_origins, dev_dirs, o, dev_proposal, conf_threshold, margin,
+                       dev_fallback, (hipStream_t)stream);
 }
 
 int ngprt_debug_eval_points(ngprt_ctx* ctx, int64_t n, const float* dev_pos, int32_t* dev_idx,

@@ -47,6 +47,9 @@ struct RayOut {
   float* depth;
   int32_t* n_samples;
   int32_t* n_reads;
+  float* t_first;
+  float* t_last;
+  float* t_half;
 };
 
 }  // namespace ngprt
@@ -80,7 +83,7 @@ int launch_export_distance(ngprt_ctx* ctx, uint8_t* out, hipStream_t s);
 int launch_load_tables(ngprt_ctx* ctx, const float* tables, hipStream_t s);
 int launch_export_tables(ngprt_ctx* ctx, void* codes, float* scales, hipStream_t s);
 int launch_render(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const RayOut& out,
-                  hipStream_t s);
+                  const float* prop, float conf_thr, float margin, int32_t* fallback, hipStream_t s);
 int launch_eval_points(ngprt_ctx* ctx, int64_t n, const float* pos, int32_t* idx, float* fused,
                        float* weights, hipStream_t s);
 int launch_march(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, int32_t cap,

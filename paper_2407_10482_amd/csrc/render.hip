@@ -21,6 +21,16 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 enum { MODE_RENDER = 0, MODE_MARCH = 1 };
 
+// Optional per-ray sample-interval proposal: rays whose confidence reaches
+// conf_thr march only [t_near - margin, t_far + margin] of the same lattice
+// and fall back to the plain march when that interval yields no sample.
+struct ProposalArgs {
+  const float* prop;     // [n][4]: t_near, t_far, t_term, confidence (NULL: plain march)
+  float conf_thr;
+  float margin;
+  int32_t* fallback;     // [n] 1 where the plain march ran after a proposal (NULL-able)
+};
+
 struct MarchRecord {
   int32_t* sample_k;
   int32_t* n_samples;
@@ -91,7 +101,7 @@ template <int DOM, int DT, int LMAX, int MODE>
 __global__ void __launch_bounds__(256) render_kernel(SceneArgs S, int64_t n, const float* __restrict__ O,
                                                      const float* __restrict__ D, RayOut out,
                                                      MarchRecord rec, const float* __restrict__ mlp,
-                                                     int naive) {
+                                                     int naive, ProposalArgs pa) {
   __shared__ float xin_all[4][8 * 64];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -100,14 +110,32 @@ __global__ void __launch_bounds__(256) render_kernel(SceneArgs S, int64_t n, con
   const bool in_range = ray < n;
 
   MarchState m;
-  march_init<DOM>(S, O + 3 * (in_range ? ray : 0), D + 3 * (in_range ? ray : 0), in_range, m);
+  const float* oray = O + 3 * (in_range ? ray : 0);
+  const float* dray = D + 3 * (in_range ? ray : 0);
+  march_init<DOM>(S, oray, dray, in_range, m);
+  bool proposed = false, fell_back = false;
+  if (pa.prop && in_range && !m.done) {
+    const float* q = pa.prop + 4 * ray;
+    if (q[3] >= pa.conf_thr) {
+      march_set_interval<DOM>(S, m, q[0] - pa.margin, q[1] + pa.margin);
+      proposed = true;
+    }
+  }
   float T = 1.0f, cd[3] = {0.f, 0.f, 0.f}, fv[4] = {0.f, 0.f, 0.f, 0.f}, depth = 0.0f;
+  float t_first = 0.0f, t_last = 0.0f, t_half = 0.0f;
+  bool half_set = false;
   int ns = 0, reads = 0;
 
   for (;;) {
     float u[3], ts;
     int ks;
     bool have = march_next<DOM>(S, m, naive != 0, reads, u, ts, ks);
+    if (!have && proposed && !fell_back && ns == 0) {
+      // the proposed interval held no occupied lattice point: plain march
+      march_init<DOM>(S, oray, dray, in_range, m);
+      fell_back = true;
+      have = march_next<DOM>(S, m, naive != 0, reads, u, ts, ks);
+    }
     if (__ballot(have) == 0) break;
     if (have) {
       float f[8];
@@ -123,10 +151,14 @@ __global__ void __launch_bounds__(256) render_kernel(SceneArgs S, int64_t n, con
       depth = __builtin_fmaf(w, ts, depth);
       if (MODE == MODE_MARCH && ns < rec.cap) rec.sample_k[ray * rec.cap + ns] = ks;
       T = T * e;
+      if (ns == 0) t_first = ts;
+      t_last = ts;
+      if (!half_set && T < 0.5f) { t_half = ts; half_set = true; }
       ++ns;
       if (T < S.thr || ns >= S.max_samples) m.done = true;
     }
   }
+  if (!half_set) t_half = t_last;
 
   if (MODE == MODE_MARCH) {
     if (in_range) {
@@ -143,6 +175,10 @@ __global__ void __launch_bounds__(256) render_kernel(SceneArgs S, int64_t n, con
     if (out.depth) out.depth[ray] = depth;
     if (out.n_samples) out.n_samples[ray] = ns;
     if (out.n_reads) out.n_reads[ray] = reads;
+    if (out.t_first) out.t_first[ray] = t_first;
+    if (out.t_last) out.t_last[ray] = t_last;
+    if (out.t_half) out.t_half[ray] = t_half;
+    if (pa.fallback) pa.fallback[ray] = fell_back ? 1 : 0;
   }
   float* xin = xin_all[wave];
   xin[0 * 64 + lane] = cd[0];
@@ -184,22 +220,22 @@ __global__ void __launch_bounds__(256) eval_points_kernel(SceneArgs S, int64_t n
 template <int MODE, int DOM, int DT>
 static void dispatch_l(const SceneArgs& S, dim3 g, hipStream_t st, int64_t n, const float* o,
                        const float* d, const RayOut& out, const MarchRecord& rec,
-                       const float* mlp, int naive) {
+                       const float* mlp, int naive, const ProposalArgs& pa) {
   if (S.L <= 8)
     hipLaunchKernelGGL((render_kernel<DOM, DT, 8, MODE>), g, dim3(256), 0, st, S, n, o, d, out, rec,
-                       mlp, naive);
+                       mlp, naive, pa);
   else
     hipLaunchKernelGGL((render_kernel<DOM, DT, 16, MODE>), g, dim3(256), 0, st, S, n, o, d, out, rec,
-                       mlp, naive);
+                       mlp, naive, pa);
 }
 
 template <int MODE>
 static void dispatch(const SceneArgs& S, int dom, int dt, dim3 g, hipStream_t st, int64_t n,
                      const float* o, const float* d, const RayOut& out, const MarchRecord& rec,
-                     const float* mlp, int naive) {
+                     const float* mlp, int naive, const ProposalArgs& pa) {
 #define NGPRT_CASE(DOMV, DTV)                                                       \
   if (dom == DOMV && dt == DTV) {                                                   \
-    dispatch_l<MODE, DOMV, DTV>(S, g, st, n, o, d, out, rec, mlp, naive);           \
+    dispatch_l<MODE, DOMV, DTV>(S, g, st, n, o, d, out, rec, mlp, naive, pa);       \
     return;                                                                         \
   }
   NGPRT_CASE(DOM_BOX, DT_F32)
@@ -212,13 +248,14 @@ static void dispatch(const SceneArgs& S, int dom, int dt, dim3 g, hipStream_t st
 }
 
 int launch_render(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const RayOut& out,
-                  hipStream_t st) {
+                  const float* prop, float conf_thr, float margin, int32_t* fallback, hipStream_t st) {
   SceneArgs S = scene_args(ctx);
   const int64_t blocks = (n + 255) / 256;
   if (blocks > 0x7FFFFFFF) return fail(ctx, NGPRT_E_SHAPE, "too many rays for one launch");
   MarchRecord rec{nullptr, nullptr, nullptr, 0};
+  ProposalArgs pa{prop, conf_thr, margin, fallback};
   dispatch<MODE_RENDER>(S, ctx->desc.domain, ctx->desc.table_dtype, dim3(unsigned(blocks)), st, n, o,
-                        d, out, rec, ctx->mlp, 0);
+                        d, out, rec, ctx->mlp, 0, pa);
   return check_launch(ctx, "render_kernel");
 }
 
@@ -229,8 +266,9 @@ int launch_march(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, int3
   if (blocks > 0x7FFFFFFF) return fail(ctx, NGPRT_E_SHAPE, "too many rays for one launch");
   MarchRecord rec{sk, ns, nr, cap};
   RayOut out{};
+  ProposalArgs pa{nullptr, 0.0f, 0.0f, nullptr};
   dispatch<MODE_MARCH>(S, ctx->desc.domain, ctx->desc.table_dtype, dim3(unsigned(blocks)), st, n, o,
-                       d, out, rec, ctx->mlp, naive);
+                       d, out, rec, ctx->mlp, naive, pa);
   return check_launch(ctx, "march_kernel");
 }
 

@@ -105,20 +105,52 @@ class Renderer:
         _dev(origins, torch.float32, (n, 3), "origins")
         _dev(dirs, torch.float32, (n, 3), "dirs")
         if out is None:
-            out = {"rgb": torch.empty((n, 3), dtype=torch.float32, device="cuda")}
-            if aux:
-                out.update(
-                    c_d=torch.empty((n, 3), dtype=torch.float32, device="cuda"),
-                    feat=torch.empty((n, 4), dtype=torch.float32, device="cuda"),
-                    t_final=torch.empty((n,), dtype=torch.float32, device="cuda"),
-                    depth=torch.empty((n,), dtype=torch.float32, device="cuda"),
-                    n_samples=torch.empty((n,), dtype=torch.int32, device="cuda"),
-                    n_reads=torch.empty((n,), dtype=torch.int32, device="cuda"))
-        o = NgprtOutputs()
-        for k in ("rgb", "c_d", "feat", "t_final", "depth", "n_samples", "n_reads"):
-            setattr(o, k, out[k].data_ptr() if k in out else None)
+            out = self.alloc_outputs(n) if aux else {"rgb": torch.empty((n, 3), dtype=torch.float32,
+                                                                        device="cuda")}
+        o = self._outputs(out)
         check(self.lib.ngprt_render(self.ctx, n, _ptr(origins), _ptr(dirs), ctypes.byref(o),
                                     _stream()), self.ctx)
+        return out
+
+    OUTPUT_FIELDS = ("rgb", "c_d", "feat", "t_final", "depth", "n_samples", "n_reads", "t_first",
+                     "t_last", "t_half")
+
+    @staticmethod
+    def _outputs(out: Dict[str, torch.Tensor]) -> NgprtOutputs:
+        o = NgprtOutputs()
+        for k in Renderer.OUTPUT_FIELDS:
+            setattr(o, k, out[k].data_ptr() if k in out else None)
+        return o
+
+    def alloc_outputs(self, n: int, labels: bool = False) -> Dict[str, torch.Tensor]:
+        f = dict(device="cuda", dtype=torch.float32)
+        out = dict(rgb=torch.empty((n, 3), **f), c_d=torch.empty((n, 3), **f),
+                   feat=torch.empty((n, 4), **f), t_final=torch.empty((n,), **f),
+                   depth=torch.empty((n,), **f),
+                   n_samples=torch.empty((n,), dtype=torch.int32, device="cuda"),
+                   n_reads=torch.empty((n,), dtype=torch.int32, device="cuda"))
+        if labels:
+            out.update(t_first=torch.empty((n,), **f), t_last=torch.empty((n,), **f),
+                       t_half=torch.empty((n,), **f))
+        return out
+
+    def render_proposal(self, origins: torch.Tensor, dirs: torch.Tensor, proposal: torch.Tensor,
+                        conf_threshold: float = 0.9, margin: float = 0.0, aux: bool = True,
+                        out: Optional[Dict[str, torch.Tensor]] = None):
+        n = origins.shape[0]
+        _dev(origins, torch.float32, (n, 3), "origins")
+        _dev(dirs, torch.float32, (n, 3), "dirs")
+        _dev(proposal, torch.float32, (n, 4), "proposal")
+        if out is None:
+            out = self.alloc_outputs(n) if aux else {"rgb": torch.empty((n, 3), dtype=torch.float32,
+                                                                        device="cuda")}
+        fb = out.get("fallback")
+        if fb is None and aux:
+            fb = out["fallback"] = torch.empty((n,), dtype=torch.int32, device="cuda")
+        o = self._outputs(out)
+        check(self.lib.ngprt_render_proposal(self.ctx, n, _ptr(origins), _ptr(dirs), _ptr(proposal),
+                                             float(conf_threshold), float(margin), ctypes.byref(o),
+                                             _ptr(fb), _stream()), self.ctx)
         return out
 
     # ---------------------------------------------------------------- debug
