@@ -194,6 +194,33 @@ int ngprt_render_backward(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origi
 int ngprt_adam_step(int64_t n, float* dev_param, const float* dev_grad, float* dev_m, float* dev_v,
                     int32_t step, float lr, float beta1, float beta2, float eps, void* stream);
 
+/* Learned per-ray sample-interval proposal (an extension; the paper names
+ * adaptive sampling only as orthogonal related work, Sec. 2).  Network:
+ * [o; d] -> Fourier features sin/cos(2^k pi r_j), k = 0..3 (48) -> 64 -> 64
+ * -> 4 with ReLU; outputs t_near, t_far, t_term, confidence.  dev_params:
+ * float32 master weights [7556] = W1[64][48], b1[64], W2[64][64], b2[64],
+ * W3[4][64], b3[4], caller-owned.  Products run on bfloat16 operands with
+ * float32 accumulation.  ctx provides workspace only (no scene needed). */
+
+/* dev_out: float32 [n][4] = t_near, t_far, t_term, sigmoid(confidence logit). */
+int ngprt_proposal_infer(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins,
+                         const float* dev_dirs, const float* dev_params, float* dev_out,
+                         void* stream);
+
+/* One training step on a batch of n_rays >= 1 rays.  dev_labels: float32
+ * [n][4] = t_near, t_far, t_term, valid (1 for rays with samples, else 0).
+ * Loss = (sum over valid rays of the squared error of the three depths
+ * + for phase 2 the cross-entropy of the confidence against "the predicted
+ * interval widened by margin contains [t_near, t_far]") / n.  Adds the batch
+ * loss to dev_loss[0] (NULL-able); writes the gradient to dev_grad [7556]
+ * (NULL-able); when dev_m and dev_v (Adam moments [7556], zero before step
+ * 1) are given, applies Adam (beta1 0.9, beta2 0.99, eps 1e-8, step >= 1) to
+ * dev_params in place.  Gradients are reduced in a fixed order. */
+int ngprt_proposal_train_step(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins,
+                              const float* dev_dirs, const float* dev_labels, int32_t phase,
+                              float margin, float* dev_params, float* dev_m, float* dev_v,
+                              int32_t step, float lr, float* dev_loss, float* dev_grad, void* stream);
+
 /* Human-readable name of a status code (static storage). */
 const char* ngprt_status_string(int status);
 

@@ -216,8 +216,13 @@ class RenderResult:
 
 
 def march(inp: OracleInputs, o: np.ndarray, d: np.ndarray, naive: bool = False,
-          terminate: bool = True):
+          terminate: bool = True, intervals=None):
     """March all rays in lock-step over the lattice index k.
+
+    intervals: optional float32 [n, 2] (t_lo, t_hi) restricting a ray to the
+    lattice points with t in [t_lo, t_hi] (NaN rows: no restriction).  Box
+    scenes start at lattice index max(0, floor((t_lo - t0) / step)); in the
+    contracted domain points with t < t_lo are visited without a read.
 
     Returns per-ray sample lists and counts; transmittance decisions in the
     float32 mirror."""
@@ -247,17 +252,34 @@ def march(inp: OracleInputs, o: np.ndarray, d: np.ndarray, naive: bool = False,
         ball_c = np.zeros((n, 3), dtype=F32)
         ball_r2 = np.zeros(n, dtype=F32)
         margin = vox * F32(1.0 / 1024.0)
+    t_lo = np.full(n, -np.inf, dtype=F32)
+    t_hi = np.full(n, np.inf, dtype=F32)
+    if intervals is not None:
+        iv = np.asarray(intervals, dtype=F32)
+        use = ~np.isnan(iv[:, 0])
+        t_lo[use] = iv[use, 0]
+        t_hi[use] = iv[use, 1]
+        if inp.domain == BOX:
+            with np.errstate(invalid="ignore"):
+                kf = np.floor((t_lo - t0) / step)
+            kstart = np.where(kf > 0, np.where(kf < F32(MAX_LATTICE), kf, F32(MAX_LATTICE)), 0)
+            next_read = np.where(use, kstart, 0).astype(np.int64)
     rec_ray, rec_k, rec_t, rec_pos, rec_T = [], [], [], [], []
     k = 0
     while alive.any() and k < MAX_LATTICE:
         ids = np.nonzero(alive)[0]
         if inp.domain == BOX:
             tk = t0[ids] + F32(k) * step
-            inside = tk < t1[ids]
+            inside = (tk < t1[ids]) & ~(tk > t_hi[ids])
             alive[ids[~inside]] = False
             ids, tk = ids[inside], tk[inside]
             pos = o[ids] + tk[:, None] * d[ids]
-            need = np.ones(len(ids), dtype=bool) if naive else (k >= next_read[ids])
+            if naive:
+                need = np.ones(len(ids), dtype=bool)
+                if intervals is not None:
+                    need = k >= next_read[ids]
+            else:
+                need = k >= next_read[ids]
         else:
             tk = t[ids]
             x = o[ids] + tk[:, None] * d[ids]
@@ -276,6 +298,7 @@ def march(inp: OracleInputs, o: np.ndarray, d: np.ndarray, naive: bool = False,
             pos[outer] = s[outer, None] * x[outer]
             jn[outer] = jn_o[outer]
             gone = (outer & (inv_r < step) & (xd >= F32(0.0))) | ~np.isfinite(r2)
+            gone |= tk > t_hi[ids]
             alive[ids[gone]] = False
             keep = ~gone
             ids, tk, pos, jn = ids[keep], tk[keep], pos[keep], jn[keep]
@@ -285,6 +308,7 @@ def march(inp: OracleInputs, o: np.ndarray, d: np.ndarray, naive: bool = False,
                 dv = pos - ball_c[ids]
                 dd = (dv[:, 0] * dv[:, 0] + dv[:, 1] * dv[:, 1]) + dv[:, 2] * dv[:, 2]
                 need = ~(has_ball[ids] & (dd < ball_r2[ids]))
+            need &= ~(tk < t_lo[ids])
         # occupancy / distance read
         u = grid_coords32(inp, pos)
         q = np.clip(np.floor(u * RF), 0, R - 1).astype(np.int64)
@@ -407,3 +431,55 @@ def inputs_from_scene(scene, dist: np.ndarray, dtype: int = DT_F32) -> OracleInp
                         resolutions=list(cfg.resolutions), domain=cfg.domain,
                         roi_half=cfg.roi_half, step=cfg.step, max_samples=cfg.max_samples,
                         t_threshold=cfg.t_threshold, dtype=dtype, mlp_dims=cfg.mlp_dims)
+
+
+def valid_rays(inp: OracleInputs, o, d):
+    """Rays the march accepts: finite, nonzero direction, and (box) hitting the ROI."""
+    o = np.asarray(o, F32)
+    d = np.asarray(d, F32)
+    dn2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+    if inp.domain == BOX:
+        return ray_box32(o, d, inp.roi_half)[2] & (dn2 > 0)
+    return np.isfinite(o).all(axis=1) & np.isfinite(d).all(axis=1) & (dn2 > 0)
+
+
+def render_proposal(inp: OracleInputs, o, d, proposal, conf_threshold=0.9, margin=0.0):
+    """Render with a per-ray interval proposal [t_near, t_far, t_term, conf]:
+    confident rays march [t_near - margin, t_far + margin]; a confident ray
+    whose interval yields no sample is marched again plainly.  Returns the
+    result and the fallback mask."""
+    o = np.asarray(o, F32)
+    d = np.asarray(d, F32)
+    n = len(o)
+    prop = np.asarray(proposal, F32)
+    conf = prop[:, 3] >= F32(conf_threshold)
+    iv = np.full((n, 2), np.nan, F32)
+    iv[conf, 0] = prop[conf, 0] - F32(margin)
+    iv[conf, 1] = prop[conf, 1] + F32(margin)
+    m = march(inp, o, d, intervals=iv)
+    fb = conf & valid_rays(inp, o, d) & (m["n_samples"] == 0)
+    if fb.any():
+        idx = np.nonzero(fb)[0]
+        m2 = march(inp, o[idx], d[idx])
+        # merge: fallback rays take the plain march's samples, reads add up
+        keep = ~np.isin(m["s_ray"], idx)
+        for key in ("s_ray", "s_k", "s_t", "s_pos", "s_T"):
+            extra = m2[key] if key != "s_ray" else idx[m2["s_ray"]]
+            m[key] = np.concatenate([m[key][keep], extra])
+        order = np.lexsort((m["s_k"], m["s_ray"]))
+        for key in ("s_ray", "s_k", "s_t", "s_pos", "s_T"):
+            m[key] = m[key][order]
+        m["n_samples"][idx] = m2["n_samples"]
+        m["n_reads"][idx] += m2["n_reads"]
+        m["t_final32"][idx] = m2["t_final32"]
+    if len(m["s_ray"]):
+        fz, _ = fused64(inp, grid_coords32(inp, m["s_pos"]).astype(np.float64))
+    else:
+        fz = np.zeros((0, 8))
+    c_d, feat, depth, T = composite64(inp, n, m["s_ray"], m["s_t"], fz)
+    rgb = 1.0 / (1.0 + np.exp(-(c_d + mlp64(inp.mlp, np.concatenate([c_d, feat], axis=1),
+                                              inp.mlp_dims))))
+    res = RenderResult(n_samples=m["n_samples"], n_reads=m["n_reads"], t_final32=m["t_final32"],
+                       t_final=T, c_d=c_d, feat=feat, depth=depth, rgb=rgb, s_ray=m["s_ray"],
+                       s_k=m["s_k"], s_t=m["s_t"], s_pos=m["s_pos"], extra={"s_T": m["s_T"]})
+    return res, fb

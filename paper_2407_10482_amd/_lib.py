@@ -62,6 +62,9 @@ SIGNATURES = [
     ("ngprt_render_backward", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P]),
     ("ngprt_adam_step", ctypes.c_int, [_I64, _P, _P, _P, _P, _I32, ctypes.c_float, ctypes.c_float,
                                        ctypes.c_float, ctypes.c_float, _P]),
+    ("ngprt_proposal_infer", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P]),
+    ("ngprt_proposal_train_step", ctypes.c_int, [_P, _I64, _P, _P, _P, _I32, ctypes.c_float, _P, _P, _P,
+                                                 _I32, ctypes.c_float, _P, _P, _P]),
     ("ngprt_status_string", ctypes.c_char_p, [ctypes.c_int]),
     ("ngprt_last_error", ctypes.c_char_p, [_P]),
 ]

@@ -114,6 +114,8 @@ void ngprt_destroy(ngprt_ctx* ctx) {
   if (ctx->grid) (void)hipFree(ctx->grid);
   if (ctx->mlp) (void)hipFree(ctx->mlp);
   if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->prop_wb) (void)hipFree(ctx->prop_wb);
+  if (ctx->prop_grad) (void)hipFree(ctx->prop_grad);
   if (switched) (void)hipSetDevice(cur);
   delete ctx;
 }
@@ -285,6 +287,32 @@ int ngprt_adam_step(int64_t n, float* dev_param, const float* dev_grad, float* d
     return NGPRT_E_INVALID_ARG;
   return launch_adam(n, dev_param, dev_grad, dev_m, dev_v, step, lr, beta1, beta2, eps,
                      (hipStream_t)stream);
+}
+
+int ngprt_proposal_infer(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins, const float* dev_dirs,
+                         const float* dev_params, float* dev_out, void* stream) {
+  if (!ctx) return NGPRT_E_INVALID_ARG;
+  if (n_rays < 0) return fail(ctx, NGPRT_E_INVALID_ARG, "n_rays < 0");
+  if (n_rays == 0) return NGPRT_OK;
+  if (!dev_origins || !dev_dirs || !dev_params || !dev_out)
+    return fail(ctx, NGPRT_E_INVALID_ARG, "NULL pointer");
+  return launch_prop_infer(ctx, n_rays, dev_origins, dev_dirs, dev_params, dev_out, (hipStream_t)stream);
+}
+
+int ngprt_proposal_train_step(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins,
+                              const float* dev_dirs, const float* dev_labels, int32_t phase, float margin,
+                              float* dev_params, float* dev_m, float* dev_v, int32_t step, float lr,
+                              float* dev_loss, float* dev_grad, void* stream) {
+  if (!ctx) return NGPRT_E_INVALID_ARG;
+  if (n_rays < 1) return fail(ctx, NGPRT_E_INVALID_ARG, "empty batch");
+  if (!dev_origins || !dev_dirs || !dev_labels || !dev_params)
+    return fail(ctx, NGPRT_E_INVALID_ARG, "NULL pointer");
+  if (phase != 1 && phase != 2) return fail(ctx, NGPRT_E_INVALID_ARG, "phase must be 1 or 2");
+  if ((dev_m == nullptr) != (dev_v == nullptr)) return fail(ctx, NGPRT_E_INVALID_ARG, "m and v go together");
+  if (dev_m && step < 1) return fail(ctx, NGPRT_E_INVALID_ARG, "step must be >= 1");
+  if (!std::isfinite(lr) || !std::isfinite(margin)) return fail(ctx, NGPRT_E_INVALID_ARG, "bad lr/margin");
+  return launch_prop_train(ctx, n_rays, dev_origins, dev_dirs, dev_labels, phase, margin, dev_params, dev_m,
+                           dev_v, step, lr, dev_loss, dev_grad, (hipStream_t)stream);
 }
 
 }  // extern "C"

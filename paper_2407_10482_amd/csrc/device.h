@@ -40,6 +40,16 @@ __device__ __forceinline__ float exp32(float x) {
   return p * __int_as_float((n + 127) << 23);
 }
 
+// float32 -> bfloat16 bits, round to nearest even (NaN -> 0x7FC0).
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+  uint32_t b = __float_as_uint(x);
+  if (x != x) return 0x7FC0;
+  uint32_t lsb = (b >> 16) & 1u;
+  return uint16_t((b + 0x7FFFu + lsb) >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+
 // Spatial hash of a corner (multi-resolution hash encoding): products modulo
 // 2^32, xor, then the low log2(T) bits.
 __device__ __forceinline__ uint32_t hash3(uint32_t x, uint32_t y, uint32_t z, uint32_t mask) {

@@ -64,8 +64,10 @@ struct ngprt_ctx {
   float scales_host[NGPRT_MAX_LEVELS][9];
   uint16_t* grid = nullptr;   // [R^3]
   float* mlp = nullptr;       // [451]
-  void* ws = nullptr;         // backward workspace (per-wave MLP gradient partials)
+  void* ws = nullptr;         // workspace (per-wave gradient partials of backward / proposal)
   size_t ws_bytes = 0;
+  void* prop_wb = nullptr;    // proposal weights in bfloat16 [7556]
+  void* prop_grad = nullptr;  // proposal gradient [7556] when the caller wants none
   bool tables_loaded = false;
   bool occ_loaded = false;
   bool mlp_loaded = false;
@@ -92,4 +94,9 @@ int launch_backward(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, c
                     float* gtab, float* gmlp, hipStream_t s);
 int launch_adam(int64_t n, float* p, const float* g, float* m, float* v, int32_t step, float lr,
                 float b1, float b2, float eps, hipStream_t s);
+int launch_prop_infer(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const float* P,
+                      float* out, hipStream_t s);
+int launch_prop_train(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const float* labels,
+                      int phase, float margin, float* P, float* m, float* v, int32_t step, float lr,
+                      float* loss, float* grad_out, hipStream_t s);
 }  // namespace ngprt

@@ -11,16 +11,10 @@
 
 #include <cstring>
 
+#include "device.h"
 #include "internal.h"
 
 namespace ngprt {
-
-__device__ __forceinline__ uint16_t bf16_rne(float x) {
-  uint32_t b = __float_as_uint(x);
-  if (x != x) return 0x7FC0;
-  uint32_t lsb = (b >> 16) & 1u;
-  return uint16_t((b + 0x7FFFu + lsb) >> 16);
-}
 
 __device__ __forceinline__ uint8_t fp8_encode(float x) {
   if (x != x) return 0x7F;

@@ -226,3 +226,47 @@ class RenderFunction(torch.autograd.Function):
 
 def render_differentiable(renderer: Renderer, tables, mlp, origins, dirs):
     return RenderFunction.apply(tables, mlp, origins, dirs, renderer)
+
+
+N_PROPOSAL_PARAMS = 7556
+
+
+class Proposal:
+    """Per-ray sample-interval proposal network on the GPU (library kernels).
+
+    Holds float32 master weights and Adam moments as torch tensors; training
+    and inference run in libngprt.so on bfloat16 operands."""
+
+    def __init__(self, params: torch.Tensor, ctx_owner: Renderer):
+        _dev(params, torch.float32, (N_PROPOSAL_PARAMS,), "proposal params")
+        self.params = params
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.step = 0
+        self.owner = ctx_owner          # supplies the library context (workspace)
+
+    def infer(self, origins: torch.Tensor, dirs: torch.Tensor) -> torch.Tensor:
+        n = origins.shape[0]
+        out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+        check(self.owner.lib.ngprt_proposal_infer(self.owner.ctx, n, _ptr(origins), _ptr(dirs),
+                                                  _ptr(self.params), _ptr(out), _stream()), self.owner.ctx)
+        return out
+
+    def grad(self, origins, dirs, labels, phase: int = 1, margin: float = 0.0):
+        """Gradient and loss of one batch, no update."""
+        g = torch.empty_like(self.params)
+        loss = torch.zeros((1,), dtype=torch.float32, device="cuda")
+        check(self.owner.lib.ngprt_proposal_train_step(
+            self.owner.ctx, origins.shape[0], _ptr(origins), _ptr(dirs), _ptr(labels), int(phase),
+            float(margin), _ptr(self.params), None, None, 0, 0.0, _ptr(loss), _ptr(g), _stream()),
+            self.owner.ctx)
+        return g, loss
+
+    def train_step(self, origins, dirs, labels, lr: float, phase: int = 1, margin: float = 0.0,
+                   loss: Optional[torch.Tensor] = None):
+        _dev(labels, torch.float32, (origins.shape[0], 4), "labels")
+        self.step += 1
+        check(self.owner.lib.ngprt_proposal_train_step(
+            self.owner.ctx, origins.shape[0], _ptr(origins), _ptr(dirs), _ptr(labels), int(phase),
+            float(margin), _ptr(self.params), _ptr(self.m), _ptr(self.v), self.step, float(lr),
+            _ptr(loss), None, _stream()), self.owner.ctx)

@@ -66,3 +66,34 @@ def test_labels_from_decided_samples():
     assert valid.tolist() == [True, False, True]
     assert np.allclose(lab[0], [0.1, 0.3, 0.2, 1]) and np.allclose(lab[2], [1.0, 1.5, 1.5, 1])
     assert np.all(lab[1] == 0)
+
+
+def test_interval_march_with_exact_labels_equals_plain():
+    import synth
+    from oracle.distgrid import distance_grid_edt
+    from oracle.render import inputs_from_scene, render, render_proposal
+    cfg = synth.tiny()
+    sc = synth.make_scene(cfg)
+    inp = inputs_from_scene(sc, distance_grid_edt(sc.occ))
+    o, d, _ = synth.scene_rays(cfg)
+    o, d = o[::9], d[::9]
+    ref = render(inp, o, d)
+    lab, valid = P.labels_from_march(len(o), ref.s_ray, ref.s_t, ref.extra["s_T"])
+    prop = np.concatenate([lab[:, :3], valid[:, None].astype(np.float32)], axis=1)
+    res, fb = render_proposal(inp, o, d, prop, 0.9, 0.0)
+    assert np.array_equal(res.s_k, ref.s_k) and np.array_equal(res.n_samples, ref.n_samples)
+    assert np.array_equal(res.rgb, ref.rgb) and not fb.any()
+    assert (res.n_reads <= ref.n_reads).all()
+    # an interval that misses everything falls back to the plain march
+    bad = prop.copy()
+    bad[:, 0] = 50.0
+    bad[:, 1] = 51.0
+    bad[:, 3] = 1.0
+    res2, fb2 = render_proposal(inp, o, d, bad, 0.9, 0.0)
+    assert fb2[ref.n_samples > 0].all()
+    assert np.array_equal(res2.s_k, ref.s_k) and np.array_equal(res2.rgb, ref.rgb)
+    # a truncated interval loses exactly the samples outside it
+    cut = prop.copy()
+    cut[:, 1] = (lab[:, 0] + lab[:, 1]) / 2
+    res3, _ = render_proposal(inp, o, d, cut, 0.9, 0.0)
+    assert (res3.n_samples <= ref.n_samples).all() and (res3.n_samples < ref.n_samples).any()
