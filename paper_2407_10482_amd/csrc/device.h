@@ -86,25 +86,25 @@ template <> struct Store<DT_BF16> {
   }
 };
 
-// OCP E4M3FN code -> float32 (exact).  Written from the format definition:
-// exponent bias 7, subnormals m * 2^-9.  Codes 0x7F/0xFF (NaN) never occur
-// in tables written by the library's encoder.
-__device__ __forceinline__ float fp8_decode(uint32_t b) {
-  uint32_t e = (b >> 3) & 15u, m = b & 7u;
-  float mag = e ? __uint_as_float(((e + 120u) << 23) | (m << 20)) : float(m) * 0.001953125f;
-  return (b & 0x80u) ? -mag : mag;
+// OCP E4M3FN codes -> float32 (exact) with gfx950's OCP conversion
+// (v_cvt_scalef32_pk_f32_fp8, scale 1): two codes per instruction.
+typedef float fp8pair __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ fp8pair fp8x2_decode(uint32_t w, bool hi) {
+  return hi ? __builtin_amdgcn_cvt_scalef32_pk_f32_fp8((int)w, 1.0f, true)
+            : __builtin_amdgcn_cvt_scalef32_pk_f32_fp8((int)w, 1.0f, false);
 }
 
 template <> struct Store<DT_FP8> {
   __device__ static __forceinline__ float logit(const void* p, size_t i) {
-    return fp8_decode(reinterpret_cast<const uint8_t*>(p)[i]);
+    return fp8x2_decode(reinterpret_cast<const uint8_t*>(p)[i], false)[0];
   }
   __device__ static __forceinline__ void feat(const void* p, size_t i, float v[8]) {
     uint2 w = reinterpret_cast<const uint2*>(p)[i];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) v[j] = fp8_decode((w.x >> (8 * j)) & 0xFFu);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) v[4 + j] = fp8_decode((w.y >> (8 * j)) & 0xFFu);
+    fp8pair a = fp8x2_decode(w.x, false), b = fp8x2_decode(w.x, true);
+    fp8pair c = fp8x2_decode(w.y, false), d = fp8x2_decode(w.y, true);
+    v[0] = a[0]; v[1] = a[1]; v[2] = b[0]; v[3] = b[1];
+    v[4] = c[0]; v[5] = c[1]; v[6] = d[0]; v[7] = d[1];
   }
 };
 
@@ -220,42 +220,49 @@ __device__ __forceinline__ void eval_fused(const SceneArgs& S, const float u[3],
     for (int l = 0; l < LMAX; ++l)
       if (l < S.L) wout[l] = w[l];
   }
-  // pass 2: features of every level, weighted, tree-summed
-  TreeSum<LMAX, 8> fs;
+  // pass 2: features of every level, weighted.  The density channel (on the
+  // decision chain) is tree-summed over levels; the colour and specular
+  // channels decide nothing and accumulate in level order with fma.
+  TreeSum<LMAX, 1> fs0;
+  float facc[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   Unroll<LMAX, LMAX>::run([&](auto I) {
     constexpr int l = I.value;
-    float prod[8];
+    float p0[1] = {0.0f};
     if (l < S.L) {
       Corners c;
       level_corners(u, S.N[l], S.Nf[l], S.mask, c);
       const size_t base = size_t(l) << S.log2T;
-      float v[8][8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) Store<DT>::feat(S.feat, base + c.idx[k], v[k]);
       float acc[8];
-      acc[0] = 0.0f;
 #pragma unroll
-      for (int k = 0; k < 8; ++k) acc[0] = acc[0] + c.w[k] * v[k][0];
+      for (int j = 0; j < 8; ++j) acc[j] = 0.0f;
+      // two groups of four corners keep the gathered rows in flight within
+      // the register budget
 #pragma unroll
-      for (int j = 1; j < 8; ++j) {
-        acc[j] = 0.0f;
+      for (int g = 0; g < 2; ++g) {
+        float v[4][8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) acc[j] = __builtin_fmaf(c.w[k], v[k][j], acc[j]);
+        for (int k = 0; k < 4; ++k) Store<DT>::feat(S.feat, base + c.idx[4 * g + k], v[k]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const float wk = c.w[4 * g + k];
+          acc[0] = acc[0] + wk * v[k][0];
+#pragma unroll
+          for (int j = 1; j < 8; ++j) acc[j] = __builtin_fmaf(wk, v[k][j], acc[j]);
+        }
       }
       if (DT == DT_FP8) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) acc[j] = S.scale[l][j] * acc[j];
       }
+      p0[0] = w[l] * acc[0];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) prod[j] = w[l] * acc[j];
-    } else {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) prod[j] = 0.0f;
+      for (int j = 0; j < 7; ++j) facc[j] = __builtin_fmaf(w[l], acc[1 + j], facc[j]);
     }
-    fs.template push<l>(prod);
+    fs0.template push<l>(p0);
   });
+  fused[0] = fs0.s[0][0];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) fused[j] = fs.s[0][j];
+  for (int j = 0; j < 7; ++j) fused[1 + j] = facc[j];
 }
 
 }  // namespace ngprt

@@ -19,7 +19,10 @@ namespace ngprt {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-enum { MODE_RENDER = 0, MODE_MARCH = 1 };
+// MODE_RENDER: plain render.  MODE_RENDER_EXT: render that also writes the
+// label outputs (t_first / t_last / t_half) and honours a proposal.
+// MODE_MARCH: sample lists for parity checks (no MLP).
+enum { MODE_RENDER = 0, MODE_MARCH = 1, MODE_RENDER_EXT = 2 };
 
 // Optional per-ray sample-interval proposal: rays whose confidence reaches
 // conf_thr march only [t_near - margin, t_far + margin] of the same lattice
@@ -97,15 +100,35 @@ __device__ __forceinline__ void wave_mlp(const float* __restrict__ P, const floa
   }
 }
 
+// Occupancy target of the render kernel (waves per SIMD): the 16-level
+// kernels need ~170 VGPRs unconstrained (2 waves); asking for 3 costs a few
+// spilled registers.  The XCD remap can be disabled for measurements.
+#ifndef NGPRT_RENDER_WAVES_PER_EU
+#define NGPRT_RENDER_WAVES_PER_EU 3
+#endif
+#ifndef NGPRT_XCD_REMAP
+#define NGPRT_XCD_REMAP 1
+#endif
+
 template <int DOM, int DT, int LMAX, int MODE>
-__global__ void __launch_bounds__(256) render_kernel(SceneArgs S, int64_t n, const float* __restrict__ O,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NGPRT_RENDER_WAVES_PER_EU)))
+render_kernel(SceneArgs S, int64_t n, const float* __restrict__ O,
                                                      const float* __restrict__ D, RayOut out,
                                                      MarchRecord rec, const float* __restrict__ mlp,
                                                      int naive, ProposalArgs pa) {
   __shared__ float xin_all[4][8 * 64];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int64_t ray_base = (int64_t(blockIdx.x) * 4 + wave) * 64;
+  // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+  // contiguous range of ray tiles so neighbouring tiles share its L2.
+#if NGPRT_XCD_REMAP
+  const unsigned G = gridDim.x, xcd = blockIdx.x % 8u, slot = blockIdx.x / 8u;
+  const unsigned q8 = G / 8u, r8 = G % 8u;
+  const unsigned block = xcd * q8 + (xcd < r8 ? xcd : r8) + slot;
+#else
+  const unsigned block = blockIdx.x;
+#endif
+  const int64_t ray_base = (int64_t(block) * 4 + wave) * 64;
   const int64_t ray = ray_base + lane;
   const bool in_range = ray < n;
 
@@ -113,8 +136,9 @@ __global__ void __launch_bounds__(256) render_kernel(SceneArgs S, int64_t n, con
   const float* oray = O + 3 * (in_range ? ray : 0);
   const float* dray = D + 3 * (in_range ? ray : 0);
   march_init<DOM>(S, oray, dray, in_range, m);
+  constexpr bool EXT = MODE == MODE_RENDER_EXT;
   bool proposed = false, fell_back = false;
-  if (pa.prop && in_range && !m.done) {
+  if (EXT && pa.prop && in_range && !m.done) {
     const float* q = pa.prop + 4 * ray;
     if (q[3] >= pa.conf_thr) {
       march_set_interval<DOM>(S, m, q[0] - pa.margin, q[1] + pa.margin);
@@ -130,7 +154,7 @@ __global__ void __launch_bounds__(256) render_kernel(SceneArgs S, int64_t n, con
     float u[3], ts;
     int ks;
     bool have = march_next<DOM>(S, m, naive != 0, reads, u, ts, ks);
-    if (!have && proposed && !fell_back && ns == 0) {
+    if (EXT && !have && proposed && !fell_back && ns == 0) {
       // the proposed interval held no occupied lattice point: plain march
       march_init<DOM>(S, oray, dray, in_range, m);
       fell_back = true;
@@ -151,9 +175,11 @@ __global__ void __launch_bounds__(256) render_kernel(SceneArgs S, int64_t n, con
       depth = __builtin_fmaf(w, ts, depth);
       if (MODE == MODE_MARCH && ns < rec.cap) rec.sample_k[ray * rec.cap + ns] = ks;
       T = T * e;
-      if (ns == 0) t_first = ts;
-      t_last = ts;
-      if (!half_set && T < 0.5f) { t_half = ts; half_set = true; }
+      if (EXT) {
+        if (ns == 0) t_first = ts;
+        t_last = ts;
+        if (!half_set && T < 0.5f) { t_half = ts; half_set = true; }
+      }
       ++ns;
       if (T < S.thr || ns >= S.max_samples) m.done = true;
     }
@@ -175,10 +201,12 @@ __global__ void __launch_bounds__(256) render_kernel(SceneArgs S, int64_t n, con
     if (out.depth) out.depth[ray] = depth;
     if (out.n_samples) out.n_samples[ray] = ns;
     if (out.n_reads) out.n_reads[ray] = reads;
-    if (out.t_first) out.t_first[ray] = t_first;
-    if (out.t_last) out.t_last[ray] = t_last;
-    if (out.t_half) out.t_half[ray] = t_half;
-    if (pa.fallback) pa.fallback[ray] = fell_back ? 1 : 0;
+    if (EXT) {
+      if (out.t_first) out.t_first[ray] = t_first;
+      if (out.t_last) out.t_last[ray] = t_last;
+      if (out.t_half) out.t_half[ray] = t_half;
+      if (pa.fallback) pa.fallback[ray] = fell_back ? 1 : 0;
+    }
   }
   float* xin = xin_all[wave];
   xin[0 * 64 + lane] = cd[0];
@@ -254,8 +282,13 @@ int launch_render(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, con
   if (blocks > 0x7FFFFFFF) return fail(ctx, NGPRT_E_SHAPE, "too many rays for one launch");
   MarchRecord rec{nullptr, nullptr, nullptr, 0};
   ProposalArgs pa{prop, conf_thr, margin, fallback};
-  dispatch<MODE_RENDER>(S, ctx->desc.domain, ctx->desc.table_dtype, dim3(unsigned(blocks)), st, n, o,
-                        d, out, rec, ctx->mlp, 0, pa);
+  const bool ext = prop || out.t_first || out.t_last || out.t_half;
+  if (ext)
+    dispatch<MODE_RENDER_EXT>(S, ctx->desc.domain, ctx->desc.table_dtype, dim3(unsigned(blocks)), st, n,
+                              o, d, out, rec, ctx->mlp, 0, pa);
+  else
+    dispatch<MODE_RENDER>(S, ctx->desc.domain, ctx->desc.table_dtype, dim3(unsigned(blocks)), st, n, o,
+                          d, out, rec, ctx->mlp, 0, pa);
   return check_launch(ctx, "render_kernel");
 }
 
