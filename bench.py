@@ -39,7 +39,177 @@ def parse():
     p.add_argument("--views", type=int, default=8)
     p.add_argument("--copy-probe-mb", type=int, default=0,
                    help="run one device copy of this many MiB first (hardware-counter calibration)")
+    p.add_argument("--mode", choices=["render", "train", "proposal"], default="render",
+                   help="render: the headline; train: forward+backward+Adam steps; "
+                        "proposal: learned sample-interval proposal vs plain marching")
+    p.add_argument("--train-size", choices=["tiny", "train_large"], default="tiny")
+    p.add_argument("--prop-epochs", type=int, default=12)
     return p.parse_args()
+
+
+def _events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def bench_train(args):
+    """One step = render 2^18 rays (16 cameras x 128^2) with the student
+    tables, mean-squared colour loss against a teacher (tables of seed 1),
+    hand-written backward, Adam on tables and MLP."""
+    import torch
+
+    import synth
+    from paper_2407_10482_amd.renderer import Renderer, adam_step, render_differentiable
+
+    cfg = synth.CONFIGS[args.train_size]()
+    sc = synth.make_scene(cfg)
+    teacher = synth.make_scene(cfg, seed=1)
+    cams = synth.random_sphere_cameras(16, 1.0, seed=123)
+    o, d, _ = synth.scene_rays(cfg, cams=cams, width=128, height=128)
+    torch.cuda.set_device(0)
+    r = Renderer.from_config(cfg)
+    r.load_scene(torch.from_numpy(teacher.tables).cuda(), torch.from_numpy(sc.occ).cuda(),
+                 torch.from_numpy(sc.mlp).cuda())
+    go, gd = torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda()
+    target = r.render(go, gd, aux=False)["rgb"].clone()
+    tables = torch.from_numpy(sc.tables).cuda().requires_grad_(True)
+    mlp = torch.from_numpy(sc.mlp).cuda().requires_grad_(True)
+    mt, vt = torch.zeros_like(tables), torch.zeros_like(tables)
+    mm, vm = torch.zeros_like(mlp), torch.zeros_like(mlp)
+    state = {"step": 0, "loss": []}
+
+    def step():
+        rgb = render_differentiable(r, tables, mlp, go, gd)
+        loss = torch.mean((rgb - target) ** 2)
+        loss.backward()
+        state["step"] += 1
+        with torch.no_grad():
+            adam_step(tables, tables.grad, mt, vt, state["step"], 0.01)
+            adam_step(mlp, mlp.grad, mm, vm, state["step"], 0.01)
+        tables.grad = None
+        mlp.grad = None
+        return loss
+
+    first = step().item()
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    start, end = _events()
+    start.record()
+    for _ in range(args.steps):
+        loss = step()
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / args.steps
+    n_params = tables.numel() + mlp.numel()
+    return {
+        "metric": "training steps/s (render + backward + Adam)",
+        "value": round(1e3 / ms, 3),
+        "unit": "steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: {cfg.n_levels} levels {cfg.n_min}..{cfg.n_max}, "
+                               f"2^{cfg.log2_table} entries, 2^18 rays from 16 cameras x 128^2, "
+                               "MSE vs a seed-1 teacher, Adam lr 0.01",
+                   "rays_per_step": len(o), "parameters": n_params},
+        "loss_first": first, "loss_last": loss.item(),
+    }
+
+
+def bench_proposal(args):
+    """Train the proposal network on 2^22 labelled rays (64 cameras x 256^2 of
+    the tiny scene, labels from the plain renderer), then render 8 unseen
+    1920x1080 views plainly and with the proposal."""
+    import torch
+
+    import synth
+    from paper_2407_10482_amd.renderer import Proposal, Renderer, proposal_init
+
+    cfg = synth.tiny()
+    sc = synth.make_scene(cfg)
+    torch.cuda.set_device(0)
+    r = Renderer.from_config(cfg)
+    r.load_scene(torch.from_numpy(sc.tables).cuda(), torch.from_numpy(sc.occ).cuda(),
+                 torch.from_numpy(sc.mlp).cuda())
+    # labels from the plain renderer
+    tcams = synth.random_sphere_cameras(64, 1.0, seed=1000)
+    to, td, _ = synth.scene_rays(cfg, cams=tcams, width=256, height=256)
+    to, td = torch.from_numpy(to).cuda(), torch.from_numpy(td).cuda()
+    lab_out = r.render(to, td, out=r.alloc_outputs(len(to), labels=True))
+    labels = torch.stack([lab_out["t_first"], lab_out["t_far"], lab_out["t_half"],
+                          (lab_out["n_samples"] > 0).float()], dim=1).contiguous()
+    net = Proposal(proposal_init(7), r)
+    n = len(to)
+    bs = 1 << 14
+    g = torch.Generator(device="cuda").manual_seed(0)
+    t0 = time.time()
+    margin = 2.0 * cfg.step
+    loss = torch.zeros((1,), dtype=torch.float32, device="cuda")
+    history = []
+    for ep in range(args.prop_epochs):
+        phase = 1 if ep < (2 * args.prop_epochs) // 3 else 2
+        lr = 3e-3 if phase == 1 else 1e-3
+        perm = torch.randperm(n, generator=g, device="cuda")
+        loss.zero_()
+        for b in range(0, n, bs):
+            idx = perm[b:b + bs]
+            net.train_step(to[idx].contiguous(), td[idx].contiguous(), labels[idx].contiguous(), lr,
+                           phase=phase, margin=margin, loss=loss)
+        history.append(round(loss.item() / (n // bs), 6))
+    torch.cuda.synchronize()
+    train_s = time.time() - t0
+    # unseen views
+    ecams = synth.random_sphere_cameras(8, 1.0, seed=2000)
+    eo, ed, _ = synth.scene_rays(cfg, cams=ecams, width=1920, height=1080)
+    eo, ed = torch.from_numpy(eo).cuda(), torch.from_numpy(ed).cuda()
+    ne = len(eo)
+    plain = r.render(eo, ed)
+    prop = net.infer(eo, ed)
+    withp = r.render_proposal(eo, ed, prop, 0.9, margin)
+    torch.cuda.synchronize()
+    mse = torch.mean((withp["rgb"] - plain["rgb"]) ** 2).item()
+    psnr = float("inf") if mse == 0 else 10 * np.log10(1.0 / mse)
+
+    def timed(fn):
+        outp = {"rgb": torch.empty((ne, 3), dtype=torch.float32, device="cuda")}
+        for _ in range(args.warmup):
+            fn(outp)
+        torch.cuda.synchronize()
+        s0, s1 = _events()
+        s0.record()
+        for _ in range(args.steps):
+            fn(outp)
+        s1.record()
+        torch.cuda.synchronize()
+        return s0.elapsed_time(s1) / args.steps
+
+    ms_plain = timed(lambda outp: r.render(eo, ed, out=outp))
+    ms_prop = timed(lambda outp: r.render_proposal(eo, ed, net.infer(eo, ed), 0.9, margin, out=outp))
+    views = 8
+    return {
+        "metric": "1080p frames/s, learned proposal vs plain distance-grid marching",
+        "value": round(views / (ms_prop / 1e3), 3),
+        "unit": "frames/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_prop, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16",
+        "data": "synthetic",
+        "config": {"workload": "tiny scene, proposal trained on 2^22 rays (64 cameras x 256^2), "
+                               "evaluated on 8 unseen 1920x1080 views; conf >= 0.9, margin 2 steps",
+                   "rays_per_step": ne},
+        "plain_fps": round(views / (ms_plain / 1e3), 3),
+        "plain_ms": round(ms_plain, 4),
+        "speedup": round(ms_plain / ms_prop, 4),
+        "samples_per_ray": {"plain": round(plain["n_samples"].float().mean().item(), 3),
+                            "proposal": round(withp["n_samples"].float().mean().item(), 3)},
+        "reads_per_ray": {"plain": round(plain["n_reads"].float().mean().item(), 3),
+                          "proposal": round(withp["n_reads"].float().mean().item(), 3)},
+        "fallback_fraction": round(withp["fallback"].float().mean().item(), 4),
+        "confident_fraction": round((prop[:, 3] >= 0.9).float().mean().item(), 4),
+        "psnr_proposal_vs_plain_db": round(psnr, 3),
+        "train_seconds": round(train_s, 1),
+        "train_loss_per_epoch": history,
+    }
 
 
 def cpu_baseline(sc, dist, o, d, dtype, seconds):
@@ -76,6 +246,12 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.mode == "train":
+        print(json.dumps(bench_train(args)), flush=True)
+        return
+    if args.mode == "proposal":
+        print(json.dumps(bench_proposal(args)), flush=True)
+        return
     import torch
 
     import synth

@@ -96,8 +96,9 @@ typedef struct ngprt_outputs {
   int32_t* n_samples;/* [n]    evaluated (occupied) samples */
   int32_t* n_reads;  /* [n]    occupancy/distance grid reads (marching points) */
   float* t_first;    /* [n]    t of the first evaluated sample (0 if none) */
-  float* t_last;     /* [n]    t of the last evaluated sample (0 if none) */
-  float* t_half;     /* [n]    t of the sample after which T < 0.5 (t_last if never) */
+  float* t_far;      /* [n]    t of the sample after which T < 2e-3, the paper's own stopping
+                      *        threshold (the last sample's t if never; 0 if no sample) */
+  float* t_half;     /* [n]    t of the sample after which T < 0.5 (last sample's t if never) */
 } ngprt_outputs;
 
 /* Create a context on the current HIP device.  Validates the descriptor
@@ -153,8 +154,9 @@ int ngprt_render(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins,
  * lattice points with t in [t_near - margin, t_far + margin]; when that
  * yields no sample (the interval misses the occupied space) the ray falls
  * back to the plain march.  Other rays march plainly.  dev_fallback: int32
- * [n] (NULL-able), 1 where the fallback ran.  A correct interval gives the
- * plain render's samples bit for bit. */
+ * [n] (NULL-able), 1 where the fallback ran.  An interval that holds all of a
+ * ray's samples reproduces the plain render bit for bit; one that ends
+ * earlier drops the tail samples. */
 int ngprt_render_proposal(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins,
                           const float* dev_dirs, const float* dev_proposal, float conf_threshold,
                           float margin, const ngprt_outputs* out, int32_t* dev_fallback, void* stream);
@@ -209,9 +211,10 @@ int ngprt_proposal_infer(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origin
 
 /* One training step on a batch of n_rays >= 1 rays.  dev_labels: float32
  * [n][4] = t_near, t_far, t_term, valid (1 for rays with samples, else 0).
- * Loss = (sum over valid rays of the squared error of the three depths
- * + for phase 2 the cross-entropy of the confidence against "the predicted
- * interval widened by margin contains [t_near, t_far]") / n.  Adds the batch
+ * Loss = (sum over valid rays of the pinball loss of t_near at quantile
+ * 0.05 and of t_far at 0.95 plus the squared error of t_term, + for phase 2
+ * the cross-entropy of the confidence against "the predicted interval
+ * widened by margin contains [t_near, t_far]") / n.  Adds the batch
  * loss to dev_loss[0] (NULL-able); writes the gradient to dev_grad [7556]
  * (NULL-able); when dev_m and dev_v (Adam moments [7556], zero before step
  * 1) are given, applies Adam (beta1 0.9, beta2 0.99, eps 1e-8, step >= 1) to

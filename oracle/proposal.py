@@ -7,15 +7,21 @@ hidden layers, outputs [t_near, t_far, t_term, conf logit].  Parameters,
 flattened: W1[64][48], b1[64], W2[64][64], b2[64], W3[4][64], b3[4]
 (7556 values).
 
-Labels come from the plain renderer's decided samples: t_near / t_far = t of
-the first / last evaluated sample, t_term = t of the sample after which the
-transmittance first drops below 0.5 (t_far if it never does); rays without
-samples are marked invalid.
+Labels come from the plain renderer's decided samples: t_near = t of the
+first evaluated sample; t_far = t of the sample after which the
+transmittance first drops below 2e-3 (the stopping threshold of the paper's
+own renderer, supplement "Real-time Rendering" item 2; the last sample's t if
+it never does); t_term = t of the sample after which the transmittance first
+drops below 0.5 (the last sample's t if never); rays without samples are
+marked invalid.
 
-Loss per batch of n rays (sums divided by n):
-  regression  sum over valid rays of sum_{c<3} (out_c - y_c)^2,
-  confidence  (second phase) binary cross-entropy of sigmoid(out_3) against
-              target = valid and [out_0 - m, out_1 + m] contains [y_0, y_1].
+Loss per batch of n rays (sums divided by n), over valid rays:
+  t_near  pinball loss at quantile 0.05 (the prediction learns to sit low),
+  t_far   pinball loss at quantile 0.95 (learns to sit high),
+  t_term  squared error;
+  pinball_q(r) = q r for r = y - pred >= 0, else (q - 1) r.
+Second phase adds the binary cross-entropy of sigmoid(out_3) against
+target = valid and [out_0 - m, out_1 + m] contains [y_0, y_1].
 
 The GPU trains with bfloat16 GEMM operands and float32 accumulation; the
 oracle reproduces the operand rounding (bf16_operands=True) and computes in
@@ -88,14 +94,28 @@ def conf_target(out, labels, valid, margin):
     return (valid & (out[:, 0] - margin <= labels[:, 0]) & (out[:, 1] + margin >= labels[:, 1])).astype(np.float64)
 
 
+Q_NEAR, Q_FAR = 0.05, 0.95
+
+
+def _pinball(pred, y, q):
+    r = y - pred
+    loss = np.where(r >= 0, q * r, (q - 1.0) * r)
+    grad = np.where(pred > y, 1.0 - q, -q)
+    return loss, grad
+
+
 def loss_and_grad_out(out, labels, valid, phase, margin):
     """Loss and dL/dout for one batch."""
     n = out.shape[0]
     v = valid.astype(np.float64)
-    diff = (out[:, :3] - labels[:, :3]) * v[:, None]
-    loss = float(np.sum(diff ** 2)) / n
+    l0, g0 = _pinball(out[:, 0], labels[:, 0], Q_NEAR)
+    l1, g1 = _pinball(out[:, 1], labels[:, 1], Q_FAR)
+    df = out[:, 2] - labels[:, 2]
+    loss = float(np.sum(v * (l0 + l1 + df * df))) / n
     g = np.zeros_like(out)
-    g[:, :3] = 2.0 * diff / n
+    g[:, 0] = v * g0 / n
+    g[:, 1] = v * g1 / n
+    g[:, 2] = v * 2.0 * df / n
     if phase >= 2:
         tgt = conf_target(out, labels, valid, margin)
         s = 1.0 / (1.0 + np.exp(-out[:, 3]))
@@ -120,6 +140,10 @@ def backward(p, fwd, g_out, bf16_operands=True):
     return np.concatenate([gW1.ravel(), gb1, gW2.ravel(), gb2, gW3.ravel(), gb3])
 
 
+T_FAR = np.float32(2e-3)
+T_TERM = np.float32(0.5)
+
+
 def labels_from_march(n_rays, s_ray, s_t, s_T):
     """(t_near, t_far, t_term, valid) per ray from decided samples sorted by
     (ray, k) with the float32 transmittance after each sample."""
@@ -132,9 +156,9 @@ def labels_from_march(n_rays, s_ray, s_t, s_T):
     rays = s_ray[starts]
     valid[rays] = True
     lab[rays, 0] = s_t[starts]
-    lab[rays, 1] = s_t[ends - 1]
     for a, b, r in zip(starts, ends, rays):
-        below = np.nonzero(s_T[a:b] < np.float32(0.5))[0]
-        lab[r, 2] = s_t[a + below[0]] if len(below) else s_t[b - 1]
+        for col, thr in ((1, T_FAR), (2, T_TERM)):
+            below = np.nonzero(s_T[a:b] < thr)[0]
+            lab[r, col] = s_t[a + below[0]] if len(below) else s_t[b - 1]
     lab[:, 3] = valid
     return lab, valid

@@ -38,7 +38,7 @@ class NgprtDesc(ctypes.Structure):
 class NgprtOutputs(ctypes.Structure):
     _fields_ = [(name, ctypes.c_void_p) for name in
                 ("rgb", "c_d", "feat", "t_final", "depth", "n_samples", "n_reads", "t_first",
-                 "t_last", "t_half")]
+                 "t_far", "t_half")]
 
 
 # (name, restype, argtypes)

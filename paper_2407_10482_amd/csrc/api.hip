@@ -212,7 +212,7 @@ int ngprt_render(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins, const
   if (rc) return rc;
   if (!ctx->mlp_loaded) return fail(ctx, NGPRT_E_NOT_LOADED, "mlp not loaded");
   RayOut o{out->rgb,       out->c_d,     out->feat,   out->t_final, out->depth,
-           out->n_samples, out->n_reads, out->t_first, out->t_last,  out->t_half};
+           out->n_samples, out->n_reads, out->t_first, out->t_far,   out->t_half};
   return launch_render(ctx, n_rays, dev_origins, dev_dirs, o, nullptr, 0.0f, 0.0f, nullptr,
                        (hipStream_t)stream);
 }
@@ -231,7 +231,7 @@ int ngprt_render_proposal(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origi
   if (rc) return rc;
   if (!ctx->mlp_loaded) return fail(ctx, NGPRT_E_NOT_LOADED, "mlp not loaded");
   RayOut o{out->rgb,       out->c_d,     out->feat,   out->t_final, out->depth,
-           out->n_samples, out->n_reads, out->t_first, out->t_last,  out->t_half};
+           out->n_samples, out->n_reads, out->t_first, out->t_far,   out->t_half};
   return launch_render(ctx, n_rays, dev_origins, dev_dirs, o, dev_proposal, conf_threshold, margin,
                        dev_fallback, (hipStream_t)stream);
 }

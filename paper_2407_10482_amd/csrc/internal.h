@@ -48,7 +48,7 @@ struct RayOut {
   int32_t* n_samples;
   int32_t* n_reads;
   float* t_first;
-  float* t_last;
+  float* t_far;
   float* t_half;
 };
 

@@ -148,7 +148,8 @@ __global__ void __launch_bounds__(64) prop_infer_kernel(int64_t n, const float* 
   }
 }
 
-// Labels [n][4]: t_near, t_far, t_term, valid (1/0).  phase 1: regression;
+// Labels [n][4]: t_near, t_far, t_term, valid (1/0).  phase 1: pinball
+// losses on t_near (quantile 0.05) and t_far (0.95), squared error on t_term;
 // phase >= 2: + confidence cross-entropy with target = valid and
 // [out0 - margin, out1 + margin] contains [t_near, t_far].  Loss terms are
 // divided by n (the batch).
@@ -178,12 +179,12 @@ __global__ void __launch_bounds__(64) prop_train_kernel(int64_t n, const float* 
 #pragma unroll
     for (int c = 0; c < 4; ++c) ov[c] = L.out[c * 64 + lane];
     if (valid) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const float df = ov[c] - y[c];
-        loss += df * df;
-        go[c] = 2.0f * df * inv_n;
-      }
+      // t_near: pinball loss at quantile 0.05; t_far: at 0.95; t_term: squared error
+      const float r0 = y[0] - ov[0], r1 = y[1] - ov[1], df = ov[2] - y[2];
+      loss += (r0 >= 0.0f ? 0.05f * r0 : -0.95f * r0) + (r1 >= 0.0f ? 0.95f * r1 : -0.05f * r1) + df * df;
+      go[0] = (ov[0] > y[0] ? 0.95f : -0.05f) * inv_n;
+      go[1] = (ov[1] > y[1] ? 0.05f : -0.95f) * inv_n;
+      go[2] = 2.0f * df * inv_n;
     }
     if (phase >= 2) {
       const float tgt = (valid && ov[0] - margin <= y[0] && ov[1] + margin >= y[1]) ? 1.0f : 0.0f;

@@ -20,7 +20,7 @@ namespace ngprt {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // MODE_RENDER: plain render.  MODE_RENDER_EXT: render that also writes the
-// label outputs (t_first / t_last / t_half) and honours a proposal.
+// label outputs (t_first / t_far / t_half) and honours a proposal.
 // MODE_MARCH: sample lists for parity checks (no MLP).
 enum { MODE_RENDER = 0, MODE_MARCH = 1, MODE_RENDER_EXT = 2 };
 
@@ -146,8 +146,10 @@ render_kernel(SceneArgs S, int64_t n, const float* __restrict__ O,
     }
   }
   float T = 1.0f, cd[3] = {0.f, 0.f, 0.f}, fv[4] = {0.f, 0.f, 0.f, 0.f}, depth = 0.0f;
-  float t_first = 0.0f, t_last = 0.0f, t_half = 0.0f;
-  bool half_set = false;
+  // labels: t of the first sample, of the sample after which T < 0.5, and of
+  // the sample after which T < 2e-3 (the paper's own stopping threshold)
+  float t_first = 0.0f, t_last = 0.0f, t_half = 0.0f, t_far = 0.0f;
+  bool half_set = false, far_set = false;
   int ns = 0, reads = 0;
 
   for (;;) {
@@ -179,12 +181,14 @@ render_kernel(SceneArgs S, int64_t n, const float* __restrict__ O,
         if (ns == 0) t_first = ts;
         t_last = ts;
         if (!half_set && T < 0.5f) { t_half = ts; half_set = true; }
+        if (!far_set && T < 2e-3f) { t_far = ts; far_set = true; }
       }
       ++ns;
       if (T < S.thr || ns >= S.max_samples) m.done = true;
     }
   }
   if (!half_set) t_half = t_last;
+  if (!far_set) t_far = t_last;
 
   if (MODE == MODE_MARCH) {
     if (in_range) {
@@ -203,7 +207,7 @@ render_kernel(SceneArgs S, int64_t n, const float* __restrict__ O,
     if (out.n_reads) out.n_reads[ray] = reads;
     if (EXT) {
       if (out.t_first) out.t_first[ray] = t_first;
-      if (out.t_last) out.t_last[ray] = t_last;
+      if (out.t_far) out.t_far[ray] = t_far;
       if (out.t_half) out.t_half[ray] = t_half;
       if (pa.fallback) pa.fallback[ray] = fell_back ? 1 : 0;
     }
@@ -282,7 +286,7 @@ int launch_render(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, con
   if (blocks > 0x7FFFFFFF) return fail(ctx, NGPRT_E_SHAPE, "too many rays for one launch");
   MarchRecord rec{nullptr, nullptr, nullptr, 0};
   ProposalArgs pa{prop, conf_thr, margin, fallback};
-  const bool ext = prop || out.t_first || out.t_last || out.t_half;
+  const bool ext = prop || out.t_first || out.t_far || out.t_half;
   if (ext)
     dispatch<MODE_RENDER_EXT>(S, ctx->desc.domain, ctx->desc.table_dtype, dim3(unsigned(blocks)), st, n,
                               o, d, out, rec, ctx->mlp, 0, pa);

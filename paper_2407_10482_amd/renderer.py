@@ -113,7 +113,7 @@ class Renderer:
         return out
 
     OUTPUT_FIELDS = ("rgb", "c_d", "feat", "t_final", "depth", "n_samples", "n_reads", "t_first",
-                     "t_last", "t_half")
+                     "t_far", "t_half")
 
     @staticmethod
     def _outputs(out: Dict[str, torch.Tensor]) -> NgprtOutputs:
@@ -130,7 +130,7 @@ class Renderer:
                    n_samples=torch.empty((n,), dtype=torch.int32, device="cuda"),
                    n_reads=torch.empty((n,), dtype=torch.int32, device="cuda"))
         if labels:
-            out.update(t_first=torch.empty((n,), **f), t_last=torch.empty((n,), **f),
+            out.update(t_first=torch.empty((n,), **f), t_far=torch.empty((n,), **f),
                        t_half=torch.empty((n,), **f))
         return out
 
@@ -229,6 +229,18 @@ def render_differentiable(renderer: Renderer, tables, mlp, origins, dirs):
 
 
 N_PROPOSAL_PARAMS = 7556
+
+
+def proposal_init(seed: int) -> torch.Tensor:
+    """He-uniform float32 weights and zero biases for the proposal network
+    (W1[64][48], b1[64], W2[64][64], b2[64], W3[4][64], b3[4]), on the GPU."""
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    parts = []
+    for fin, fout in ((48, 64), (64, 64), (64, 4)):
+        a = (6.0 / fin) ** 0.5
+        parts.append((torch.rand((fout * fin,), generator=g, dtype=torch.float64) * 2 - 1) * a)
+        parts.append(torch.zeros(fout, dtype=torch.float64))
+    return torch.cat(parts).float().cuda()
 
 
 class Proposal:

@@ -109,4 +109,14 @@ def hd(seed: int = 0, table_dtype: int = DTYPE_F32) -> SceneConfig:
         table_dtype=table_dtype, seed=seed)
 
 
-CONFIGS = {"tiny": tiny, "hd": hd}
+def train_large(seed: int = 0, table_dtype: int = DTYPE_F32) -> SceneConfig:
+    """The tiny scene's geometry with the hd hash grid (16 levels 16..4096,
+    2^19 entries): the large-table training measurement."""
+    cfg = tiny(seed, table_dtype)
+    cfg.name = "train_large"
+    cfg.n_levels, cfg.n_max, cfg.log2_table = 16, 4096, 19
+    cfg.resolutions = geometric_resolutions(cfg.n_min, cfg.n_max, cfg.n_levels)
+    return cfg
+
+
+CONFIGS = {"tiny": tiny, "hd": hd, "train_large": train_large}

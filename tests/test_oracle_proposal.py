@@ -46,7 +46,11 @@ def test_proposal_gradient_matches_finite_differences():
                 ff = P.forward(pp, enc, bf16_operands=False)
                 out = ff["out"]
                 v = tgt_valid.astype(np.float64)
-                val = np.sum(((out[:, :3] - labels[:, :3]) * v[:, None]) ** 2) / n
+                # pinball losses written out from their definition
+                r0 = labels[:, 0] - out[:, 0]
+                r1 = labels[:, 1] - out[:, 1]
+                pin = np.maximum(0.05 * r0, -0.95 * r0) + np.maximum(0.95 * r1, -0.05 * r1)
+                val = np.sum(v * (pin + (out[:, 2] - labels[:, 2]) ** 2)) / n
                 if phase >= 2:
                     tgt = P.conf_target(f["out"], labels, valid, 0.05)
                     s = 1 / (1 + np.exp(-out[:, 3]))
@@ -61,10 +65,14 @@ def test_proposal_gradient_matches_finite_differences():
 def test_labels_from_decided_samples():
     s_ray = np.array([0, 0, 0, 2, 2])
     s_t = np.array([0.1, 0.2, 0.3, 1.0, 1.5], F32)
-    s_T = np.array([0.9, 0.4, 0.1, 0.8, 0.7], F32)
+    s_T = np.array([0.9, 0.4, 0.001, 0.8, 0.7], F32)
     lab, valid = P.labels_from_march(3, s_ray, s_t, s_T)
     assert valid.tolist() == [True, False, True]
+    # ray 0: T < 0.5 after the 2nd sample, < 2e-3 after the 3rd
     assert np.allclose(lab[0], [0.1, 0.3, 0.2, 1]) and np.allclose(lab[2], [1.0, 1.5, 1.5, 1])
+    s_T2 = np.array([0.001, 0.0005, 0.0001, 0.8, 0.7], F32)
+    lab2, _ = P.labels_from_march(3, s_ray, s_t, s_T2)
+    assert np.allclose(lab2[0], [0.1, 0.1, 0.1, 1])
     assert np.all(lab[1] == 0)
 
 
@@ -79,7 +87,10 @@ def test_interval_march_with_exact_labels_equals_plain():
     o, d = o[::9], d[::9]
     ref = render(inp, o, d)
     lab, valid = P.labels_from_march(len(o), ref.s_ray, ref.s_t, ref.extra["s_T"])
-    prop = np.concatenate([lab[:, :3], valid[:, None].astype(np.float32)], axis=1)
+    # an interval from the first to the last sample holds every sample
+    t_last = np.zeros(len(o), np.float32)
+    t_last[ref.s_ray] = ref.s_t          # samples are sorted by (ray, k): the last write wins
+    prop = np.stack([lab[:, 0], t_last, lab[:, 2], valid.astype(np.float32)], axis=1)
     res, fb = render_proposal(inp, o, d, prop, 0.9, 0.0)
     assert np.array_equal(res.s_k, ref.s_k) and np.array_equal(res.n_samples, ref.n_samples)
     assert np.array_equal(res.rgb, ref.rgb) and not fb.any()
@@ -92,8 +103,11 @@ def test_interval_march_with_exact_labels_equals_plain():
     res2, fb2 = render_proposal(inp, o, d, bad, 0.9, 0.0)
     assert fb2[ref.n_samples > 0].all()
     assert np.array_equal(res2.s_k, ref.s_k) and np.array_equal(res2.rgb, ref.rgb)
-    # a truncated interval loses exactly the samples outside it
+    # ending the interval where T first drops below 2e-3 drops the tail
+    # samples, which carry at most 2e-3 of the colour weight
     cut = prop.copy()
-    cut[:, 1] = (lab[:, 0] + lab[:, 1]) / 2
+    cut[:, 1] = lab[:, 1]
     res3, _ = render_proposal(inp, o, d, cut, 0.9, 0.0)
     assert (res3.n_samples <= ref.n_samples).all() and (res3.n_samples < ref.n_samples).any()
+    assert np.abs(res3.c_d - ref.c_d).max() <= 2.1e-3 * np.abs(ref.c_d).max() + 1e-12
+    assert np.all((res3.t_final <= 2e-3 + 1e-9) | (res3.n_samples == ref.n_samples))
