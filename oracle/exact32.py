@@ -21,8 +21,7 @@ with LOG2E = fl32(log2 e) = 0x3FB8AA3B, LN2_HI = 0.693359375 (0x3F318000),
 LN2_LO = fl32(ln 2 - LN2_HI) = 0xB95E8083, and c_j = fl32(1/j!).
 Its error against the true exponential is a few ulp (pinned in the tests).
 
-pairwise_sum: level sums are taken as a balanced binary tree over the levels
-padded with zeros to the next power of two, S(v[0:n]) = S(v[0:n/2]) + S(v[n/2:n]).
+Sums over hash levels are taken in level order, l = 0, 1, ..., L - 1.
 """
 from __future__ import annotations
 
@@ -65,18 +64,6 @@ def exp32(x) -> np.ndarray:
     out[lo] = F32(0.0)
     out[nan] = np.nan
     return out[0] if scalar else out
-
-
-def pairwise_sum(vals):
-    """Balanced-tree sum of a list of equally shaped float32 arrays."""
-    n = len(vals)
-    p = 1
-    while p < n:
-        p *= 2
-    work = list(vals) + [np.zeros_like(vals[0])] * (p - n)
-    while len(work) > 1:
-        work = [work[i] + work[i + 1] for i in range(0, len(work), 2)]
-    return work[0]
 
 
 def sqrt32(x) -> np.ndarray:

@@ -22,8 +22,8 @@ What one ray computes (paper sections in brackets):
 3. At a sample: trilinear lookup in every hash level [Sec. 3 Eq. 3,
    Sec. 4.1 Eq. 6] of 8 feature channels and 1 attention logit.
 4. Attention across levels [Sec. 4.2 Eq. 7-8, softmax reading]: weights
-   w_l = softmax_l(logit_l) (max-subtracted), fused channel = sum_l w_l v_l;
-   density and colour share the weights.
+   w_l = softmax_l(logit_l), fused channel = sum_l w_l v_l; density and
+   colour share the weights.
 5. Activation and compositing [Eq. 2, Eq. 5; supplement "Activation
    Layers"]: sigma = exp(fused_0); alpha = 1 - exp(-sigma * delta);
    C_d += T alpha c_d, F += T alpha v_s, T *= 1 - alpha; the ray stops once
@@ -45,7 +45,7 @@ from typing import List, Optional
 
 import numpy as np
 
-from .exact32 import F32, exp32, pairwise_sum, sqrt32
+from .exact32 import F32, exp32, sqrt32
 from .hashgrid import corners32, corners64
 from . import quant
 
@@ -93,6 +93,12 @@ class OracleInputs:
             self.val64 = self.deq32.astype(np.float64) * self.scales.astype(np.float64)[:, None, :]
         else:
             raise ValueError("unknown table dtype")
+        # softmax shift: the largest stored logit over all levels (float32,
+        # dequantised), a scene constant
+        lg = self.deq32[:, :, 8]
+        if self.scales is not None:
+            lg = lg * self.scales[:, 8][:, None]
+        self.logit_shift = F32(np.max(lg))
         self.occ_flat = np.ascontiguousarray(self.occ, dtype=np.uint8).ravel()
         self.dist_flat = np.ascontiguousarray(self.dist, dtype=np.uint8).ravel()
 
@@ -116,10 +122,17 @@ class OracleInputs:
 def fused32(inp: OracleInputs, u: np.ndarray):
     """Float32 mirror of the lookup + attention chain at grid coordinates u.
 
+    Softmax across levels with a constant shift c (the largest stored
+    logit; the softmax is unchanged by any common shift): e_l =
+    exp32(a_l - c); levels accumulated in order, S = sum e_l,
+    fused_j = (sum e_l v_l[j]) / S, attention weights e_l / S.
+
     Returns fused channels [m, 8], attention weights [m, L], corner indices
     [m, L, 8]."""
     m = u.shape[0]
-    logits, vals, idxs = [], [], []
+    esum = np.zeros(m, dtype=F32)
+    num = np.zeros((m, 8), dtype=F32)
+    es, idxs = [], []
     for l, N in enumerate(inp.resolutions):
         idx, w = corners32(u, N, inp.T)
         idxs.append(idx)
@@ -129,17 +142,15 @@ def fused32(inp: OracleInputs, u: np.ndarray):
             acc = acc + w[:, c:c + 1] * g[:, c, :]
         if inp.scales is not None:
             acc = inp.scales[l][None, :] * acc
-        logits.append(acc[:, 8])
-        vals.append([acc[:, ch] for ch in range(8)])
-    mx = logits[0]
-    for a in logits[1:]:
-        mx = np.maximum(mx, a)
-    e = [exp32(a - mx) for a in logits]
-    S = pairwise_sum(e)
-    wl = [x / S for x in e]
-    fused = np.stack([pairwise_sum([wl[l] * vals[l][ch] for l in range(inp.L)])
-                      for ch in range(8)], axis=1)
-    return fused, np.stack(wl, axis=1), np.stack(idxs, axis=1)
+        e = exp32(acc[:, 8] - inp.logit_shift)
+        esum = esum + e
+        num = num + e[:, None] * acc[:, :8]
+        es.append(e)
+    ok = esum > 0
+    safe = np.where(ok, esum, F32(1.0))
+    fused = np.where(ok[:, None], num / safe[:, None], F32(0.0)).astype(F32)
+    wl = np.where(ok[:, None], np.stack(es, axis=1) / safe[:, None], F32(0.0)).astype(F32)
+    return fused, wl, np.stack(idxs, axis=1)
 
 
 def fused64(inp: OracleInputs, u: np.ndarray):

@@ -48,6 +48,7 @@ SceneArgs scene_args(const ngprt_ctx* ctx) {
   S.step = d.step;
   S.thr = d.t_threshold;
   S.max_samples = d.max_samples;
+  S.lshift = ctx->logit_shift;
   return S;
 }
 
@@ -140,7 +141,7 @@ int ngprt_create(const ngprt_desc* desc, ngprt_ctx** out) {
   const int64_t R = desc->occ_res;
   bool ok = hipMalloc(&ctx->feat, size_t(L * ctx->T * 8) * eb) == hipSuccess &&
             hipMalloc(&ctx->logit, size_t(L * ctx->T) * eb) == hipSuccess &&
-            hipMalloc((void**)&ctx->scales_dev, sizeof(float) * NGPRT_MAX_LEVELS * 9) == hipSuccess &&
+            hipMalloc((void**)&ctx->scales_dev, sizeof(float) * (NGPRT_MAX_LEVELS * 9 + 1)) == hipSuccess &&
             hipMalloc((void**)&ctx->grid, size_t(R * R * R) * sizeof(uint16_t)) == hipSuccess &&
             hipMalloc((void**)&ctx->mlp, sizeof(float) * kMlpParams) == hipSuccess;
   if (ok)

@@ -212,7 +212,8 @@ __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, c
     if (__ballot(have) == 0) break;
     if (have) {
       float f[8], wl[LMAX];
-      eval_fused<DT_F32, LMAX>(S, u, f, wl);
+      int32_t idx_unused[LMAX * 8];
+      eval_fused<DT_F32, LMAX, true>(S, u, f, wl, idx_unused);
       const float sigma = exp32(f[0]);
       const float e = exp32(-(sigma * S.step));
       const float w = T * (1.0f - e);

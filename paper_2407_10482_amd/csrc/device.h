@@ -137,114 +137,43 @@ __device__ __forceinline__ void level_corners(const float u[3], int N, float Nf,
   }
 }
 
-// Balanced-tree accumulator over a compile-time number of leaves (a power of
-// two): leaves pushed in order, merged as a binary counter, so the result is
-// ((v0+v1)+(v2+v3))+... exactly.
-template <int LMAX, int W> struct TreeSum {
-  static constexpr int DEPTH = (LMAX >= 16) ? 5 : (LMAX >= 8 ? 4 : (LMAX >= 4 ? 3 : 2));
-  float s[DEPTH][W];
-  int top = 0;
-  template <int LEAF>
-  __device__ __forceinline__ void push(const float v[W]) {
-#pragma unroll
-    for (int j = 0; j < W; ++j) s[top][j] = v[j];
-    ++top;
-    // merges = trailing zeros of (LEAF + 1)
-    constexpr int m = __builtin_ctz(LEAF + 1);
-#pragma unroll
-    for (int q = 0; q < m; ++q) {
-#pragma unroll
-      for (int j = 0; j < W; ++j) s[top - 2][j] = s[top - 2][j] + s[top - 1][j];
-      --top;
-    }
-  }
-};
-
-template <int LMAX, int I> struct Unroll {
-  template <class F> __device__ __forceinline__ static void run(F&& f) {
-    Unroll<LMAX, I - 1>::run(f);
-    f(std::integral_constant<int, I - 1>{});
-  }
-};
-template <int LMAX> struct Unroll<LMAX, 0> {
-  template <class F> __device__ __forceinline__ static void run(F&&) {}
-};
-
-// Lookup + attention at grid coordinate u: fused channels [8]; optionally
-// attention weights [L] and corner indices [L][8].
-template <int DT, int LMAX>
+// Lookup + attention at grid coordinate u, in one pass over the levels.
+// Per level: 8 corners, each gathering its feature row and logit; the
+// interpolated logit a_l gives e_l = exp32(a_l - c), where c is the scene's
+// largest stored logit (a constant: softmax is unchanged by any common shift,
+// and a_l <= c up to rounding keeps exp32 from overflowing); the levels are
+// accumulated in order: S = sum e_l, N_j = sum e_l v_l[j]; fused_j = N_j / S.
+// The density channel and S are on the decision chain (plain float32 ops);
+// the colour and specular channels use fma.  Optionally the attention
+// weights e_l / S [L] and corner indices [L][8].
+template <int DT, int LMAX, bool DEBUG = false>
 __device__ __forceinline__ void eval_fused(const SceneArgs& S, const float u[3], float fused[8],
                                            float* wout = nullptr, int32_t* idxout = nullptr) {
-  float a[LMAX];
-  // pass 1: interpolated logits of every level
+  float esum = 0.0f, num0 = 0.0f;
+  float num[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int l = 0; l < LMAX; ++l) {
-    a[l] = 0.0f;
     if (l < S.L) {
       Corners c;
       level_corners(u, S.N[l], S.Nf[l], S.mask, c);
       const size_t base = size_t(l) << S.log2T;
-      float v[8];
+      float acc[9];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) v[k] = Store<DT>::logit(S.logit, base + c.idx[k]);
-      float acc = 0.0f;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) acc = acc + c.w[k] * v[k];
-      if (DT == DT_FP8) acc = S.scale[l][8] * acc;
-      a[l] = acc;
-      if (idxout) {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) idxout[l * 8 + k] = int32_t(c.idx[k]);
-      }
-    }
-  }
-  // softmax across levels (max-subtracted), tree-ordered normaliser
-  float mx = a[0];
-#pragma unroll
-  for (int l = 1; l < LMAX; ++l)
-    if (l < S.L) mx = fmaxf(mx, a[l]);
-  float e[LMAX];
-#pragma unroll
-  for (int l = 0; l < LMAX; ++l) e[l] = (l < S.L) ? exp32(a[l] - mx) : 0.0f;
-  TreeSum<LMAX, 1> ts;
-  Unroll<LMAX, LMAX>::run([&](auto I) {
-    float x[1] = {e[I.value]};
-    ts.template push<I.value>(x);
-  });
-  const float Ssum = ts.s[0][0];
-  float w[LMAX];
-#pragma unroll
-  for (int l = 0; l < LMAX; ++l) w[l] = (l < S.L) ? e[l] / Ssum : 0.0f;
-  if (wout) {
-#pragma unroll
-    for (int l = 0; l < LMAX; ++l)
-      if (l < S.L) wout[l] = w[l];
-  }
-  // pass 2: features of every level, weighted.  The density channel (on the
-  // decision chain) is tree-summed over levels; the colour and specular
-  // channels decide nothing and accumulate in level order with fma.
-  TreeSum<LMAX, 1> fs0;
-  float facc[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  Unroll<LMAX, LMAX>::run([&](auto I) {
-    constexpr int l = I.value;
-    float p0[1] = {0.0f};
-    if (l < S.L) {
-      Corners c;
-      level_corners(u, S.N[l], S.Nf[l], S.mask, c);
-      const size_t base = size_t(l) << S.log2T;
-      float acc[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) acc[j] = 0.0f;
+      for (int j = 0; j < 9; ++j) acc[j] = 0.0f;
       // two groups of four corners keep the gathered rows in flight within
       // the register budget
 #pragma unroll
       for (int g = 0; g < 2; ++g) {
-        float v[4][8];
+        float v[4][8], lg[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) Store<DT>::feat(S.feat, base + c.idx[4 * g + k], v[k]);
+        for (int k = 0; k < 4; ++k) {
+          Store<DT>::feat(S.feat, base + c.idx[4 * g + k], v[k]);
+          lg[k] = Store<DT>::logit(S.logit, base + c.idx[4 * g + k]);
+        }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const float wk = c.w[4 * g + k];
+          acc[8] = acc[8] + wk * lg[k];
           acc[0] = acc[0] + wk * v[k][0];
 #pragma unroll
           for (int j = 1; j < 8; ++j) acc[j] = __builtin_fmaf(wk, v[k][j], acc[j]);
@@ -252,17 +181,34 @@ __device__ __forceinline__ void eval_fused(const SceneArgs& S, const float u[3],
       }
       if (DT == DT_FP8) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) acc[j] = S.scale[l][j] * acc[j];
+        for (int j = 0; j < 9; ++j) acc[j] = S.scale[l][j] * acc[j];
       }
-      p0[0] = w[l] * acc[0];
+      const float e = exp32(acc[8] - S.lshift);
+      esum = esum + e;
+      num0 = num0 + e * acc[0];
 #pragma unroll
-      for (int j = 0; j < 7; ++j) facc[j] = __builtin_fmaf(w[l], acc[1 + j], facc[j]);
+      for (int j = 0; j < 7; ++j) num[j] = __builtin_fmaf(e, acc[1 + j], num[j]);
+      if (DEBUG) {
+        wout[l] = e;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) idxout[l * 8 + k] = int32_t(c.idx[k]);
+      }
     }
-    fs0.template push<l>(p0);
-  });
-  fused[0] = fs0.s[0][0];
+  }
+  if (esum > 0.0f) {
+    fused[0] = num0 / esum;
+    const float inv = 1.0f / esum;
 #pragma unroll
-  for (int j = 0; j < 7; ++j) fused[1 + j] = facc[j];
+    for (int j = 0; j < 7; ++j) fused[1 + j] = num[j] * inv;
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) fused[j] = 0.0f;
+  }
+  if (DEBUG) {
+#pragma unroll
+    for (int l = 0; l < LMAX; ++l)
+      if (l < S.L) wout[l] = esum > 0.0f ? wout[l] / esum : 0.0f;
+  }
 }
 
 }  // namespace ngprt

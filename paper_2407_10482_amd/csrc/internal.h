@@ -25,6 +25,7 @@ struct SceneArgs {
   int N[kMaxLevels];
   float Nf[kMaxLevels];
   float scale[kMaxLevels][9];     // FP8 dequantisation scales (1 otherwise)
+  float lshift;                   // largest stored (dequantised) logit: the softmax shift
   const void* feat;               // [L][T][8] storage dtype
   const void* logit;              // [L][T]    storage dtype
   const uint16_t* grid;           // [R^3]: low byte G, bit 8 = occupied
@@ -60,8 +61,9 @@ struct ngprt_ctx {
   int64_t T = 0;
   void* feat = nullptr;       // [L][T][8]
   void* logit = nullptr;      // [L][T]
-  float* scales_dev = nullptr;// [L][9]
+  float* scales_dev = nullptr;// [16][9] scales + 1 scratch word
   float scales_host[NGPRT_MAX_LEVELS][9];
+  float logit_shift = 0.0f;   // largest stored logit (set by load_tables)
   uint16_t* grid = nullptr;   // [R^3]
   float* mlp = nullptr;       // [451]
   void* ws = nullptr;         // workspace (per-wave gradient partials of backward / proposal)

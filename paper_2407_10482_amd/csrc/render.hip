@@ -236,7 +236,7 @@ __global__ void __launch_bounds__(256) eval_points_kernel(SceneArgs S, int64_t n
   for (int a = 0; a < 3; ++a) u[a] = (p[a] - S.lo) * S.inv_ext;
   float f[8], w[LMAX];
   int32_t id[LMAX * 8];
-  eval_fused<DT, LMAX>(S, u, f, w, id);
+  eval_fused<DT, LMAX, true>(S, u, f, w, id);
   if (fused)
     for (int j = 0; j < 8; ++j) fused[i * 8 + j] = f[j];
   if (weights)

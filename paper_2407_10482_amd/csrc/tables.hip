@@ -74,7 +74,7 @@ __global__ void amax_kernel(const float* __restrict__ src, uint32_t* __restrict_
 }
 
 struct Scales9 {
-  float s[kMaxLevels][9];
+  float s[kMaxLevels][9] = {};
 };
 
 __global__ void split_fp8_kernel(const float* __restrict__ src, uint8_t* __restrict__ feat,
@@ -86,6 +86,56 @@ __global__ void split_fp8_kernel(const float* __restrict__ src, uint8_t* __restr
   const float* s = src + e * 9;
   for (int j = 0; j < 8; ++j) feat[e * 8 + j] = fp8_encode(s[j] / sc.s[l][j]);
   logit[e] = fp8_encode(s[8] / sc.s[l][8]);
+}
+
+// Largest stored logit (dequantised, float32) over all levels: the
+// constant shift of the softmax across levels.  Floats are compared through
+// an order-preserving unsigned key.
+__device__ __forceinline__ uint32_t order_key(float f) {
+  const uint32_t b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+template <int DT>
+__global__ void logit_max_kernel(const void* __restrict__ logit, int64_t T, Scales9 sc,
+                                 uint32_t* __restrict__ out) {
+  __shared__ uint32_t part;
+  const int l = int(blockIdx.y);
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (threadIdx.x == 0) part = 0;
+  __syncthreads();
+  if (i < T) {
+    const size_t e = size_t(l) * size_t(T) + size_t(i);
+    float v = Store<DT>::logit(logit, e);
+    if (DT == DT_FP8) v = sc.s[l][8] * v;
+    if (v == v) atomicMax(&part, order_key(v));
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(out, part);
+}
+
+static int compute_logit_shift(ngprt_ctx* ctx, const Scales9& sc, hipStream_t st) {
+  const int L = ctx->desc.n_levels;
+  const int64_t T = ctx->T;
+  uint32_t* key = reinterpret_cast<uint32_t*>(ctx->scales_dev) + kMaxLevels * 9;  // word after the scales
+  if (hipMemsetAsync(key, 0, sizeof(uint32_t), st) != hipSuccess) return check_launch(ctx, "memset");
+  dim3 g(unsigned((T + 255) / 256), unsigned(L));
+  switch (ctx->desc.table_dtype) {
+    case DT_F32: hipLaunchKernelGGL(logit_max_kernel<DT_F32>, g, dim3(256), 0, st, ctx->logit, T, sc, key); break;
+    case DT_BF16: hipLaunchKernelGGL(logit_max_kernel<DT_BF16>, g, dim3(256), 0, st, ctx->logit, T, sc, key); break;
+    default: hipLaunchKernelGGL(logit_max_kernel<DT_FP8>, g, dim3(256), 0, st, ctx->logit, T, sc, key); break;
+  }
+  int rc = check_launch(ctx, "logit_max_kernel");
+  if (rc) return rc;
+  uint32_t k = 0;
+  if (hipMemcpyAsync(&k, key, sizeof(uint32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return check_launch(ctx, "logit shift readback");
+  const uint32_t b = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
+  float f;
+  std::memcpy(&f, &b, 4);
+  ctx->logit_shift = (k == 0) ? 0.0f : f;
+  return NGPRT_OK;
 }
 
 template <typename Tv>
@@ -105,14 +155,18 @@ int launch_load_tables(ngprt_ctx* ctx, const float* src, hipStream_t st) {
   for (int l = 0; l < kMaxLevels; ++l)
     for (int c = 0; c < 9; ++c) ctx->scales_host[l][c] = 1.0f;
   switch (ctx->desc.table_dtype) {
-    case DT_F32:
+    case DT_F32: {
       hipLaunchKernelGGL(split_f32_kernel, dim3(nb), dim3(256), 0, st, src, (float*)ctx->feat,
                          (float*)ctx->logit, n);
-      return check_launch(ctx, "split_f32_kernel");
-    case DT_BF16:
+      int rc = check_launch(ctx, "split_f32_kernel");
+      return rc ? rc : compute_logit_shift(ctx, Scales9{}, st);
+    }
+    case DT_BF16: {
       hipLaunchKernelGGL(split_bf16_kernel, dim3(nb), dim3(256), 0, st, src, (uint16_t*)ctx->feat,
                          (uint16_t*)ctx->logit, n);
-      return check_launch(ctx, "split_bf16_kernel");
+      int rc = check_launch(ctx, "split_bf16_kernel");
+      return rc ? rc : compute_logit_shift(ctx, Scales9{}, st);
+    }
     case DT_FP8: {
       uint32_t* amax = reinterpret_cast<uint32_t*>(ctx->scales_dev);
       if (hipMemsetAsync(amax, 0, sizeof(uint32_t) * L * 9, st) != hipSuccess)
@@ -145,9 +199,8 @@ int launch_load_tables(ngprt_ctx* ctx, const float* src, hipStream_t st) {
                          (uint8_t*)ctx->logit, T, sc);
       rc = check_launch(ctx, "split_fp8_kernel");
       if (rc) return rc;
-      // the host copy of the scales must outlive the async upload
-      if (hipStreamSynchronize(st) != hipSuccess) return check_launch(ctx, "fp8 ingest");
-      return NGPRT_OK;
+      // synchronises: the host copy of the scales outlives the async upload
+      return compute_logit_shift(ctx, sc, st);
     }
     default:
       return fail(ctx, NGPRT_E_DTYPE, "unknown table dtype");
