@@ -80,6 +80,13 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build the HIP library first "
                            "(python -c 'import __graft_entry__ as g; g.build()')")
+    # Load PyTorch's HIP runtime first so libngprt binds to the same
+    # libamdhip64 instance (its SONAME satisfies libngprt's dependency);
+    # loading libngprt first would bring in a second runtime.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     for name, res, args in SIGNATURES:
         fn = getattr(lib, name)
