@@ -118,8 +118,8 @@ def bench_train(args):
 
 
 def bench_proposal(args):
-    """Train the proposal network on 2^22 labelled rays (64 cameras x 256^2 of
-    the tiny scene, labels from the plain renderer), then render 8 unseen
+    """Train the proposal network on 2^22 labelled rays (1024 cameras x 64^2
+    of the tiny scene, labels from the plain renderer), then render 8 unseen
     1920x1080 views plainly and with the proposal."""
     import torch
 
@@ -133,8 +133,8 @@ def bench_proposal(args):
     r.load_scene(torch.from_numpy(sc.tables).cuda(), torch.from_numpy(sc.occ).cuda(),
                  torch.from_numpy(sc.mlp).cuda())
     # labels from the plain renderer
-    tcams = synth.random_sphere_cameras(64, 1.0, seed=1000)
-    to, td, _ = synth.scene_rays(cfg, cams=tcams, width=256, height=256)
+    tcams = synth.random_sphere_cameras(1024, 1.0, seed=1000)
+    to, td, _ = synth.scene_rays(cfg, cams=tcams, width=64, height=64)
     to, td = torch.from_numpy(to).cuda(), torch.from_numpy(td).cuda()
     lab_out = r.render(to, td, out=r.alloc_outputs(len(to), labels=True))
     labels = torch.stack([lab_out["t_first"], lab_out["t_far"], lab_out["t_half"],
@@ -194,7 +194,7 @@ def bench_proposal(args):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_prop, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16",
         "data": "synthetic",
-        "config": {"workload": "tiny scene, proposal trained on 2^22 rays (64 cameras x 256^2), "
+        "config": {"workload": "tiny scene, proposal trained on 2^22 rays (1024 cameras x 64^2), "
                                "evaluated on 8 unseen 1920x1080 views; conf >= 0.9, margin 2 steps",
                    "rays_per_step": ne},
         "plain_fps": round(views / (ms_plain / 1e3), 3),

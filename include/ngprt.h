@@ -96,8 +96,8 @@ typedef struct ngprt_outputs {
   int32_t* n_samples;/* [n]    evaluated (occupied) samples */
   int32_t* n_reads;  /* [n]    occupancy/distance grid reads (marching points) */
   float* t_first;    /* [n]    t of the first evaluated sample (0 if none) */
-  float* t_far;      /* [n]    t of the sample after which T < 2e-3, the paper's own stopping
-                      *        threshold (the last sample's t if never; 0 if no sample) */
+  float* t_far;      /* [n]    t of the sample after which T < 1e-3 (the last sample's t if
+                      *        never; 0 if no sample): the proposal's far-end label */
   float* t_half;     /* [n]    t of the sample after which T < 0.5 (last sample's t if never) */
 } ngprt_outputs;
 
@@ -150,13 +150,11 @@ int ngprt_render(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins,
 
 /* Render with a per-ray sample-interval proposal (an extension; see
  * ngprt_proposal_infer).  dev_proposal: float32 [n][4] = t_near, t_far,
- * t_term, confidence.  Rays with confidence >= conf_threshold march only the
- * lattice points with t in [t_near - margin, t_far + margin]; when that
- * yields no sample (the interval misses the occupied space) the ray falls
- * back to the plain march.  Other rays march plainly.  dev_fallback: int32
- * [n] (NULL-able), 1 where the fallback ran.  An interval that holds all of a
- * ray's samples reproduces the plain render bit for bit; one that ends
- * earlier drops the tail samples. */
+ * t_term, confidence.  A ray whose confidence reaches conf_threshold stops
+ * marching after t_far + margin (same lattice, so its samples are the plain
+ * march's first ones); if it has no sample by then it carries on as the
+ * plain march (dev_fallback, int32 [n] NULL-able, marks those rays: their
+ * result is the plain render's bit for bit).  Other rays march plainly. */
 int ngprt_render_proposal(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins,
                           const float* dev_dirs, const float* dev_proposal, float conf_threshold,
                           float margin, const ngprt_outputs* out, int32_t* dev_fallback, void* stream);

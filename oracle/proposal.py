@@ -9,9 +9,10 @@ flattened: W1[64][48], b1[64], W2[64][64], b2[64], W3[4][64], b3[4]
 
 Labels come from the plain renderer's decided samples: t_near = t of the
 first evaluated sample; t_far = t of the sample after which the
-transmittance first drops below 2e-3 (the stopping threshold of the paper's
-own renderer, supplement "Real-time Rendering" item 2; the last sample's t if
-it never does); t_term = t of the sample after which the transmittance first
+transmittance first drops below 1e-3 (the last sample's t if it never does;
+the paper's own renderer stops at 2e-3, supplement "Real-time Rendering"
+item 2, and the workload at 1e-4: beyond 1e-3 a ray's remaining colour weight
+is below 0.1 %); t_term = t of the sample after which the transmittance first
 drops below 0.5 (the last sample's t if never); rays without samples are
 marked invalid.
 
@@ -140,7 +141,7 @@ def backward(p, fwd, g_out, bf16_operands=True):
     return np.concatenate([gW1.ravel(), gb1, gW2.ravel(), gb2, gW3.ravel(), gb3])
 
 
-T_FAR = np.float32(2e-3)
+T_FAR = np.float32(1e-3)
 T_TERM = np.float32(0.5)
 
 

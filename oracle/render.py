@@ -265,6 +265,7 @@ def march(inp: OracleInputs, o: np.ndarray, d: np.ndarray, naive: bool = False,
         margin = vox * F32(1.0 / 1024.0)
     t_lo = np.full(n, -np.inf, dtype=F32)
     t_hi = np.full(n, np.inf, dtype=F32)
+    stopped_hi = np.zeros(n, dtype=bool)
     if intervals is not None:
         iv = np.asarray(intervals, dtype=F32)
         use = ~np.isnan(iv[:, 0])
@@ -281,6 +282,8 @@ def march(inp: OracleInputs, o: np.ndarray, d: np.ndarray, naive: bool = False,
         ids = np.nonzero(alive)[0]
         if inp.domain == BOX:
             tk = t0[ids] + F32(k) * step
+            at_hi = (tk < t1[ids]) & (tk > t_hi[ids])
+            stopped_hi[ids[at_hi]] = True
             inside = (tk < t1[ids]) & ~(tk > t_hi[ids])
             alive[ids[~inside]] = False
             ids, tk = ids[inside], tk[inside]
@@ -293,6 +296,10 @@ def march(inp: OracleInputs, o: np.ndarray, d: np.ndarray, naive: bool = False,
                 need = k >= next_read[ids]
         else:
             tk = t[ids]
+            at_hi = tk > t_hi[ids]               # checked before the exit test
+            stopped_hi[ids[at_hi]] = True
+            alive[ids[at_hi]] = False
+            ids, tk = ids[~at_hi], tk[~at_hi]
             x = o[ids] + tk[:, None] * d[ids]
             r2 = (x[:, 0] * x[:, 0] + x[:, 1] * x[:, 1]) + x[:, 2] * x[:, 2]
             outer = r2 > F32(1.0)
@@ -309,7 +316,6 @@ def march(inp: OracleInputs, o: np.ndarray, d: np.ndarray, naive: bool = False,
             pos[outer] = s[outer, None] * x[outer]
             jn[outer] = jn_o[outer]
             gone = (outer & (inv_r < step) & (xd >= F32(0.0))) | ~np.isfinite(r2)
-            gone |= tk > t_hi[ids]
             alive[ids[gone]] = False
             keep = ~gone
             ids, tk, pos, jn = ids[keep], tk[keep], pos[keep], jn[keep]
@@ -376,7 +382,8 @@ def march(inp: OracleInputs, o: np.ndarray, d: np.ndarray, naive: bool = False,
         s_pos = np.zeros((0, 3), F32)
         s_T = np.zeros(0, F32)
     return dict(n_samples=nsamp.astype(np.int32), n_reads=nreads.astype(np.int32),
-                t_final32=T, s_ray=s_ray, s_k=s_k, s_t=s_t, s_pos=s_pos, s_T=s_T)
+                t_final32=T, s_ray=s_ray, s_k=s_k, s_t=s_t, s_pos=s_pos, s_T=s_T,
+                stopped_hi=stopped_hi)
 
 
 def mlp64(params: np.ndarray, x: np.ndarray, dims=(7, 16, 16, 3)) -> np.ndarray:
@@ -455,34 +462,34 @@ def valid_rays(inp: OracleInputs, o, d):
 
 
 def render_proposal(inp: OracleInputs, o, d, proposal, conf_threshold=0.9, margin=0.0):
-    """Render with a per-ray interval proposal [t_near, t_far, t_term, conf]:
-    confident rays march [t_near - margin, t_far + margin]; a confident ray
-    whose interval yields no sample is marched again plainly.  Returns the
-    result and the fallback mask."""
+    """Render with a per-ray proposal [t_near, t_far, t_term, conf]: a
+    confident ray ends its march after t_far + margin; one with no sample by
+    then carries on, which is exactly the plain march.  Returns the result
+    and the fallback mask."""
     o = np.asarray(o, F32)
     d = np.asarray(d, F32)
     n = len(o)
     prop = np.asarray(proposal, F32)
     conf = prop[:, 3] >= F32(conf_threshold)
     iv = np.full((n, 2), np.nan, F32)
-    iv[conf, 0] = prop[conf, 0] - F32(margin)
+    iv[conf, 0] = -np.inf
     iv[conf, 1] = prop[conf, 1] + F32(margin)
     m = march(inp, o, d, intervals=iv)
-    fb = conf & valid_rays(inp, o, d) & (m["n_samples"] == 0)
+    plain = march(inp, o, d)
+    # a confident ray stopped at its proposed end without a sample resumes
+    # there, which makes it the plain march
+    fb = conf & (m["n_samples"] == 0) & m["stopped_hi"]
     if fb.any():
         idx = np.nonzero(fb)[0]
-        m2 = march(inp, o[idx], d[idx])
-        # merge: fallback rays take the plain march's samples, reads add up
         keep = ~np.isin(m["s_ray"], idx)
+        take = np.isin(plain["s_ray"], idx)
         for key in ("s_ray", "s_k", "s_t", "s_pos", "s_T"):
-            extra = m2[key] if key != "s_ray" else idx[m2["s_ray"]]
-            m[key] = np.concatenate([m[key][keep], extra])
+            m[key] = np.concatenate([m[key][keep], plain[key][take]])
         order = np.lexsort((m["s_k"], m["s_ray"]))
         for key in ("s_ray", "s_k", "s_t", "s_pos", "s_T"):
             m[key] = m[key][order]
-        m["n_samples"][idx] = m2["n_samples"]
-        m["n_reads"][idx] += m2["n_reads"]
-        m["t_final32"][idx] = m2["t_final32"]
+        for key in ("n_samples", "n_reads", "t_final32"):
+            m[key][idx] = plain[key][idx]
     if len(m["s_ray"]):
         fz, _ = fused64(inp, grid_coords32(inp, m["s_pos"]).astype(np.float64))
     else:

@@ -27,7 +27,8 @@ struct MarchState {
   int next_read;      // box: first lattice index not known to be empty
   bool has_ball;      // contract: known-empty ball
   float bc[3], br2;
-  float t_lo, t_hi;   // optional interval: points with t < t_lo are not read, t > t_hi ends the ray
+  float t_hi;         // optional end: a lattice point with t > t_hi stops the march
+  bool stopped_at_hi; // the march ended at t_hi (and can be resumed)
   bool done;
 };
 
@@ -47,8 +48,8 @@ __device__ __forceinline__ void march_init(const SceneArgs& S, const float* o, c
   m.next_read = 0;
   m.has_ball = false;
   m.t = 0.0f;
-  m.t_lo = -__int_as_float(0x7F800000);
   m.t_hi = __int_as_float(0x7F800000);
+  m.stopped_at_hi = false;
   if (DOM == DOM_BOX) {
     const float lo = S.lo, hi = -S.lo;
     float t0 = 0.0f, t1 = __int_as_float(0x7F800000);
@@ -71,23 +72,6 @@ __device__ __forceinline__ void march_init(const SceneArgs& S, const float* o, c
     valid = valid && (m.dn2 > 0.0f);
   }
   m.done = !valid;
-}
-
-// Restrict the march to lattice points with t in [t_lo, t_hi] (same
-// lattice, so the samples inside the interval are the plain march's).
-// Box: start at lattice index max(0, floor((t_lo - t0) / step)).
-// Contract: lattice points before t_lo are stepped over without reads.
-template <int DOM>
-__device__ __forceinline__ void march_set_interval(const SceneArgs& S, MarchState& m, float t_lo,
-                                                   float t_hi) {
-  m.t_hi = t_hi;
-  if (DOM == DOM_BOX) {
-    const float kf = floorf((t_lo - m.t0) / S.step);
-    m.k = kf > 0.0f ? (kf < (float)kMaxLattice ? (int)kf : kMaxLattice) : 0;
-    m.next_read = m.k;
-  } else {
-    m.t_lo = t_lo;
-  }
 }
 
 // Grid-domain position -> grid coordinate u in [0,1]^3 and voxel index.
@@ -114,11 +98,13 @@ __device__ __forceinline__ bool march_next(const SceneArgs& S, MarchState& m, bo
     float tcur;
     if (DOM == DOM_BOX) {
       tcur = m.t0 + (float)m.k * S.step;
-      if (!(tcur < m.t1) || tcur > m.t_hi) { m.done = true; break; }
+      if (!(tcur < m.t1)) { m.done = true; break; }
+      if (tcur > m.t_hi) { m.done = true; m.stopped_at_hi = true; break; }
 #pragma unroll
       for (int a = 0; a < 3; ++a) p[a] = m.o[a] + tcur * m.d[a];
     } else {
       tcur = m.t;
+      if (tcur > m.t_hi) { m.done = true; m.stopped_at_hi = true; break; }
       float x[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) x[a] = m.o[a] + tcur * m.d[a];
@@ -142,8 +128,6 @@ __device__ __forceinline__ bool march_next(const SceneArgs& S, MarchState& m, bo
         for (int a = 0; a < 3; ++a) p[a] = x[a];
       }
       m.t = tcur + S.step / jn;
-      if (tcur > m.t_hi) { m.done = true; break; }
-      if (tcur < m.t_lo) { ++m.k; continue; }
     }
     const int kcur = m.k;
     bool need = true;

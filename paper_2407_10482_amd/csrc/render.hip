@@ -3,7 +3,8 @@
 //
 // One lane owns one ray; a wave owns 64 rays (an 8x8 pixel tile when the
 // caller orders rays tile-major, which keeps the coarse-level gathers of a
-// wave on shared cache lines).  Each iteration every live lane first marches
+// wave on shared cache lines; neighbouring rays also march alike, so the
+// wave's lanes finish within a sample or two of each other).  Each iteration every live lane first marches
 // to its next occupied lattice point (divergent but cheap: one 2-byte grid
 // read per marching point, none inside a known-empty region), then all lanes
 // holding a sample evaluate it together (the gather-heavy part runs with the
@@ -25,8 +26,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 enum { MODE_RENDER = 0, MODE_MARCH = 1, MODE_RENDER_EXT = 2 };
 
 // Optional per-ray sample-interval proposal: rays whose confidence reaches
-// conf_thr march only [t_near - margin, t_far + margin] of the same lattice
-// and fall back to the plain march when that interval yields no sample.
+// conf_thr end their march after t_far + margin (same lattice); a ray with
+// no sample by then carries on as the plain march.
 struct ProposalArgs {
   const float* prop;     // [n][4]: t_near, t_far, t_term, confidence (NULL: plain march)
   float conf_thr;
@@ -100,14 +101,16 @@ __device__ __forceinline__ void wave_mlp(const float* __restrict__ P, const floa
   }
 }
 
-// Occupancy target of the render kernel (waves per SIMD): the 16-level
-// kernels need ~170 VGPRs unconstrained (2 waves); asking for 3 costs a few
-// spilled registers.  The XCD remap can be disabled for measurements.
+// Occupancy floor of the render kernel (waves per SIMD; the 16-level kernels
+// fit 4 with ~126 VGPRs).  NGPRT_XCD_REMAP=1 gives each XCD a contiguous
+// range of ray tiles; measured on the 8-view 1080p workload it is slower
+// (56.4 -> 64.5 ms): with the default round-robin placement all XCDs work on
+// neighbouring tiles at once, and their L2 misses share Infinity Cache lines.
 #ifndef NGPRT_RENDER_WAVES_PER_EU
-#define NGPRT_RENDER_WAVES_PER_EU 3
+#define NGPRT_RENDER_WAVES_PER_EU 4
 #endif
 #ifndef NGPRT_XCD_REMAP
-#define NGPRT_XCD_REMAP 1
+#define NGPRT_XCD_REMAP 0
 #endif
 
 template <int DOM, int DT, int LMAX, int MODE>
@@ -119,9 +122,8 @@ render_kernel(SceneArgs S, int64_t n, const float* __restrict__ O,
   __shared__ float xin_all[4][8 * 64];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-  // contiguous range of ray tiles so neighbouring tiles share its L2.
 #if NGPRT_XCD_REMAP
+  // workgroups are dispatched round-robin over the 8 XCDs
   const unsigned G = gridDim.x, xcd = blockIdx.x % 8u, slot = blockIdx.x / 8u;
   const unsigned q8 = G / 8u, r8 = G % 8u;
   const unsigned block = xcd * q8 + (xcd < r8 ? xcd : r8) + slot;
@@ -141,13 +143,13 @@ render_kernel(SceneArgs S, int64_t n, const float* __restrict__ O,
   if (EXT && pa.prop && in_range && !m.done) {
     const float* q = pa.prop + 4 * ray;
     if (q[3] >= pa.conf_thr) {
-      march_set_interval<DOM>(S, m, q[0] - pa.margin, q[1] + pa.margin);
+      m.t_hi = q[1] + pa.margin;
       proposed = true;
     }
   }
   float T = 1.0f, cd[3] = {0.f, 0.f, 0.f}, fv[4] = {0.f, 0.f, 0.f, 0.f}, depth = 0.0f;
   // labels: t of the first sample, of the sample after which T < 0.5, and of
-  // the sample after which T < 2e-3 (the paper's own stopping threshold)
+  // the sample after which T < 1e-3 (the proposal's far end)
   float t_first = 0.0f, t_last = 0.0f, t_half = 0.0f, t_far = 0.0f;
   bool half_set = false, far_set = false;
   int ns = 0, reads = 0;
@@ -156,9 +158,11 @@ render_kernel(SceneArgs S, int64_t n, const float* __restrict__ O,
     float u[3], ts;
     int ks;
     bool have = march_next<DOM>(S, m, naive != 0, reads, u, ts, ks);
-    if (EXT && !have && proposed && !fell_back && ns == 0) {
-      // the proposed interval held no occupied lattice point: plain march
-      march_init<DOM>(S, oray, dray, in_range, m);
+    if (EXT && !have && proposed && !fell_back && ns == 0 && m.stopped_at_hi) {
+      // nothing sampled before the proposed end: carry on as the plain march
+      m.t_hi = __int_as_float(0x7F800000);
+      m.done = false;
+      m.stopped_at_hi = false;
       fell_back = true;
       have = march_next<DOM>(S, m, naive != 0, reads, u, ts, ks);
     }
@@ -181,7 +185,7 @@ render_kernel(SceneArgs S, int64_t n, const float* __restrict__ O,
         if (ns == 0) t_first = ts;
         t_last = ts;
         if (!half_set && T < 0.5f) { t_half = ts; half_set = true; }
-        if (!far_set && T < 2e-3f) { t_far = ts; far_set = true; }
+        if (!far_set && T < 1e-3f) { t_far = ts; far_set = true; }
       }
       ++ns;
       if (T < S.thr || ns >= S.max_samples) m.done = true;

@@ -65,12 +65,12 @@ def test_proposal_gradient_matches_finite_differences():
 def test_labels_from_decided_samples():
     s_ray = np.array([0, 0, 0, 2, 2])
     s_t = np.array([0.1, 0.2, 0.3, 1.0, 1.5], F32)
-    s_T = np.array([0.9, 0.4, 0.001, 0.8, 0.7], F32)
+    s_T = np.array([0.9, 0.4, 0.0005, 0.8, 0.7], F32)
     lab, valid = P.labels_from_march(3, s_ray, s_t, s_T)
     assert valid.tolist() == [True, False, True]
-    # ray 0: T < 0.5 after the 2nd sample, < 2e-3 after the 3rd
+    # ray 0: T < 0.5 after the 2nd sample, < 1e-3 after the 3rd
     assert np.allclose(lab[0], [0.1, 0.3, 0.2, 1]) and np.allclose(lab[2], [1.0, 1.5, 1.5, 1])
-    s_T2 = np.array([0.001, 0.0005, 0.0001, 0.8, 0.7], F32)
+    s_T2 = np.array([0.0009, 0.0005, 0.0001, 0.8, 0.7], F32)
     lab2, _ = P.labels_from_march(3, s_ray, s_t, s_T2)
     assert np.allclose(lab2[0], [0.1, 0.1, 0.1, 1])
     assert np.all(lab[1] == 0)
@@ -95,19 +95,19 @@ def test_interval_march_with_exact_labels_equals_plain():
     assert np.array_equal(res.s_k, ref.s_k) and np.array_equal(res.n_samples, ref.n_samples)
     assert np.array_equal(res.rgb, ref.rgb) and not fb.any()
     assert (res.n_reads <= ref.n_reads).all()
-    # an interval that misses everything falls back to the plain march
+    # an end before any sample: the ray resumes, and is the plain march
     bad = prop.copy()
-    bad[:, 0] = 50.0
-    bad[:, 1] = 51.0
+    bad[:, 1] = -1.0
     bad[:, 3] = 1.0
     res2, fb2 = render_proposal(inp, o, d, bad, 0.9, 0.0)
     assert fb2[ref.n_samples > 0].all()
     assert np.array_equal(res2.s_k, ref.s_k) and np.array_equal(res2.rgb, ref.rgb)
-    # ending the interval where T first drops below 2e-3 drops the tail
-    # samples, which carry at most 2e-3 of the colour weight
+    assert np.array_equal(res2.n_reads, ref.n_reads)
+    # ending where T first drops below 1e-3 drops the tail samples, which
+    # carry at most 1e-3 of the colour weight
     cut = prop.copy()
     cut[:, 1] = lab[:, 1]
     res3, _ = render_proposal(inp, o, d, cut, 0.9, 0.0)
     assert (res3.n_samples <= ref.n_samples).all() and (res3.n_samples < ref.n_samples).any()
-    assert np.abs(res3.c_d - ref.c_d).max() <= 2.1e-3 * np.abs(ref.c_d).max() + 1e-12
-    assert np.all((res3.t_final <= 2e-3 + 1e-9) | (res3.n_samples == ref.n_samples))
+    assert np.abs(res3.c_d - ref.c_d).max() <= 1.05e-3 * np.abs(ref.c_d).max() + 1e-12
+    assert np.all((res3.t_final <= 1e-3 + 1e-9) | (res3.n_samples == ref.n_samples))
