@@ -234,10 +234,10 @@ __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, c
         if (l >= S.L) break;
         Corners c;
         level_corners(u, S.N[l], S.Nf[l], S.mask, c);
-        const size_t base = size_t(l) << S.log2T;
+        const void* fb = feat_level<DT_F32>(S.feat, l, S.log2T);
         float v[8][8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) Store<DT_F32>::feat(S.feat, base + c.idx[k], v[k]);
+        for (int k = 0; k < 8; ++k) Store<DT_F32>::feat(fb, c.idx[k], v[k]);
         float gw = 0.0f;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {

@@ -61,12 +61,15 @@ __device__ __forceinline__ uint32_t hash3(uint32_t x, uint32_t y, uint32_t z, ui
 
 template <int DT> struct Store;
 
+// Accessors take the level's uniform base pointer and a 32-bit entry index,
+// so a gather is one global load with a scalar base and a 32-bit offset.
 template <> struct Store<DT_F32> {
-  __device__ static __forceinline__ float logit(const void* p, size_t i) {
-    return reinterpret_cast<const float*>(p)[i];
+  static constexpr int kRow = 32;
+  __device__ static __forceinline__ float logit(const void* lbase, uint32_t i) {
+    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(lbase) + (i << 2));
   }
-  __device__ static __forceinline__ void feat(const void* p, size_t i, float v[8]) {
-    const float4* q = reinterpret_cast<const float4*>(p) + 2 * i;
+  __device__ static __forceinline__ void feat(const void* lbase, uint32_t i, float v[8]) {
+    const float4* q = reinterpret_cast<const float4*>(reinterpret_cast<const char*>(lbase) + (i << 5));
     float4 a = q[0], b = q[1];
     v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
     v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
@@ -74,11 +77,14 @@ template <> struct Store<DT_F32> {
 };
 
 template <> struct Store<DT_BF16> {
-  __device__ static __forceinline__ float logit(const void* p, size_t i) {
-    return __uint_as_float(uint32_t(reinterpret_cast<const uint16_t*>(p)[i]) << 16);
+  static constexpr int kRow = 16;
+  __device__ static __forceinline__ float logit(const void* lbase, uint32_t i) {
+    return __uint_as_float(uint32_t(*reinterpret_cast<const uint16_t*>(
+                               reinterpret_cast<const char*>(lbase) + (i << 1)))
+                           << 16);
   }
-  __device__ static __forceinline__ void feat(const void* p, size_t i, float v[8]) {
-    uint4 w = reinterpret_cast<const uint4*>(p)[i];
+  __device__ static __forceinline__ void feat(const void* lbase, uint32_t i, float v[8]) {
+    uint4 w = *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(lbase) + (i << 4));
     v[0] = __uint_as_float(w.x << 16); v[1] = __uint_as_float(w.x & 0xFFFF0000u);
     v[2] = __uint_as_float(w.y << 16); v[3] = __uint_as_float(w.y & 0xFFFF0000u);
     v[4] = __uint_as_float(w.z << 16); v[5] = __uint_as_float(w.z & 0xFFFF0000u);
@@ -96,17 +102,28 @@ __device__ __forceinline__ fp8pair fp8x2_decode(uint32_t w, bool hi) {
 }
 
 template <> struct Store<DT_FP8> {
-  __device__ static __forceinline__ float logit(const void* p, size_t i) {
-    return fp8x2_decode(reinterpret_cast<const uint8_t*>(p)[i], false)[0];
+  static constexpr int kRow = 8;
+  __device__ static __forceinline__ float logit(const void* lbase, uint32_t i) {
+    return fp8x2_decode(*(reinterpret_cast<const uint8_t*>(lbase) + i), false)[0];
   }
-  __device__ static __forceinline__ void feat(const void* p, size_t i, float v[8]) {
-    uint2 w = reinterpret_cast<const uint2*>(p)[i];
+  __device__ static __forceinline__ void feat(const void* lbase, uint32_t i, float v[8]) {
+    uint2 w = *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(lbase) + (i << 3));
     fp8pair a = fp8x2_decode(w.x, false), b = fp8x2_decode(w.x, true);
     fp8pair c = fp8x2_decode(w.y, false), d = fp8x2_decode(w.y, true);
     v[0] = a[0]; v[1] = a[1]; v[2] = b[0]; v[3] = b[1];
     v[4] = c[0]; v[5] = c[1]; v[6] = d[0]; v[7] = d[1];
   }
 };
+
+// level base pointers of the feature and logit arrays
+template <int DT>
+__device__ __forceinline__ const void* feat_level(const void* feat, int l, int log2T) {
+  return reinterpret_cast<const char*>(feat) + ((size_t(l) << log2T) * Store<DT>::kRow);
+}
+template <int DT>
+__device__ __forceinline__ const void* logit_level(const void* logit, int l, int log2T) {
+  return reinterpret_cast<const char*>(logit) + ((size_t(l) << log2T) * (Store<DT>::kRow / 8));
+}
 
 // ---------------------------------------------------------------------------
 // One hash level at grid coordinate u: corner indices and trilinear weights.
@@ -146,17 +163,24 @@ __device__ __forceinline__ void level_corners(const float u[3], int N, float Nf,
 // The density channel and S are on the decision chain (plain float32 ops);
 // the colour and specular channels use fma.  Optionally the attention
 // weights e_l / S [L] and corner indices [L][8].
+#ifndef NGPRT_LEVEL_UNROLL
+#define NGPRT_LEVEL_UNROLL 2
+#endif
+
 template <int DT, int LMAX, bool DEBUG = false>
 __device__ __forceinline__ void eval_fused(const SceneArgs& S, const float u[3], float fused[8],
                                            float* wout = nullptr, int32_t* idxout = nullptr) {
   float esum = 0.0f, num0 = 0.0f;
   float num[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
+  // a rolled level loop: per-level constants come in by scalar loads instead
+  // of being held in (and spilled from) scalar registers across the march
+#pragma unroll NGPRT_LEVEL_UNROLL
   for (int l = 0; l < LMAX; ++l) {
     if (l < S.L) {
       Corners c;
       level_corners(u, S.N[l], S.Nf[l], S.mask, c);
-      const size_t base = size_t(l) << S.log2T;
+      const void* fb = feat_level<DT>(S.feat, l, S.log2T);
+      const void* lb = logit_level<DT>(S.logit, l, S.log2T);
       float acc[9];
 #pragma unroll
       for (int j = 0; j < 9; ++j) acc[j] = 0.0f;
@@ -167,8 +191,8 @@ __device__ __forceinline__ void eval_fused(const SceneArgs& S, const float u[3],
         float v[4][8], lg[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          Store<DT>::feat(S.feat, base + c.idx[4 * g + k], v[k]);
-          lg[k] = Store<DT>::logit(S.logit, base + c.idx[4 * g + k]);
+          Store<DT>::feat(fb, c.idx[4 * g + k], v[k]);
+          lg[k] = Store<DT>::logit(lb, c.idx[4 * g + k]);
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {

@@ -105,8 +105,9 @@ __global__ void logit_max_kernel(const void* __restrict__ logit, int64_t T, Scal
   if (threadIdx.x == 0) part = 0;
   __syncthreads();
   if (i < T) {
-    const size_t e = size_t(l) * size_t(T) + size_t(i);
-    float v = Store<DT>::logit(logit, e);
+    float v = Store<DT>::logit(reinterpret_cast<const char*>(logit) +
+                                   (size_t(l) * size_t(T) + size_t(i)) * (Store<DT>::kRow / 8),
+                               0);
     if (DT == DT_FP8) v = sc.s[l][8] * v;
     if (v == v) atomicMax(&part, order_key(v));
   }
