@@ -117,6 +117,9 @@ def bench_train(args):
     }
 
 
+CONF = 0.99      # proposal confidence needed to stop a ray at its predicted far end
+
+
 def bench_proposal(args):
     """Train the proposal network on 2^22 labelled rays (1024 cameras x 64^2
     of the tiny scene, labels from the plain renderer), then render 8 unseen
@@ -144,11 +147,11 @@ def bench_proposal(args):
     bs = 1 << 14
     g = torch.Generator(device="cuda").manual_seed(0)
     t0 = time.time()
-    margin = 2.0 * cfg.step
+    margin = 4.0 * cfg.step
     loss = torch.zeros((1,), dtype=torch.float32, device="cuda")
     history = []
     for ep in range(args.prop_epochs):
-        phase = 1 if ep < (2 * args.prop_epochs) // 3 else 2
+        phase = 1 if ep < args.prop_epochs // 2 else 2
         lr = 3e-3 if phase == 1 else 1e-3
         perm = torch.randperm(n, generator=g, device="cuda")
         loss.zero_()
@@ -166,7 +169,7 @@ def bench_proposal(args):
     ne = len(eo)
     plain = r.render(eo, ed)
     prop = net.infer(eo, ed)
-    withp = r.render_proposal(eo, ed, prop, 0.9, margin)
+    withp = r.render_proposal(eo, ed, prop, CONF, margin)
     torch.cuda.synchronize()
     mse = torch.mean((withp["rgb"] - plain["rgb"]) ** 2).item()
     psnr = float("inf") if mse == 0 else 10 * np.log10(1.0 / mse)
@@ -185,7 +188,7 @@ def bench_proposal(args):
         return s0.elapsed_time(s1) / args.steps
 
     ms_plain = timed(lambda outp: r.render(eo, ed, out=outp))
-    ms_prop = timed(lambda outp: r.render_proposal(eo, ed, net.infer(eo, ed), 0.9, margin, out=outp))
+    ms_prop = timed(lambda outp: r.render_proposal(eo, ed, net.infer(eo, ed), CONF, margin, out=outp))
     views = 8
     return {
         "metric": "1080p frames/s, learned proposal vs plain distance-grid marching",
@@ -195,7 +198,7 @@ def bench_proposal(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16",
         "data": "synthetic",
         "config": {"workload": "tiny scene, proposal trained on 2^22 rays (1024 cameras x 64^2), "
-                               "evaluated on 8 unseen 1920x1080 views; conf >= 0.9, margin 2 steps",
+                               "evaluated on 8 unseen 1920x1080 views; conf >= 0.99, margin 4 steps",
                    "rays_per_step": ne},
         "plain_fps": round(views / (ms_plain / 1e3), 3),
         "plain_ms": round(ms_plain, 4),
@@ -205,7 +208,7 @@ def bench_proposal(args):
         "reads_per_ray": {"plain": round(plain["n_reads"].float().mean().item(), 3),
                           "proposal": round(withp["n_reads"].float().mean().item(), 3)},
         "fallback_fraction": round(withp["fallback"].float().mean().item(), 4),
-        "confident_fraction": round((prop[:, 3] >= 0.9).float().mean().item(), 4),
+        "confident_fraction": round((prop[:, 3] >= CONF).float().mean().item(), 4),
         "psnr_proposal_vs_plain_db": round(psnr, 3),
         "train_seconds": round(train_s, 1),
         "train_loss_per_epoch": history,

@@ -13,7 +13,9 @@
 //          P_i the running sum of w_j s_j; then the softmax adjoint
 //          dL/da_l = w_l (dL/df . v_l - dL/df . f) and the trilinear scatter of
 //          every level's 9-channel gradient into its 8 corner entries with
-//          hardware float atomics (order-nondeterministic sums).
+//          hardware float atomics (order-nondeterministic sums).  On coarse
+//          levels, whose cells neighbouring rays share, the wave first sums
+//          the contributions to equal entries so one lane issues the atomics.
 // A second kernel reduces the per-wave MLP partials in a fixed order.
 #include <hip/hip_runtime.h>
 
@@ -28,6 +30,12 @@ namespace ngprt {
 typedef float bf32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kPad = 17;   // LDS row pitch of the per-wave staging (bank spread)
+// levels up to this resolution merge equal entries across the wave before
+// their atomics (their cells are shared by neighbouring rays' samples)
+#ifndef NGPRT_MERGE_RES
+#define NGPRT_MERGE_RES 64
+#endif
+constexpr int kMergeRes = NGPRT_MERGE_RES;
 
 // D[i][j] = sum over the wave's 64 rays r of A_r[i] * B_r[j] (i, j < 16).
 // sA, sB: [64][kPad].  Lane l returns D[4*(l/16) + q][l%16], q = 0..3.
@@ -200,18 +208,22 @@ __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, c
   }
 
   // ---------------- pass 2: re-march and scatter
+  // Every lane takes part in each iteration (lanes without a sample carry a
+  // zero gradient) so that coarse levels can merge equal table entries across
+  // the wave before the atomics.
   march_init<DOM>(S, o, d, in_range, m);
   T = 1.0f;
   ns = 0;
   float Pc = 0.0f;
   const size_t T_entries = size_t(1) << S.log2T;
   for (;;) {
-    float u[3], ts;
+    float u[3] = {0.f, 0.f, 0.f}, ts;
     int ks;
-    bool have = march_next<DOM>(S, m, false, reads, u, ts, ks);
+    const bool have = march_next<DOM>(S, m, false, reads, u, ts, ks);
     if (__ballot(have) == 0) break;
+    float gf[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, wl[LMAX], gff = 0.0f;
     if (have) {
-      float f[8], wl[LMAX];
+      float f[8];
       int32_t idx_unused[LMAX * 8];
       eval_fused<DT_F32, LMAX, true>(S, u, f, wl, idx_unused);
       const float sigma = exp32(f[0]);
@@ -222,18 +234,27 @@ __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, c
       Pc = __builtin_fmaf(w, s, Pc);
       const float Tn = T * e;
       const float gsig = S.step * (Tn * s - (Stot - Pc));
-      float gf[8];
       gf[0] = sigma * gsig;
       for (int j = 0; j < 3; ++j) gf[1 + j] = w * gcd[j];
       for (int j = 0; j < 4; ++j) gf[4 + j] = w * gfv[j];
-      float gff = 0.0f;
 #pragma unroll
       for (int j = 0; j < 8; ++j) gff = __builtin_fmaf(gf[j], f[j], gff);
+      T = Tn;
+      ++ns;
+      if (T < S.thr || ns >= S.max_samples) m.done = true;
+    } else {
 #pragma unroll
-      for (int l = 0; l < LMAX; ++l) {
-        if (l >= S.L) break;
-        Corners c;
-        level_corners(u, S.N[l], S.Nf[l], S.mask, c);
+      for (int l = 0; l < LMAX; ++l) wl[l] = 0.0f;
+    }
+#pragma unroll
+    for (int l = 0; l < LMAX; ++l) {
+      if (l >= S.L) break;
+      Corners c;
+      level_corners(u, S.N[l], S.Nf[l], S.mask, c);
+      float gv[9];
+#pragma unroll
+      for (int j = 0; j < 9; ++j) gv[j] = 0.0f;
+      if (have) {
         const void* fb = feat_level<DT_F32>(S.feat, l, S.log2T);
         float v[8][8];
 #pragma unroll
@@ -246,12 +267,40 @@ __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, c
           for (int k = 0; k < 8; ++k) acc = __builtin_fmaf(c.w[k], v[k][j], acc);
           gw = __builtin_fmaf(gf[j], acc, gw);
         }
-        const float ga = wl[l] * (gw - gff);
-        float gv[9];
 #pragma unroll
         for (int j = 0; j < 8; ++j) gv[j] = wl[l] * gf[j];
-        gv[8] = ga;
-        float* gbase = gtab + (size_t(l) * T_entries) * 9;
+        gv[8] = wl[l] * (gw - gff);
+      }
+      float* gbase = gtab + (size_t(l) * T_entries) * 9;
+      if (S.N[l] <= kMergeRes) {
+        // coarse level: neighbouring rays' samples share cells; sum equal
+        // entries over the wave, one lane issues the atomics
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          bool pending = have;
+          uint64_t pm = __ballot(pending);
+          while (pm) {
+            const int leader = __ffsll((unsigned long long)pm) - 1;
+            const uint32_t key = __shfl(c.idx[k], leader, 64);
+            const bool mine = pending && c.idx[k] == key;
+            float x[9];
+#pragma unroll
+            for (int j = 0; j < 9; ++j) x[j] = mine ? c.w[k] * gv[j] : 0.0f;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+              for (int j = 0; j < 9; ++j) x[j] += __shfl_xor(x[j], off, 64);
+            }
+            if (lane == leader) {
+              float* dst = gbase + size_t(key) * 9;
+#pragma unroll
+              for (int j = 0; j < 9; ++j) unsafeAtomicAdd(dst + j, x[j]);
+            }
+            pending = pending && !mine;
+            pm = __ballot(pending);
+          }
+        }
+      } else if (have) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
           float* dst = gbase + size_t(c.idx[k]) * 9;
@@ -259,9 +308,6 @@ __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, c
           for (int j = 0; j < 9; ++j) unsafeAtomicAdd(dst + j, c.w[k] * gv[j]);
         }
       }
-      T = Tn;
-      ++ns;
-      if (T < S.thr || ns >= S.max_samples) m.done = true;
     }
   }
 }

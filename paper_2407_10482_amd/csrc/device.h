@@ -164,7 +164,7 @@ __device__ __forceinline__ void level_corners(const float u[3], int N, float Nf,
 // the colour and specular channels use fma.  Optionally the attention
 // weights e_l / S [L] and corner indices [L][8].
 #ifndef NGPRT_LEVEL_UNROLL
-#define NGPRT_LEVEL_UNROLL 2
+#define NGPRT_LEVEL_UNROLL 1
 #endif
 
 template <int DT, int LMAX, bool DEBUG = false>
