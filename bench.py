@@ -24,6 +24,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# sources whose change invalidates hardware counters taken on the render kernel
+KERNEL_SOURCES = ["paper_2407_10482_amd/csrc/" + f for f in
+                  ("render.hip", "device.h", "march.h", "internal.h")] + ["paper_2407_10482_amd/build.py"]
 BYTES_PER_ENTRY = {0: 36, 1: 18, 2: 9}     # 8 feature channels + 1 logit per entry
 DTYPE_NAME = {0: "f32", 1: "bf16", 2: "fp8"}
 
@@ -39,6 +42,8 @@ def parse():
     p.add_argument("--views", type=int, default=8)
     p.add_argument("--copy-probe-mb", type=int, default=0,
                    help="run one device copy of this many MiB first (hardware-counter calibration)")
+    p.add_argument("--probe-points", type=int, default=1 << 24,
+                   help="points of the random-gather ceiling probe (0 skips it)")
     p.add_argument("--mode", choices=["render", "train", "proposal"], default="render",
                    help="render: the headline; train: forward+backward+Adam steps; "
                         "proposal: learned sample-interval proposal vs plain marching")
@@ -243,6 +248,50 @@ def cpu_baseline(sc, dist, o, d, dtype, seconds):
     }
 
 
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(dtype_name: str):
+    """HBM bytes per render launch from the committed counter summary, or None
+    when it is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"render_kernel_hd_{dtype_name}_counters.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel sources sha256/16") != kernel_source_hash():
+        return None
+    try:
+        return int(vals["HBM bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def gather_probe(r, n_points: int, reps: int, pairs: bool) -> float:
+    """Requested-gather GB/s of the random-gather probe (mean over reps)."""
+    import torch
+    buf = torch.empty((n_points,), dtype=torch.float32, device="cuda")
+    r.gather_probe(n_points, seed=99, pairs=pairs, out=buf)
+    a, b = _events()
+    a.record()
+    for i in range(reps):
+        r.gather_probe(n_points, seed=i, pairs=pairs, out=buf)
+    b.record()
+    torch.cuda.synchronize()
+    s = a.elapsed_time(b) / reps / 1e3
+    return n_points * r.L * 8 * BYTES_PER_ENTRY[r.table_dtype] / s / 1e9
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -293,20 +342,27 @@ def main():
     for _ in range(args.warmup):
         r.render(go, gd, out=out)
     torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    start.record()
-    for _ in range(args.steps):
+    # events on the stream the render kernel is launched on (torch's current
+    # stream): one pair around the whole timed region, one per step
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    ev[0].record()
+    for i in range(args.steps):
         r.render(go, gd, out=out)
-    end.record()
+        ev[i + 1].record()
     torch.cuda.synchronize()
-    ms = start.elapsed_time(end) / args.steps
+    ms = ev[0].elapsed_time(ev[-1]) / args.steps
+    per_step = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
+    probe = {}
+    if args.probe_points > 0:
+        for pairs in (False, True):
+            probe["pairs" if pairs else "uniform"] = round(gather_probe(r, args.probe_points, 5, pairs), 1)
     views = len(cams)
     fps = views / (ms / 1e3)
     L = cfg.n_levels
     gather = n_samples * L * 8 * BYTES_PER_ENTRY[dtype]
     alg_bytes = gather + 2 * n_reads + n * (24 + 12)
     achieved = alg_bytes / (ms / 1e3) / 1e9
+    traffic = committed_traffic(DTYPE_NAME[dtype])
     res = {
         "metric": "1080p frames/s (plain distance-grid marching)",
         "value": round(fps, 3),
@@ -327,7 +383,10 @@ def main():
             "rays_per_step": n,
             "views": views,
         },
+        "ms_median": round(float(np.median(per_step)), 4),
+        "ms_p90": round(float(np.percentile(per_step, 90)), 4),
         "msamples_per_s": round(n_samples / (ms / 1e3) / 1e6, 1),
+        "mreads_per_s": round(n_reads / (ms / 1e3) / 1e6, 1),
         "samples_per_ray": round(n_samples / n, 3),
         "reads_per_ray": round(n_reads / n, 3),
         "roofline": {
@@ -337,8 +396,15 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": traffic,
             "algorithmic_bytes_per_launch": alg_bytes,
+            "requested_gather_gbs_per_level": round(gather / L / (ms / 1e3) / 1e9, 1),
+            "hbm_gbs_measured": None if traffic is None else round(traffic / (ms / 1e3) / 1e9, 1),
+            "hbm_frac_measured": None if traffic is None else round(traffic / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "gather_probe_gbs": probe or None,
+            "frac_of_gather_probe": (round(gather / (ms / 1e3) / 1e9 / probe["pairs"], 4)
+                                     if probe else None),
+            "kernel_sources": kernel_source_hash(),
         },
     }
     if args.cpu_seconds > 0:

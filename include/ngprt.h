@@ -167,6 +167,19 @@ int ngprt_render_proposal(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origi
 int ngprt_debug_eval_points(ngprt_ctx* ctx, int64_t n, const float* dev_pos, int32_t* dev_idx,
                             float* dev_fused, float* dev_weights, void* stream);
 
+/* Gather ceiling probe (measurement aid, not on the render path).  For each
+ * of n_points pseudo-random "samples" (stream `seed`), gathers, per level of
+ * the loaded tables, 8 feature rows + logits at random entries of that level
+ * (pairs = 0: all independent; pairs = 1: 4 random entries e and their
+ * neighbours e ^ 1, the placement of a cell's two x-adjacent corners under
+ * the spatial hash of the multiresolution hash encoding, Sec. 3 of the
+ * paper, when the cell's x index is even), dequantises them like the render
+ * path and writes their float32 sum to dev_out [n_points].  Requested bytes
+ * per point equal a render sample's: L * 8 * (row + logit) bytes.  Tables
+ * must be loaded; NULL dev_out or pairs outside {0, 1} -> INVALID_ARG. */
+int ngprt_gather_probe(ngprt_ctx* ctx, int64_t n_points, uint32_t seed, int32_t pairs, float* dev_out,
+                       void* stream);
+
 /* March only (no MLP): per ray, the lattice indices of the first `cap`
  * evaluated samples (dev_sample_k int32 [n][cap], -1 padded), the sample
  * count and the grid-read count.  naive != 0 reads every lattice point

@@ -56,6 +56,7 @@ SIGNATURES = [
     ("ngprt_load_mlp", ctypes.c_int, [_P, _P, _P]),
     ("ngprt_render", ctypes.c_int, [_P, _I64, _P, _P, ctypes.POINTER(NgprtOutputs), _P]),
     ("ngprt_debug_eval_points", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P]),
+    ("ngprt_gather_probe", ctypes.c_int, [_P, _I64, ctypes.c_uint32, _I32, _P, _P]),
     ("ngprt_debug_march", ctypes.c_int, [_P, _I64, _P, _P, _I32, _P, _P, _P, _I32, _P]),
     ("ngprt_render_proposal", ctypes.c_int, [_P, _I64, _P, _P, _P, ctypes.c_float, ctypes.c_float,
                                              ctypes.POINTER(NgprtOutputs), _P, _P]),

@@ -247,6 +247,17 @@ int ngprt_debug_eval_points(ngprt_ctx* ctx, int64_t n, const float* dev_pos, int
   return launch_eval_points(ctx, n, dev_pos, dev_idx, dev_fused, dev_weights, (hipStream_t)stream);
 }
 
+int ngprt_gather_probe(ngprt_ctx* ctx, int64_t n_points, uint32_t seed, int32_t pairs, float* dev_out,
+                       void* stream) {
+  if (!ctx) return NGPRT_E_INVALID_ARG;
+  if (n_points < 0) return fail(ctx, NGPRT_E_INVALID_ARG, "n_points < 0");
+  if (n_points == 0) return NGPRT_OK;
+  if (!dev_out) return fail(ctx, NGPRT_E_INVALID_ARG, "dev_out is NULL");
+  if (pairs != 0 && pairs != 1) return fail(ctx, NGPRT_E_INVALID_ARG, "pairs must be 0 or 1");
+  if (!ctx->tables_loaded) return fail(ctx, NGPRT_E_NOT_LOADED, "tables not loaded");
+  return launch_gather_probe(ctx, n_points, seed, pairs, dev_out, (hipStream_t)stream);
+}
+
 int ngprt_debug_march(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins, const float* dev_dirs,
                       int32_t cap, int32_t* dev_sample_k, int32_t* dev_n_samples, int32_t* dev_n_reads,
                       int32_t naive, void* stream) {

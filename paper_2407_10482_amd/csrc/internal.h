@@ -94,6 +94,7 @@ int launch_march(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, int3
                  int32_t* sk, int32_t* ns, int32_t* nr, int naive, hipStream_t s);
 int launch_backward(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const float* grad_rgb,
                     float* gtab, float* gmlp, hipStream_t s);
+int launch_gather_probe(ngprt_ctx* ctx, int64_t n, uint32_t seed, int pairs, float* out, hipStream_t s);
 int launch_adam(int64_t n, float* p, const float* g, float* m, float* v, int32_t step, float lr,
                 float b1, float b2, float eps, hipStream_t s);
 int launch_prop_infer(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const float* P,

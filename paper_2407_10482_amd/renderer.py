@@ -164,6 +164,15 @@ class Renderer:
                                                _stream()), self.ctx)
         return idx, fused, w
 
+    def gather_probe(self, n_points: int, seed: int = 0, pairs: bool = False, out: torch.Tensor = None):
+        """Random-gather ceiling probe over the loaded tables (measurement aid)."""
+        if out is None:
+            out = torch.empty((n_points,), dtype=torch.float32, device="cuda")
+        _dev(out, torch.float32, (n_points,), "out")
+        check(self.lib.ngprt_gather_probe(self.ctx, n_points, seed & 0xFFFFFFFF, int(bool(pairs)), _ptr(out),
+                                          _stream()), self.ctx)
+        return out
+
     def march(self, origins: torch.Tensor, dirs: torch.Tensor, cap: int = 64, naive: bool = False):
         n = origins.shape[0]
         _dev(origins, torch.float32, (n, 3), "origins")
