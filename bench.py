@@ -40,6 +40,8 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="approximate CPU time for the oracle baseline (0 skips it)")
     p.add_argument("--views", type=int, default=8)
+    p.add_argument("--group", type=int, default=1,
+                   help="ray order: 8x8-pixel tiles taken in blocks of group x group tiles")
     p.add_argument("--copy-probe-mb", type=int, default=0,
                    help="run one device copy of this many MiB first (hardware-counter calibration)")
     p.add_argument("--probe-points", type=int, default=1 << 24,
@@ -194,6 +196,9 @@ def bench_proposal(args):
 
     ms_plain = timed(lambda outp: r.render(eo, ed, out=outp))
     ms_prop = timed(lambda outp: r.render_proposal(eo, ed, net.infer(eo, ed), CONF, margin, out=outp))
+    pbuf = torch.empty((ne, 4), dtype=torch.float32, device="cuda")
+    ms_infer = timed(lambda outp: net.infer(eo, ed, out=pbuf))
+    ms_render_only = timed(lambda outp: r.render_proposal(eo, ed, prop, CONF, margin, out=outp))
     views = 8
     return {
         "metric": "1080p frames/s, learned proposal vs plain distance-grid marching",
@@ -208,6 +213,8 @@ def bench_proposal(args):
         "plain_fps": round(views / (ms_plain / 1e3), 3),
         "plain_ms": round(ms_plain, 4),
         "speedup": round(ms_plain / ms_prop, 4),
+        "ms_infer": round(ms_infer, 4),
+        "ms_render_with_proposal": round(ms_render_only, 4),
         "samples_per_ray": {"plain": round(plain["n_samples"].float().mean().item(), 3),
                             "proposal": round(withp["n_samples"].float().mean().item(), 3)},
         "reads_per_ray": {"plain": round(plain["n_reads"].float().mean().item(), 3),
@@ -314,7 +321,7 @@ def main():
     t0 = time.time()
     sc = synth.make_scene(cfg)
     cams = synth.camera_positions(cfg)[: args.views]
-    o, d, _ = synth.scene_rays(cfg, cams=cams)
+    o, d, _ = synth.scene_rays(cfg, cams=cams, group=args.group)
     print(f"# scene + rays generated in {time.time() - t0:.1f} s ({len(o)} rays)", file=sys.stderr,
           flush=True)
     torch.cuda.set_device(0)

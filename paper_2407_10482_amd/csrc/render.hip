@@ -102,15 +102,14 @@ __device__ __forceinline__ void wave_mlp(const float* __restrict__ P, const floa
 }
 
 // Occupancy floor of the render kernel (waves per SIMD; the 16-level kernels
-// fit 4 with ~126 VGPRs).  NGPRT_XCD_REMAP=1 gives each XCD a contiguous
-// range of ray tiles; measured on the 8-view 1080p workload it is slower
-// (56.4 -> 64.5 ms): with the default round-robin placement all XCDs work on
-// neighbouring tiles at once, and their L2 misses share Infinity Cache lines.
+// fit 4 with ~126 VGPRs).  Giving each XCD one contiguous eighth of the rays
+// measured slower on the 8-view 1080p workload (56.4 -> 64.5 ms): the XCDs
+// then work on different views at once and share no Infinity Cache lines.
 #ifndef NGPRT_RENDER_WAVES_PER_EU
 #define NGPRT_RENDER_WAVES_PER_EU 4
 #endif
-#ifndef NGPRT_XCD_REMAP
-#define NGPRT_XCD_REMAP 0
+#ifndef NGPRT_XCD_CHUNK
+#define NGPRT_XCD_CHUNK 0
 #endif
 
 template <int DOM, int DT, int LMAX, int MODE>
@@ -122,11 +121,16 @@ render_kernel(SceneArgs S, int64_t n, const float* __restrict__ O,
   __shared__ float xin_all[4][8 * 64];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-#if NGPRT_XCD_REMAP
-  // workgroups are dispatched round-robin over the 8 XCDs
-  const unsigned G = gridDim.x, xcd = blockIdx.x % 8u, slot = blockIdx.x / 8u;
-  const unsigned q8 = G / 8u, r8 = G % 8u;
-  const unsigned block = xcd * q8 + (xcd < r8 ? xcd : r8) + slot;
+#if NGPRT_XCD_CHUNK > 0
+  // workgroups are dispatched round-robin over the 8 XCDs: give each XCD runs
+  // of NGPRT_XCD_CHUNK consecutive ray tiles-of-4 (neighbouring rays share
+  // cache lines in its L2) while all XCDs still sweep the same image region
+  // (their L2 misses share Infinity Cache lines); the last partial round of
+  // 8 * chunk workgroups keeps the identity placement
+  constexpr unsigned C = NGPRT_XCD_CHUNK;
+  const unsigned xcd = blockIdx.x % 8u, slot = blockIdx.x / 8u;
+  const unsigned full = gridDim.x / (8u * C);
+  const unsigned block = (slot / C < full) ? (slot / C) * (8u * C) + xcd * C + (slot % C) : blockIdx.x;
 #else
   const unsigned block = blockIdx.x;
 #endif

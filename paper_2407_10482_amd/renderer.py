@@ -266,9 +266,11 @@ class Proposal:
         self.step = 0
         self.owner = ctx_owner          # supplies the library context (workspace)
 
-    def infer(self, origins: torch.Tensor, dirs: torch.Tensor) -> torch.Tensor:
+    def infer(self, origins: torch.Tensor, dirs: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         n = origins.shape[0]
-        out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+        if out is None:
+            out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+        _dev(out, torch.float32, (n, 4), "out")
         check(self.owner.lib.ngprt_proposal_infer(self.owner.ctx, n, _ptr(origins), _ptr(dirs),
                                                   _ptr(self.params), _ptr(out), _stream()), self.owner.ctx)
         return out

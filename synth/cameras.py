@@ -19,19 +19,27 @@ from .configs import SceneConfig
 from .scene import camera_positions
 
 
-def tile_order(width: int, height: int, tile: int = 8) -> np.ndarray:
-    """Pixel indices (row*W + col) in tile-major order."""
+def tile_order(width: int, height: int, tile: int = 8, group: int = 1) -> np.ndarray:
+    """Pixel indices (row*W + col) in tile-major order; with group > 1 the
+    tiles are taken in blocks of group x group tiles (row-major over blocks,
+    row-major inside a block, blocks clipped at the image edge)."""
     if width % tile or height % tile:
         raise ValueError("image size must be a multiple of the tile size")
-    ty, tx, py, px = np.meshgrid(np.arange(height // tile), np.arange(width // tile),
-                                 np.arange(tile), np.arange(tile), indexing="ij")
-    rows = ty * tile + py
-    cols = tx * tile + px
+    if group < 1:
+        raise ValueError("group must be >= 1")
+    ty, tx = np.meshgrid(np.arange(height // tile), np.arange(width // tile), indexing="ij")
+    ty, tx = ty.ravel(), tx.ravel()
+    order = np.lexsort((tx % group, ty % group, tx // group, ty // group))
+    ty, tx = ty[order], tx[order]
+    py, px = np.meshgrid(np.arange(tile), np.arange(tile), indexing="ij")
+    rows = ty[:, None] * tile + py.ravel()[None, :]
+    cols = tx[:, None] * tile + px.ravel()[None, :]
     return (rows * width + cols).ravel()
 
 
 def pinhole_rays(cam_pos: np.ndarray, width: int, height: int, fov_deg: float = 60.0,
-                 tile: int = 8, target=(0.0, 0.0, 0.0)) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+                 tile: int = 8, target=(0.0, 0.0, 0.0), group: int = 1
+                 ) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
     cam_pos = np.asarray(cam_pos, dtype=np.float64)
     fwd = np.asarray(target, dtype=np.float64) - cam_pos
     fwd /= np.linalg.norm(fwd)
@@ -42,7 +50,7 @@ def pinhole_rays(cam_pos: np.ndarray, width: int, height: int, fov_deg: float = 
     right /= np.linalg.norm(right)
     cam_up = np.cross(right, fwd)
     tan_h = np.tan(np.deg2rad(fov_deg) * 0.5)
-    pix = tile_order(width, height, tile)
+    pix = tile_order(width, height, tile, group)
     rows = pix // width
     cols = pix % width
     xn = (2.0 * (cols + 0.5) / width - 1.0) * tan_h
@@ -54,14 +62,14 @@ def pinhole_rays(cam_pos: np.ndarray, width: int, height: int, fov_deg: float = 
             np.ascontiguousarray(d, dtype=np.float32), pix)
 
 
-def scene_rays(cfg: SceneConfig, cams=None, width=None, height=None):
+def scene_rays(cfg: SceneConfig, cams=None, width=None, height=None, group: int = 1):
     """All rays of the config's cameras, concatenated camera-major."""
     pos = camera_positions(cfg) if cams is None else np.asarray(cams)
     W = cfg.cam_width if width is None else width
     H = cfg.cam_height if height is None else height
     os_, ds_, ps_ = [], [], []
     for c in pos:
-        o, d, p = pinhole_rays(c, W, H, cfg.fov_deg)
+        o, d, p = pinhole_rays(c, W, H, cfg.fov_deg, group=group)
         os_.append(o)
         ds_.append(d)
         ps_.append(p)
