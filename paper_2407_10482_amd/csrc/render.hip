@@ -103,7 +103,7 @@ __device__ __forceinline__ void wave_mlp(const float* __restrict__ P, const floa
 
 // Occupancy floor of the render kernel (waves per SIMD; the 16-level kernels
 // fit 4 with ~126 VGPRs).  Giving each XCD one contiguous eighth of the rays
-// measured slower on the 8-view 1080p workload (56.4 -> 64.5 ms): the XCDs
+// measured slower on the 8-view 1080p workload (54.2 -> 61.9 ms): the XCDs
 // then work on different views at once and share no Infinity Cache lines.
 #ifndef NGPRT_RENDER_WAVES_PER_EU
 #define NGPRT_RENDER_WAVES_PER_EU 4
