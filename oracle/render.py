@@ -47,7 +47,7 @@ import numpy as np
 
 from .exact32 import F32, exp32, sqrt32
 from .hashgrid import corners32, corners64
-from . import quant
+from . import baked, quant
 
 BOX = 0
 CONTRACT = 1
@@ -69,6 +69,11 @@ class OracleInputs:
     t_threshold: float
     dtype: int = DT_F32
     mlp_dims: tuple = (7, 16, 16, 3)
+    # baked feature model (coarse grid + sigmoid-gated fine levels); 0 = hash model
+    coarse_res: int = 0
+    block_index: Optional[np.ndarray] = None   # int32 [nb, nb, nb]
+    atlas: Optional[np.ndarray] = None         # float32 [n_blocks, 8, 8, 8, C]
+    coarse_default: Optional[np.ndarray] = None  # float32 [C]
     # derived
     stored: Optional[np.ndarray] = None     # stored codes / values [L, T, 9]
     scales: Optional[np.ndarray] = None     # float32 [L, 9] (FP8 only)
@@ -114,6 +119,10 @@ class OracleInputs:
     def R(self):
         return self.occ.shape[0]
 
+    @property
+    def coarse_channels(self):
+        return 8 + 2 * self.L
+
 
 # --------------------------------------------------------------------------
 # per-sample lookup + attention
@@ -128,7 +137,9 @@ def fused32(inp: OracleInputs, u: np.ndarray):
     fused_j = (sum e_l v_l[j]) / S, attention weights e_l / S.
 
     Returns fused channels [m, 8], attention weights [m, L], corner indices
-    [m, L, 8]."""
+    [m, L, 8].  (Baked model: see oracle.baked.fused32.)"""
+    if inp.coarse_res:
+        return baked.fused32(inp, u)
     m = u.shape[0]
     esum = np.zeros(m, dtype=F32)
     num = np.zeros((m, 8), dtype=F32)
@@ -155,6 +166,8 @@ def fused32(inp: OracleInputs, u: np.ndarray):
 
 def fused64(inp: OracleInputs, u: np.ndarray):
     """Float64 lookup + attention; returns fused [m, 8], weights [m, L]."""
+    if inp.coarse_res:
+        return baked.fused64(inp, u)
     u = np.asarray(u, dtype=np.float64)
     m = u.shape[0]
     logits, vals = [], []
@@ -445,10 +458,14 @@ def render(inp: OracleInputs, o: np.ndarray, d: np.ndarray, naive: bool = False,
 
 def inputs_from_scene(scene, dist: np.ndarray, dtype: int = DT_F32) -> OracleInputs:
     cfg = scene.cfg
+    extra = {}
+    if getattr(scene, "block_index", None) is not None:
+        extra = dict(coarse_res=cfg.coarse_res, block_index=scene.block_index, atlas=scene.atlas,
+                     coarse_default=scene.default)
     return OracleInputs(tables=scene.tables, occ=scene.occ, dist=dist, mlp=scene.mlp,
                         resolutions=list(cfg.resolutions), domain=cfg.domain,
                         roi_half=cfg.roi_half, step=cfg.step, max_samples=cfg.max_samples,
-                        t_threshold=cfg.t_threshold, dtype=dtype, mlp_dims=cfg.mlp_dims)
+                        t_threshold=cfg.t_threshold, dtype=dtype, mlp_dims=cfg.mlp_dims, **extra)
 
 
 def valid_rays(inp: OracleInputs, o, d):

@@ -13,6 +13,14 @@ rendering arithmetic:
 * ``precision`` -- ``tiny`` with BF16 or FP8-E4M3 tables.
 * ``train``     -- one differentiable step on the ``tiny`` grid shape.
 * ``proposal``  -- the learned sample-interval proposal on the ``tiny`` scene.
+* ``baked_tiny`` / ``baked_hd`` -- the paper's own feature construction: a
+                   block-sparse coarse grid of resolution L_C holding the
+                   density, colour, specular feature and per-level attention
+                   parameters, plus L fine hash levels (8 channels) fused by
+                   sigmoid-gated separate attention.  ``baked_tiny``: box ROI,
+                   L_C = 64, fine levels 128 and 256, 2^14 entries;
+                   ``baked_hd``: the hd geometry, L_C = 512, fine levels
+                   1024 * 2^l (l < L, L = 2..4), 2^22 entries.
 
 Level resolutions follow a geometric progression between the coarsest and
 finest resolution (the multi-resolution hash encoding the method builds on,
@@ -41,6 +49,10 @@ DTYPE_F32 = 0
 DTYPE_BF16 = 1
 DTYPE_FP8 = 2
 
+MODEL_HASH = 0        # every level a hash level, softmax attention over levels
+MODEL_BAKED = 1       # coarse baked grid + fine hash levels with sigmoid gates
+BLOCK = 8             # coarse grid: vertices per block edge
+
 
 @dataclass
 class SceneConfig:
@@ -68,10 +80,17 @@ class SceneConfig:
     seed: int = 0
     mlp_dims: Tuple[int, int, int, int] = (7, 16, 16, 3)
     resolutions: List[int] = field(default_factory=list)
+    model: int = MODEL_HASH
+    coarse_res: int = 0        # L_C of the baked model (vertex lattice L_C + 1 per axis)
 
     def __post_init__(self):
         if not self.resolutions:
             self.resolutions = geometric_resolutions(self.n_min, self.n_max, self.n_levels)
+
+    @property
+    def coarse_channels(self) -> int:
+        """8 feature channels + (omega, beta) per fine level."""
+        return 8 + 2 * self.n_levels
 
     @property
     def table_size(self) -> int:
@@ -119,4 +138,33 @@ def train_large(seed: int = 0, table_dtype: int = DTYPE_F32) -> SceneConfig:
     return cfg
 
 
-CONFIGS = {"tiny": tiny, "hd": hd, "train_large": train_large}
+def baked_tiny(seed: int = 0, table_dtype: int = DTYPE_F32) -> SceneConfig:
+    """The tiny scene with the paper's feature construction: L_C = 64, fine
+    hash levels 128 and 256 with 2^14 entries."""
+    cfg = tiny(seed, table_dtype)
+    cfg.name = "baked_tiny"
+    cfg.model, cfg.coarse_res = MODEL_BAKED, 64
+    cfg.density_scale = 1e4       # ~18 evaluated samples per ray
+    cfg.n_levels, cfg.n_min, cfg.n_max = 2, 128, 256
+    cfg.resolutions = [128, 256]
+    return cfg
+
+
+def baked_hd(seed: int = 0, table_dtype: int = DTYPE_F32, n_fine: int = 2) -> SceneConfig:
+    """The hd geometry with the paper's feature construction (supplement,
+    "Multi-level Hash Features"): L_C = 512, fine levels 1024 * 2^l for
+    l < n_fine, 2^22 entries per fine level."""
+    if not 1 <= n_fine <= 4:
+        raise ValueError("n_fine must be 1..4")
+    cfg = hd(seed, table_dtype)
+    cfg.name = f"baked_hd_l{n_fine}"
+    cfg.model, cfg.coarse_res = MODEL_BAKED, 512
+    cfg.density_scale = 4000.0    # ~14 evaluated samples and ~35 grid reads per ray
+    cfg.n_levels, cfg.log2_table = n_fine, 22
+    cfg.resolutions = [1024 << l for l in range(n_fine)]
+    cfg.n_min, cfg.n_max = cfg.resolutions[0], cfg.resolutions[-1]
+    return cfg
+
+
+CONFIGS = {"tiny": tiny, "hd": hd, "train_large": train_large, "baked_tiny": baked_tiny,
+           "baked_hd": baked_hd}
