@@ -46,6 +46,10 @@ def parse():
                    help="run one device copy of this many MiB first (hardware-counter calibration)")
     p.add_argument("--probe-points", type=int, default=1 << 24,
                    help="points of the random-gather ceiling probe (0 skips it)")
+    p.add_argument("--model", choices=["hash", "baked"], default="hash",
+                   help="hash: 16 hash levels fused by softmax attention (the headline); baked: "
+                        "the paper's coarse grid + sigmoid-gated fine levels")
+    p.add_argument("--fine-levels", type=int, default=2, help="baked model: fine levels (1..4)")
     p.add_argument("--mode", choices=["render", "train", "proposal"], default="render",
                    help="render: the headline; train: forward+backward+Adam steps; "
                         "proposal: learned sample-interval proposal vs plain marching")
@@ -317,9 +321,15 @@ def main():
     from paper_2407_10482_amd.renderer import Renderer
 
     dtype = {"f32": 0, "bf16": 1, "fp8": 2}[args.dtype]
-    cfg = synth.hd(table_dtype=dtype)
+    baked = args.model == "baked"
     t0 = time.time()
-    sc = synth.make_scene(cfg)
+    if baked:
+        from synth.baked import make_baked_scene
+        cfg = synth.baked_hd(table_dtype=dtype, n_fine=args.fine_levels)
+        sc = make_baked_scene(cfg)
+    else:
+        cfg = synth.hd(table_dtype=dtype)
+        sc = synth.make_scene(cfg)
     cams = synth.camera_positions(cfg)[: args.views]
     o, d, _ = synth.scene_rays(cfg, cams=cams, group=args.group)
     print(f"# scene + rays generated in {time.time() - t0:.1f} s ({len(o)} rays)", file=sys.stderr,
@@ -336,6 +346,9 @@ def main():
     r = Renderer.from_config(cfg, dtype)
     r.load_scene(torch.from_numpy(sc.tables).cuda(), torch.from_numpy(sc.occ).cuda(),
                  torch.from_numpy(sc.mlp).cuda())
+    if baked:
+        r.load_coarse(torch.from_numpy(sc.block_index).cuda(), torch.from_numpy(sc.atlas).cuda(),
+                      sc.default)
     go = torch.from_numpy(o).cuda()
     gd = torch.from_numpy(d).cuda()
     n = len(o)
@@ -366,12 +379,29 @@ def main():
     views = len(cams)
     fps = views / (ms / 1e3)
     L = cfg.n_levels
-    gather = n_samples * L * 8 * BYTES_PER_ENTRY[dtype]
+    if baked:
+        # per sample: 8 coarse vertices (4 B block index + 4 B per coarse
+        # channel) and 8 corner rows per fine level (no logit)
+        per_sample = 8 * (4 + 4 * cfg.coarse_channels) + L * 8 * (BYTES_PER_ENTRY[dtype] * 8 // 9)
+    else:
+        per_sample = L * 8 * BYTES_PER_ENTRY[dtype]
+    gather = n_samples * per_sample
     alg_bytes = gather + 2 * n_reads + n * (24 + 12)
     achieved = alg_bytes / (ms / 1e3) / 1e9
-    traffic = committed_traffic(DTYPE_NAME[dtype])
+    traffic = None if baked else committed_traffic(DTYPE_NAME[dtype])
+    if baked:
+        workload = (f"baked_hd: 8 views x 1920x1080 rays, coarse grid L_C=512 block-sparse "
+                    f"({sc.n_blocks} of {sc.block_index.size} blocks of 8^3 vertices), {L} fine hash levels "
+                    f"{cfg.resolutions[0]}..{cfg.resolutions[-1]}, 2^22 entries, {DTYPE_NAME[dtype]} fine "
+                    "tables, sigmoid-gated separate attention, contracted scene of 200 blobs, 256^3 "
+                    "occupancy + distance grid, <=1024 samples/ray, T<1e-4")
+    else:
+        workload = ("hd: 8 views x 1920x1080 rays, 16 hash levels 16..4096, 2^19 entries, "
+                    f"{DTYPE_NAME[dtype]} tables, contracted scene of 200 blobs, 256^3 "
+                    "occupancy + distance grid, <=1024 samples/ray, T<1e-4")
     res = {
-        "metric": "1080p frames/s (plain distance-grid marching)",
+        "metric": ("1080p frames/s (baked model, plain distance-grid marching)" if baked
+                   else "1080p frames/s (plain distance-grid marching)"),
         "value": round(fps, 3),
         "unit": "frames/s",
         "n_gpus": 1,
@@ -384,9 +414,7 @@ def main():
         "dtype": DTYPE_NAME[dtype],
         "data": "synthetic",
         "config": {
-            "workload": "hd: 8 views x 1920x1080 rays, 16 hash levels 16..4096, 2^19 entries, "
-                        f"{DTYPE_NAME[dtype]} tables, contracted scene of 200 blobs, 256^3 "
-                        "occupancy + distance grid, <=1024 samples/ray, T<1e-4",
+            "workload": workload,
             "rays_per_step": n,
             "views": views,
         },
@@ -405,6 +433,7 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
             "algorithmic_bytes_per_launch": alg_bytes,
+            "algorithmic_bytes_per_sample": per_sample,
             "requested_gather_gbs_per_level": round(gather / L / (ms / 1e3) / 1e9, 1),
             "hbm_gbs_measured": None if traffic is None else round(traffic / (ms / 1e3) / 1e9, 1),
             "hbm_frac_measured": None if traffic is None else round(traffic / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),

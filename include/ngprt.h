@@ -69,6 +69,19 @@ enum ngprt_domain {
   NGPRT_ROI_CONTRACT = 1
 };
 
+enum ngprt_feature_model {
+  /* Every level a hash level of 8 feature channels + 1 attention logit;
+   * the levels are fused by a softmax over the interpolated logits. */
+  NGPRT_MODEL_HASH = 0,
+  /* The paper's construction (Sec. 4.1 Eq. 6; Sec. 4.2 Eq. 7-8): a coarse
+   * vertex grid of resolution L_C (loaded by ngprt_load_coarse) holds the
+   * deferred features f~ and per-level attention parameters (omega_l,
+   * beta_l); n_levels (1..4) fine hash levels hold 8-channel features f^_l;
+   * f = f~ + [sum_l sigmoid(omega_l) sigma^_l, sum_l sigmoid(beta_l) c^_l,
+   * sum_l sigmoid(beta_l) v^_l]. */
+  NGPRT_MODEL_BAKED = 1
+};
+
 /* Scene descriptor (copied by ngprt_create). */
 typedef struct ngprt_desc {
   int32_t n_levels;                          /* L, 1..16 */
@@ -82,6 +95,8 @@ typedef struct ngprt_desc {
   int32_t max_samples;                       /* cap on evaluated samples per ray, >= 1 */
   float t_threshold;                         /* stop once T < t_threshold; 0 disables */
   int32_t mlp_in, mlp_hidden, mlp_out;       /* must be 7, 16, 3 */
+  int32_t feature_model;                     /* enum ngprt_feature_model */
+  int32_t coarse_res;                        /* L_C of NGPRT_MODEL_BAKED, 1..2048 (else ignored) */
 } ngprt_desc;
 
 typedef struct ngprt_ctx ngprt_ctx;
@@ -119,6 +134,24 @@ int ngprt_validate_desc(const ngprt_desc* desc);
  *  code = RNE-saturate(x / s).  Stored internally as a feature array
  *  [L][T][8] and a logit array [L][T]. */
 int ngprt_load_tables(ngprt_ctx* ctx, const float* dev_tables, void* stream);
+
+/* NGPRT_MODEL_BAKED: load the coarse grid (Sec. 4.1: the baked grids F~ and
+ * A of resolution L_C, stored together).  Vertices (vx, vy, vz), 0 <= v <=
+ * L_C, are grouped in blocks of 8^3; nb = ceil((L_C + 1) / 8).
+ *  dev_block_index  int32 [nb][nb][nb] (z, y, x): the block's row in the
+ *                   atlas, or -1 for an empty block; every entry must be in
+ *                   [-1, n_blocks) (checked on the host: the index grid is
+ *                   copied back once; otherwise NGPRT_E_INVALID_ARG).
+ *  dev_atlas        float32 [n_blocks][8][8][8][C] (z, y, x inside the
+ *                   block), C = 8 + 2L channels [sigma~, r, g, b, s0..s3,
+ *                   omega_1, beta_1, ..., omega_L, beta_L] (attention
+ *                   parameters before their sigmoid); NULL if n_blocks = 0.
+ *  host_default     float32 [C]: the value of every vertex of an empty block.
+ * The fine levels are loaded by ngprt_load_tables in the same [L][T][9]
+ * layout as the hash model, channel 8 unused.  Synchronises the stream.
+ * NGPRT_MODEL_HASH contexts return NGPRT_E_UNSUPPORTED. */
+int ngprt_load_coarse(ngprt_ctx* ctx, int64_t n_blocks, const int32_t* dev_block_index,
+                      const float* dev_atlas, const float* host_default, void* stream);
 
 /* Read back the stored tables as [L][T][9] in the storage dtype
  * (float32 / bf16 bits / e4m3 bytes) and, for FP8, the scales [L][9]
@@ -194,7 +227,8 @@ int ngprt_debug_march(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins,
  * and dL/dmlp into dev_grad_mlp, float32 [451]; the caller zeroes them.
  * The forward is recomputed per ray (two re-marches, no per-sample state);
  * table gradients are summed with float atomics, so their low bits depend
- * on execution order.  Needs float32 tables (NGPRT_E_DTYPE otherwise).  May
+ * on execution order.  Needs float32 tables (NGPRT_E_DTYPE otherwise) and
+ * the hash feature model (NGPRT_E_UNSUPPORTED for NGPRT_MODEL_BAKED).  May
  * grow a library-owned workspace (stream-ordered allocation). */
 int ngprt_render_backward(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins,
                           const float* dev_dirs, const float* dev_grad_rgb, float* dev_grad_tables,

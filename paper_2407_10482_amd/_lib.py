@@ -15,6 +15,7 @@ STATUS = {0: "NGPRT_OK", -1: "NGPRT_E_INVALID_ARG", -2: "NGPRT_E_SHAPE", -3: "NG
 
 F32, BF16, FP8E4M3 = 0, 1, 2
 ROI_BOX, ROI_CONTRACT = 0, 1
+MODEL_HASH, MODEL_BAKED = 0, 1
 
 
 class NgprtDesc(ctypes.Structure):
@@ -32,6 +33,8 @@ class NgprtDesc(ctypes.Structure):
         ("mlp_in", ctypes.c_int32),
         ("mlp_hidden", ctypes.c_int32),
         ("mlp_out", ctypes.c_int32),
+        ("feature_model", ctypes.c_int32),
+        ("coarse_res", ctypes.c_int32),
     ]
 
 
@@ -51,6 +54,7 @@ SIGNATURES = [
     ("ngprt_validate_desc", ctypes.c_int, [ctypes.POINTER(NgprtDesc)]),
     ("ngprt_load_tables", ctypes.c_int, [_P, _P, _P]),
     ("ngprt_export_tables", ctypes.c_int, [_P, _P, _P, _P]),
+    ("ngprt_load_coarse", ctypes.c_int, [_P, _I64, _P, _P, _P, _P]),
     ("ngprt_load_occupancy", ctypes.c_int, [_P, _P, _P, _P]),
     ("ngprt_export_distance", ctypes.c_int, [_P, _P, _P]),
     ("ngprt_load_mlp", ctypes.c_int, [_P, _P, _P]),
@@ -113,7 +117,8 @@ def check(code: int, ctx=None):
 
 
 def make_desc(resolutions, log2_table_size, table_dtype, domain, roi_half, occ_res, step,
-              max_samples, t_threshold, mlp=(7, 16, 3)) -> NgprtDesc:
+              max_samples, t_threshold, mlp=(7, 16, 3), feature_model=MODEL_HASH,
+              coarse_res=0) -> NgprtDesc:
     d = NgprtDesc()
     d.n_levels = len(resolutions)
     for i, r in enumerate(resolutions[:MAX_LEVELS]):
@@ -127,4 +132,6 @@ def make_desc(resolutions, log2_table_size, table_dtype, domain, roi_half, occ_r
     d.max_samples = int(max_samples)
     d.t_threshold = float(t_threshold)
     d.mlp_in, d.mlp_hidden, d.mlp_out = mlp
+    d.feature_model = int(feature_model)
+    d.coarse_res = int(coarse_res)
     return d

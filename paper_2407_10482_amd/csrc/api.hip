@@ -7,6 +7,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "internal.h"
 
@@ -49,6 +50,16 @@ SceneArgs scene_args(const ngprt_ctx* ctx) {
   S.thr = d.t_threshold;
   S.max_samples = d.max_samples;
   S.lshift = ctx->logit_shift;
+  S.model = d.feature_model;
+  if (d.feature_model == NGPRT_MODEL_BAKED) {
+    S.LC = d.coarse_res;
+    S.LCf = float(d.coarse_res);
+    S.nb = (d.coarse_res + 1 + 7) / 8;
+    S.Cpad = coarse_row_floats(d.n_levels);
+    S.cidx = ctx->cidx;
+    S.catlas = ctx->catlas;
+    for (int j = 0; j < 16; ++j) S.cdef[j] = ctx->cdef[j];
+  }
   return S;
 }
 
@@ -100,6 +111,12 @@ int ngprt_validate_desc(const ngprt_desc* d) {
   if (d->max_samples < 1) return NGPRT_E_INVALID_ARG;
   if (!(d->t_threshold >= 0.0f) || !std::isfinite(d->t_threshold)) return NGPRT_E_INVALID_ARG;
   if (d->mlp_in != 7 || d->mlp_hidden != 16 || d->mlp_out != 3) return NGPRT_E_UNSUPPORTED;
+  if (d->feature_model != NGPRT_MODEL_HASH && d->feature_model != NGPRT_MODEL_BAKED)
+    return NGPRT_E_INVALID_ARG;
+  if (d->feature_model == NGPRT_MODEL_BAKED) {
+    if (d->n_levels > 4) return NGPRT_E_SHAPE;
+    if (d->coarse_res < 1 || d->coarse_res > 2048) return NGPRT_E_SHAPE;
+  }
   return NGPRT_OK;
 }
 
@@ -117,6 +134,8 @@ void ngprt_destroy(ngprt_ctx* ctx) {
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->prop_wb) (void)hipFree(ctx->prop_wb);
   if (ctx->prop_grad) (void)hipFree(ctx->prop_grad);
+  if (ctx->cidx) (void)hipFree(ctx->cidx);
+  if (ctx->catlas) (void)hipFree(ctx->catlas);
   if (switched) (void)hipSetDevice(cur);
   delete ctx;
 }
@@ -164,6 +183,55 @@ int ngprt_load_tables(ngprt_ctx* ctx, const float* dev_tables, void* stream) {
   return rc;
 }
 
+int ngprt_load_coarse(ngprt_ctx* ctx, int64_t n_blocks, const int32_t* dev_block_index,
+                      const float* dev_atlas, const float* host_default, void* stream) {
+  if (!ctx) return NGPRT_E_INVALID_ARG;
+  const ngprt_desc& d = ctx->desc;
+  if (d.feature_model != NGPRT_MODEL_BAKED)
+    return fail(ctx, NGPRT_E_UNSUPPORTED, "the context does not use the baked feature model");
+  if (n_blocks < 0 || n_blocks > (int64_t(1) << 31) / 512)
+    return fail(ctx, NGPRT_E_INVALID_ARG, "n_blocks out of range");
+  if (!dev_block_index || !host_default || (n_blocks > 0 && !dev_atlas))
+    return fail(ctx, NGPRT_E_INVALID_ARG, "NULL pointer");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t nb = (d.coarse_res + 1 + 7) / 8;
+  const int64_t n_idx = nb * nb * nb;
+  // the index grid decides which atlas rows the kernels read: check it here
+  std::vector<int32_t> idx(static_cast<size_t>(n_idx));
+  if (hipMemcpyAsync(idx.data(), dev_block_index, sizeof(int32_t) * n_idx, hipMemcpyDeviceToHost, st) !=
+          hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return check_launch(ctx, "block index copy");
+  for (int64_t i = 0; i < n_idx; ++i)
+    if (idx[size_t(i)] < -1 || idx[size_t(i)] >= n_blocks)
+      return fail(ctx, NGPRT_E_INVALID_ARG, "block index entry outside [-1, n_blocks)");
+  const int C = 8 + 2 * d.n_levels, Cpad = coarse_row_floats(d.n_levels);
+  if (ctx->cidx) (void)hipFree(ctx->cidx);
+  if (ctx->catlas) (void)hipFree(ctx->catlas);
+  ctx->cidx = nullptr;
+  ctx->catlas = nullptr;
+  ctx->coarse_loaded = false;
+  if (hipMalloc((void**)&ctx->cidx, sizeof(int32_t) * n_idx) != hipSuccess ||
+      (n_blocks > 0 &&
+       hipMalloc((void**)&ctx->catlas, sizeof(float) * size_t(n_blocks) * 512 * Cpad) != hipSuccess)) {
+    (void)hipGetLastError();
+    return fail(ctx, NGPRT_E_ALLOC, "coarse grid allocation failed");
+  }
+  if (hipMemcpyAsync(ctx->cidx, idx.data(), sizeof(int32_t) * n_idx, hipMemcpyHostToDevice, st) !=
+      hipSuccess)
+    return check_launch(ctx, "block index upload");
+  ctx->n_blocks = n_blocks;
+  for (int j = 0; j < 16; ++j) ctx->cdef[j] = j < C ? host_default[j] : 0.0f;
+  if (n_blocks > 0) {
+    int rc = launch_pack_atlas(ctx, dev_atlas, n_blocks, st);
+    if (rc) return rc;
+  }
+  // the host copy of the index grid is freed on return: finish the upload first
+  if (hipStreamSynchronize(st) != hipSuccess) return check_launch(ctx, "coarse grid upload");
+  ctx->coarse_loaded = true;
+  return NGPRT_OK;
+}
+
 int ngprt_export_tables(ngprt_ctx* ctx, void* dev_codes, float* dev_scales, void* stream) {
   if (!ctx) return NGPRT_E_INVALID_ARG;
   if (!dev_codes) return fail(ctx, NGPRT_E_INVALID_ARG, "dev_codes is NULL");
@@ -198,6 +266,8 @@ int ngprt_load_mlp(ngprt_ctx* ctx, const float* dev_params, void* stream) {
 
 static int check_ready(ngprt_ctx* ctx) {
   if (!ctx->tables_loaded) return fail(ctx, NGPRT_E_NOT_LOADED, "tables not loaded");
+  if (ctx->desc.feature_model == NGPRT_MODEL_BAKED && !ctx->coarse_loaded)
+    return fail(ctx, NGPRT_E_NOT_LOADED, "coarse grid not loaded");
   if (!ctx->occ_loaded) return fail(ctx, NGPRT_E_NOT_LOADED, "occupancy not loaded");
   return NGPRT_OK;
 }
@@ -244,6 +314,8 @@ int ngprt_debug_eval_points(ngprt_ctx* ctx, int64_t n, const float* dev_pos, int
   if (n == 0) return NGPRT_OK;
   if (!dev_pos) return fail(ctx, NGPRT_E_INVALID_ARG, "dev_pos is NULL");
   if (!ctx->tables_loaded) return fail(ctx, NGPRT_E_NOT_LOADED, "tables not loaded");
+  if (ctx->desc.feature_model == NGPRT_MODEL_BAKED && !ctx->coarse_loaded)
+    return fail(ctx, NGPRT_E_NOT_LOADED, "coarse grid not loaded");
   return launch_eval_points(ctx, n, dev_pos, dev_idx, dev_fused, dev_weights, (hipStream_t)stream);
 }
 
@@ -282,6 +354,8 @@ int ngprt_render_backward(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origi
     return fail(ctx, NGPRT_E_INVALID_ARG, "NULL pointer");
   if (ctx->desc.table_dtype != NGPRT_F32)
     return fail(ctx, NGPRT_E_DTYPE, "backward needs float32 tables");
+  if (ctx->desc.feature_model != NGPRT_MODEL_HASH)
+    return fail(ctx, NGPRT_E_UNSUPPORTED, "backward supports the hash feature model only");
   int rc = check_ready(ctx);
   if (rc) return rc;
   if (!ctx->mlp_loaded) return fail(ctx, NGPRT_E_NOT_LOADED, "mlp not loaded");

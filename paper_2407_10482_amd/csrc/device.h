@@ -235,4 +235,136 @@ __device__ __forceinline__ void eval_fused(const SceneArgs& S, const float u[3],
   }
 }
 
+// ---------------------------------------------------------------------------
+// Baked feature model (Sec. 4.1 Eq. 6, Sec. 4.2 Eq. 7-8): a block-sparse
+// coarse vertex grid of resolution L_C holds the deferred features f~ and
+// the attention parameters a = (omega_l, beta_l); L fine hash levels hold
+// 8-channel features f^_l.  f = f~ + [sum_l g(omega_l) sigma^_l,
+// sum_l g(beta_l) c^_l, sum_l g(beta_l) v^_l] with g the sigmoid.
+//
+// Coarse vertex v lives in block (v >> 3) (per axis) at local offset v & 7;
+// the block's atlas row comes from the index grid (-1: empty block, whose
+// vertices take the default vector).  Atlas rows hold Cpad >= 8 + 2L floats.
+// Decision chain: every coarse channel acc = acc + w_k v_k (k = 0..7, plain
+// float32); fine density as the hash levels; g = 1 / (1 + exp32(-a));
+// f_0 = f~_0, then f_0 = f_0 + g_omega_l * sigma^_l in level order.
+__device__ __forceinline__ float sigmoid32(float a) { return 1.0f / (1.0f + exp32(-a)); }
+
+template <int DT, int LMAX, bool DEBUG = false>
+__device__ __forceinline__ void eval_baked(const SceneArgs& S, const float u[3], float fused[8],
+                                           float* wout = nullptr, int32_t* idxout = nullptr) {
+  static_assert(LMAX <= 4, "the coarse row holds at most 16 channels");
+  constexpr int CMAX = 8 + 2 * LMAX;
+  int i0[3];
+  float f[3], g[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float p = u[a] * S.LCf;
+    int i = (int)floorf(p);
+    i = i < 0 ? 0 : (i > S.LC - 1 ? S.LC - 1 : i);
+    i0[a] = i;
+    f[a] = __builtin_fmaf(u[a], S.LCf, -(float)i);
+    g[a] = 1.0f - f[a];
+  }
+  float co[CMAX];
+#pragma unroll
+  for (int j = 0; j < CMAX; ++j) co[j] = 0.0f;
+  const bool wide = S.Cpad > 12;      // rows of 16 floats (L = 3, 4), else 12
+  // corners one after another (rolled): each brings a whole row of up to 16
+  // floats, and holding several in flight would spill
+#ifndef NGPRT_COARSE_UNROLL
+#define NGPRT_COARSE_UNROLL 1
+#endif
+#pragma unroll NGPRT_COARSE_UNROLL
+  for (int k = 0; k < 8; ++k) {
+    const int bx = k & 1, by = (k >> 1) & 1, bz = (k >> 2) & 1;
+    const int vx = i0[0] + bx, vy = i0[1] + by, vz = i0[2] + bz;
+    const int bid = S.cidx[((vz >> 3) * S.nb + (vy >> 3)) * S.nb + (vx >> 3)];
+    const float wk = ((bx ? f[0] : g[0]) * (by ? f[1] : g[1])) * (bz ? f[2] : g[2]);
+    float v[16];
+    if (bid >= 0) {
+      const float4* row = reinterpret_cast<const float4*>(
+          S.catlas + (size_t(bid) * 512 + size_t(((vz & 7) * 8 + (vy & 7)) * 8 + (vx & 7))) * S.Cpad);
+      float4 q0 = row[0], q1 = row[1], q2 = row[2];
+      float4 q3 = wide ? row[3] : make_float4(0.f, 0.f, 0.f, 0.f);
+      v[0] = q0.x; v[1] = q0.y; v[2] = q0.z; v[3] = q0.w;
+      v[4] = q1.x; v[5] = q1.y; v[6] = q1.z; v[7] = q1.w;
+      v[8] = q2.x; v[9] = q2.y; v[10] = q2.z; v[11] = q2.w;
+      v[12] = q3.x; v[13] = q3.y; v[14] = q3.z; v[15] = q3.w;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) v[j] = S.cdef[j];
+    }
+#pragma unroll
+    for (int j = 0; j < CMAX; ++j) co[j] = co[j] + wk * v[j];
+  }
+  float f0 = co[0];
+  float fc[7];
+#pragma unroll
+  for (int j = 0; j < 7; ++j) fc[j] = co[1 + j];
+  // fine levels, rolled; the level's attention parameters are picked by
+  // selects (no dynamically indexed register array)
+#pragma unroll 1
+  for (int l = 0; l < LMAX; ++l) {
+    if (l < S.L) {
+      Corners c;
+      level_corners(u, S.N[l], S.Nf[l], S.mask, c);
+      const void* fb = feat_level<DT>(S.feat, l, S.log2T);
+      float acc[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[j] = 0.0f;
+#pragma unroll
+      for (int gq = 0; gq < 2; ++gq) {
+        float v[4][8];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Store<DT>::feat(fb, c.idx[4 * gq + k], v[k]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const float wk = c.w[4 * gq + k];
+          acc[0] = acc[0] + wk * v[k][0];
+#pragma unroll
+          for (int j = 1; j < 8; ++j) acc[j] = __builtin_fmaf(wk, v[k][j], acc[j]);
+        }
+      }
+      if (DT == DT_FP8) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[j] = S.scale[l][j] * acc[j];
+      }
+      float aw = co[8], ab = co[9];
+#pragma unroll
+      for (int q = 1; q < LMAX; ++q) {
+        aw = l == q ? co[8 + 2 * q] : aw;
+        ab = l == q ? co[9 + 2 * q] : ab;
+      }
+      const float gw = sigmoid32(aw);
+      const float gb = sigmoid32(ab);
+      f0 = f0 + gw * acc[0];
+#pragma unroll
+      for (int j = 0; j < 7; ++j) fc[j] = __builtin_fmaf(gb, acc[1 + j], fc[j]);
+      if (DEBUG) {
+#pragma unroll
+        for (int q = 0; q < LMAX; ++q)
+          if (q == l) {
+            wout[q] = gw;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) idxout[q * 8 + k] = int32_t(c.idx[k]);
+          }
+      }
+    }
+  }
+  fused[0] = f0;
+#pragma unroll
+  for (int j = 0; j < 7; ++j) fused[1 + j] = fc[j];
+}
+
+// One sample's fused deferred feature under the scene's feature model.
+template <int MODEL, int DT, int LMAX, bool DEBUG = false>
+__device__ __forceinline__ void eval_sample(const SceneArgs& S, const float u[3], float fused[8],
+                                            float* wout = nullptr, int32_t* idxout = nullptr) {
+  if constexpr (MODEL == 1)
+    eval_baked<DT, LMAX, DEBUG>(S, u, fused, wout, idxout);
+  else
+    eval_fused<DT, LMAX, DEBUG>(S, u, fused, wout, idxout);
+}
+
 }  // namespace ngprt

@@ -17,6 +17,10 @@ constexpr int kMaxLevels = NGPRT_MAX_LEVELS;
 constexpr int kMlpParams = 451;
 constexpr int kMaxLattice = 1 << 16;   // hard bound on lattice points per ray
 
+// floats per coarse atlas row of the baked model: 8 + 2L channels rounded up
+// to whole float4 loads (12 for L <= 2, 16 for L = 3, 4)
+inline int coarse_row_floats(int L) { return (8 + 2 * L + 3) / 4 * 4; }
+
 // Scene constants passed by value to kernels (lands in scalar registers).
 struct SceneArgs {
   int L;
@@ -38,6 +42,15 @@ struct SceneArgs {
   float step;
   float thr;
   int max_samples;
+  // baked feature model (model = 1): block-sparse coarse vertex grid
+  int model;
+  int LC;                         // coarse resolution (vertices 0..LC per axis)
+  float LCf;
+  int nb;                         // blocks per axis, ceil((LC + 1) / 8)
+  int Cpad;                       // floats per atlas row (12 or 16)
+  const int32_t* cidx;            // [nb^3] atlas row of each block or -1
+  const float* catlas;            // [n_blocks][512][Cpad]
+  float cdef[16];                 // value of every vertex of an empty block
 };
 
 struct RayOut {
@@ -70,6 +83,11 @@ struct ngprt_ctx {
   size_t ws_bytes = 0;
   void* prop_wb = nullptr;    // proposal weights in bfloat16 [7556]
   void* prop_grad = nullptr;  // proposal gradient [7556] when the caller wants none
+  int32_t* cidx = nullptr;    // baked model: block index grid [nb^3]
+  float* catlas = nullptr;    // baked model: atlas [n_blocks][512][Cpad]
+  int64_t n_blocks = 0;
+  float cdef[16] = {};
+  bool coarse_loaded = false;
   bool tables_loaded = false;
   bool occ_loaded = false;
   bool mlp_loaded = false;
@@ -94,6 +112,7 @@ int launch_march(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, int3
                  int32_t* sk, int32_t* ns, int32_t* nr, int naive, hipStream_t s);
 int launch_backward(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const float* grad_rgb,
                     float* gtab, float* gmlp, hipStream_t s);
+int launch_pack_atlas(ngprt_ctx* ctx, const float* atlas, int64_t n_blocks, hipStream_t s);
 int launch_gather_probe(ngprt_ctx* ctx, int64_t n, uint32_t seed, int pairs, float* out, hipStream_t s);
 int launch_adam(int64_t n, float* p, const float* g, float* m, float* v, int32_t step, float lr,
                 float b1, float b2, float eps, hipStream_t s);

@@ -112,7 +112,7 @@ __device__ __forceinline__ void wave_mlp(const float* __restrict__ P, const floa
 #define NGPRT_XCD_CHUNK 0
 #endif
 
-template <int DOM, int DT, int LMAX, int MODE>
+template <int DOM, int DT, int LMAX, int MODE, int MODEL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NGPRT_RENDER_WAVES_PER_EU)))
 render_kernel(SceneArgs S, int64_t n, const float* __restrict__ O,
                                                      const float* __restrict__ D, RayOut out,
@@ -173,7 +173,7 @@ render_kernel(SceneArgs S, int64_t n, const float* __restrict__ O,
     if (__ballot(have) == 0) break;
     if (have) {
       float f[8];
-      eval_fused<DT, LMAX>(S, u, f);
+      eval_sample<MODEL, DT, LMAX>(S, u, f);
       const float sigma = exp32(f[0]);
       const float e = exp32(-(sigma * S.step));
       const float alpha = 1.0f - e;
@@ -233,7 +233,7 @@ render_kernel(SceneArgs S, int64_t n, const float* __restrict__ O,
   wave_mlp(mlp, xin, lane, ray_base, n, out.rgb);
 }
 
-template <int DT, int LMAX>
+template <int DT, int LMAX, int MODEL>
 __global__ void __launch_bounds__(256) eval_points_kernel(SceneArgs S, int64_t n,
                                                           const float* __restrict__ pos,
                                                           int32_t* idx, float* fused, float* weights) {
@@ -244,7 +244,7 @@ __global__ void __launch_bounds__(256) eval_points_kernel(SceneArgs S, int64_t n
   for (int a = 0; a < 3; ++a) u[a] = (p[a] - S.lo) * S.inv_ext;
   float f[8], w[LMAX];
   int32_t id[LMAX * 8];
-  eval_fused<DT, LMAX, true>(S, u, f, w, id);
+  eval_sample<MODEL, DT, LMAX, true>(S, u, f, w, id);
   if (fused)
     for (int j = 0; j < 8; ++j) fused[i * 8 + j] = f[j];
   if (weights)
@@ -261,11 +261,14 @@ template <int MODE, int DOM, int DT>
 static void dispatch_l(const SceneArgs& S, dim3 g, hipStream_t st, int64_t n, const float* o,
                        const float* d, const RayOut& out, const MarchRecord& rec,
                        const float* mlp, int naive, const ProposalArgs& pa) {
-  if (S.L <= 8)
-    hipLaunchKernelGGL((render_kernel<DOM, DT, 8, MODE>), g, dim3(256), 0, st, S, n, o, d, out, rec,
+  if (S.model == 1)
+    hipLaunchKernelGGL((render_kernel<DOM, DT, 4, MODE, 1>), g, dim3(256), 0, st, S, n, o, d, out, rec,
+                       mlp, naive, pa);
+  else if (S.L <= 8)
+    hipLaunchKernelGGL((render_kernel<DOM, DT, 8, MODE, 0>), g, dim3(256), 0, st, S, n, o, d, out, rec,
                        mlp, naive, pa);
   else
-    hipLaunchKernelGGL((render_kernel<DOM, DT, 16, MODE>), g, dim3(256), 0, st, S, n, o, d, out, rec,
+    hipLaunchKernelGGL((render_kernel<DOM, DT, 16, MODE, 0>), g, dim3(256), 0, st, S, n, o, d, out, rec,
                        mlp, naive, pa);
 }
 
@@ -324,12 +327,19 @@ int launch_eval_points(ngprt_ctx* ctx, int64_t n, const float* pos, int32_t* idx
   if (blocks > 0x7FFFFFFF) return fail(ctx, NGPRT_E_SHAPE, "too many points for one launch");
   dim3 g = dim3(unsigned(blocks));
   const int dt = ctx->desc.table_dtype;
-#define NGPRT_EV(DTV, LM)                                                                   \
-  hipLaunchKernelGGL((eval_points_kernel<DTV, LM>), g, dim3(256), 0, st, S, n, pos, idx, fused, \
+#define NGPRT_EV(DTV, LM, MD)                                                                   \
+  hipLaunchKernelGGL((eval_points_kernel<DTV, LM, MD>), g, dim3(256), 0, st, S, n, pos, idx, fused, \
                      weights)
-  if (dt == DT_F32) { if (S.L <= 8) NGPRT_EV(DT_F32, 8); else NGPRT_EV(DT_F32, 16); }
-  if (dt == DT_BF16) { if (S.L <= 8) NGPRT_EV(DT_BF16, 8); else NGPRT_EV(DT_BF16, 16); }
-  if (dt == DT_FP8) { if (S.L <= 8) NGPRT_EV(DT_FP8, 8); else NGPRT_EV(DT_FP8, 16); }
+#define NGPRT_EV_DT(DTV)                   \
+  if (dt == DTV) {                         \
+    if (S.model == 1) NGPRT_EV(DTV, 4, 1); \
+    else if (S.L <= 8) NGPRT_EV(DTV, 8, 0); \
+    else NGPRT_EV(DTV, 16, 0);              \
+  }
+  NGPRT_EV_DT(DT_F32)
+  NGPRT_EV_DT(DT_BF16)
+  NGPRT_EV_DT(DT_FP8)
+#undef NGPRT_EV_DT
 #undef NGPRT_EV
   return check_launch(ctx, "eval_points_kernel");
 }

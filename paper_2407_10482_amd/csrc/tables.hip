@@ -235,4 +235,25 @@ int launch_export_tables(ngprt_ctx* ctx, void* codes, float* scales, hipStream_t
   return NGPRT_OK;
 }
 
+// Baked model: coarse atlas [n_blocks][512][C] float32 -> rows of Cpad
+// floats (zero padded) so a row is whole float4 loads.
+__global__ void pack_atlas_kernel(const float* __restrict__ src, float* __restrict__ dst, int64_t rows,
+                                  int C, int Cpad) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= rows * Cpad) return;
+  const int64_t r = i / Cpad;
+  const int c = int(i - r * Cpad);
+  dst[i] = c < C ? src[r * C + c] : 0.0f;
+}
+
+int launch_pack_atlas(ngprt_ctx* ctx, const float* atlas, int64_t n_blocks, hipStream_t st) {
+  const int C = 8 + 2 * ctx->desc.n_levels, Cpad = coarse_row_floats(ctx->desc.n_levels);
+  const int64_t total = n_blocks * 512 * Cpad;
+  const int64_t blocks = (total + 255) / 256;
+  if (blocks > 0x7FFFFFFF) return fail(ctx, NGPRT_E_SHAPE, "atlas too large");
+  hipLaunchKernelGGL(pack_atlas_kernel, dim3(unsigned(blocks)), dim3(256), 0, st, atlas, ctx->catlas,
+                     n_blocks * 512, C, Cpad);
+  return check_launch(ctx, "pack_atlas_kernel");
+}
+
 }  // namespace ngprt

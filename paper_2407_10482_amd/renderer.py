@@ -8,7 +8,8 @@ from typing import Dict, Optional, Sequence
 import torch
 
 from . import _lib
-from ._lib import F32, BF16, FP8E4M3, ROI_BOX, ROI_CONTRACT, NgprtOutputs, check, load_library
+from ._lib import (BF16, F32, FP8E4M3, MODEL_BAKED, MODEL_HASH, ROI_BOX, ROI_CONTRACT, NgprtOutputs,
+                   check, load_library)
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -36,15 +37,19 @@ class Renderer:
 
     def __init__(self, resolutions: Sequence[int], log2_table_size: int, table_dtype: int = F32,
                  domain: int = ROI_BOX, roi_half: float = 1.0, occ_res: int = 64,
-                 step: float = 1.0 / 256.0, max_samples: int = 1024, t_threshold: float = 1e-4):
+                 step: float = 1.0 / 256.0, max_samples: int = 1024, t_threshold: float = 1e-4,
+                 feature_model: int = MODEL_HASH, coarse_res: int = 0):
         self.lib = load_library()
         self.resolutions = list(resolutions)
         self.L = len(self.resolutions)
         self.T = 1 << log2_table_size
         self.R = occ_res
         self.table_dtype = table_dtype
+        self.feature_model = feature_model
+        self.coarse_res = coarse_res
         self.desc = _lib.make_desc(resolutions, log2_table_size, table_dtype, domain, roi_half,
-                                   occ_res, step, max_samples, t_threshold)
+                                   occ_res, step, max_samples, t_threshold,
+                                   feature_model=feature_model, coarse_res=coarse_res)
         ctx = ctypes.c_void_p()
         check(self.lib.ngprt_create(ctypes.byref(self.desc), ctypes.byref(ctx)))
         self.ctx = ctx
@@ -52,7 +57,8 @@ class Renderer:
     @classmethod
     def from_config(cls, cfg, table_dtype: Optional[int] = None) -> "Renderer":
         return cls(cfg.resolutions, cfg.log2_table, cfg.table_dtype if table_dtype is None else table_dtype,
-                   cfg.domain, cfg.roi_half, cfg.occ_res, cfg.step, cfg.max_samples, cfg.t_threshold)
+                   cfg.domain, cfg.roi_half, cfg.occ_res, cfg.step, cfg.max_samples, cfg.t_threshold,
+                   getattr(cfg, "model", MODEL_HASH), getattr(cfg, "coarse_res", 0))
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -79,6 +85,19 @@ class Renderer:
     def load_mlp(self, params: torch.Tensor):
         _dev(params, torch.float32, (451,), "mlp params")
         check(self.lib.ngprt_load_mlp(self.ctx, _ptr(params), _stream()), self.ctx)
+
+    def load_coarse(self, block_index: torch.Tensor, atlas: torch.Tensor, default):
+        """Baked model: block index grid int32 [nb]^3, atlas float32
+        [n_blocks, 8, 8, 8, C], default vector (C floats, host)."""
+        nb = (self.coarse_res + 1 + 7) // 8
+        C = 8 + 2 * self.L
+        _dev(block_index, torch.int32, (nb, nb, nb), "block_index")
+        n_blocks = atlas.shape[0]
+        if n_blocks:
+            _dev(atlas, torch.float32, (n_blocks, 8, 8, 8, C), "atlas")
+        dflt = (ctypes.c_float * C)(*[float(x) for x in default])
+        check(self.lib.ngprt_load_coarse(self.ctx, n_blocks, _ptr(block_index),
+                                         _ptr(atlas) if n_blocks else None, dflt, _stream()), self.ctx)
 
     def load_scene(self, tables, occ, mlp, dist=None):
         self.load_tables(tables)

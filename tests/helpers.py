@@ -11,7 +11,11 @@ from oracle.render import inputs_from_scene
 @functools.lru_cache(maxsize=4)
 def scene_and_dist(name: str, dtype: int = 0):
     cfg = synth.CONFIGS[name](table_dtype=dtype)
-    sc = synth.make_scene(cfg)
+    if cfg.model == synth.MODEL_BAKED:
+        from synth.baked import make_baked_scene
+        sc = make_baked_scene(cfg)
+    else:
+        sc = synth.make_scene(cfg)
     dist = distance_grid_edt(sc.occ)
     return sc, dist
 
@@ -28,11 +32,15 @@ def gpu_renderer(name: str, dtype: int = 0, **overrides):
     cfg = sc.cfg
     kw = dict(resolutions=cfg.resolutions, log2_table_size=cfg.log2_table, table_dtype=dtype,
               domain=cfg.domain, roi_half=cfg.roi_half, occ_res=cfg.occ_res, step=cfg.step,
-              max_samples=cfg.max_samples, t_threshold=cfg.t_threshold)
+              max_samples=cfg.max_samples, t_threshold=cfg.t_threshold,
+              feature_model=cfg.model, coarse_res=cfg.coarse_res)
     kw.update(overrides)
     r = Renderer(**kw)
     r.load_scene(torch.from_numpy(sc.tables).cuda(), torch.from_numpy(sc.occ).cuda(),
                  torch.from_numpy(sc.mlp).cuda())
+    if cfg.model == synth.MODEL_BAKED:
+        r.load_coarse(torch.from_numpy(sc.block_index).cuda(), torch.from_numpy(sc.atlas).cuda(),
+                      sc.default)
     torch.cuda.synchronize()
     return r
 

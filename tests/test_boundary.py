@@ -56,12 +56,27 @@ def _good_desc():
     ("occ_res", 1, -2), ("occ_res", 2048, -2), ("step", 0.0, -1), ("step", -0.1, -1),
     ("step", float("nan"), -1), ("step", 1e-6, -1), ("max_samples", 0, -1),
     ("t_threshold", -1.0, -1), ("t_threshold", float("nan"), -1), ("mlp_in", 8, -7),
-    ("mlp_hidden", 64, -7),
+    ("mlp_hidden", 64, -7), ("feature_model", 2, -1), ("feature_model", -1, -1),
 ])
 def test_validate_desc_rejects(lib, field, value, code):
     d = _good_desc()
     setattr(d, field, value)
     assert lib.ngprt_validate_desc(ctypes.byref(d)) == code
+
+
+def test_validate_desc_baked_model(lib):
+    cfg = synth.baked_hd(n_fine=4)
+    d = _lib.make_desc(cfg.resolutions, cfg.log2_table, 0, cfg.domain, cfg.roi_half, cfg.occ_res,
+                       cfg.step, cfg.max_samples, cfg.t_threshold, feature_model=_lib.MODEL_BAKED,
+                       coarse_res=cfg.coarse_res)
+    assert lib.ngprt_validate_desc(ctypes.byref(d)) == 0
+    d.coarse_res = 0
+    assert lib.ngprt_validate_desc(ctypes.byref(d)) == -2
+    d.coarse_res = 4096
+    assert lib.ngprt_validate_desc(ctypes.byref(d)) == -2
+    d.coarse_res = 512
+    d.n_levels = 5                        # at most 4 fine levels (16 coarse channels)
+    assert lib.ngprt_validate_desc(ctypes.byref(d)) == -2
 
 
 def test_validate_desc_accepts_workloads(lib):
