@@ -111,9 +111,12 @@ def test_baked_empty_atlas_and_errors():
     with pytest.raises(NgprtError):                # backward: hash model only
         r.backward(go, gd, torch.zeros((len(o), 3), device="cuda"),
                    torch.zeros((r.L, r.T, 9), device="cuda"), torch.zeros((451,), device="cuda"))
-    h = gpu_renderer("tiny")
+    import ctypes
+    from paper_2407_10482_amd._lib import check
+    h = gpu_renderer("tiny")                       # a hash-model context
+    dflt = (ctypes.c_float * len(default))(*[float(x) for x in default])
     with pytest.raises(NgprtError):
-        h.load_coarse(empty_idx, empty_atlas, default)
+        check(h.lib.ngprt_load_coarse(h.ctx, 0, empty_idx.data_ptr(), None, dflt, None), h.ctx)
     torch.cuda.synchronize()
 
 
