@@ -50,6 +50,11 @@ def parse():
                    help="hash: 16 hash levels fused by softmax attention (the headline); baked: "
                         "the paper's coarse grid + sigmoid-gated fine levels")
     p.add_argument("--fine-levels", type=int, default=2, help="baked model: fine levels (1..4)")
+    p.add_argument("--occ", choices=["single", "pyramid"], default="single",
+                   help="single: one 256^3 occupancy grid + distance grid (the headline); pyramid: "
+                        "the paper's 512^3..32^3 occupancy pyramid + 256^3 distance grid")
+    p.add_argument("--no-dist", action="store_true",
+                   help="pyramid only: march without the distance grid (the ablation of Table 4)")
     p.add_argument("--mode", choices=["render", "train", "proposal"], default="render",
                    help="render: the headline; train: forward+backward+Adam steps; "
                         "proposal: learned sample-interval proposal vs plain marching")
@@ -323,12 +328,15 @@ def main():
     dtype = {"f32": 0, "bf16": 1, "fp8": 2}[args.dtype]
     baked = args.model == "baked"
     t0 = time.time()
+    pyr = args.occ == "pyramid"
     if baked:
         from synth.baked import make_baked_scene
         cfg = synth.baked_hd(table_dtype=dtype, n_fine=args.fine_levels)
+        if pyr:
+            cfg.occ_levels, cfg.occ_fine_res = 5, 512
         sc = make_baked_scene(cfg)
     else:
-        cfg = synth.hd(table_dtype=dtype)
+        cfg = synth.hd_pyramid(table_dtype=dtype) if pyr else synth.hd(table_dtype=dtype)
         sc = synth.make_scene(cfg)
     cams = synth.camera_positions(cfg)[: args.views]
     o, d, _ = synth.scene_rays(cfg, cams=cams, group=args.group)
@@ -343,9 +351,13 @@ def main():
         torch.cuda.synchronize()
         print(f"# copy probe: {nbytes} bytes read + {nbytes} bytes written", file=sys.stderr, flush=True)
         del src, dst
-    r = Renderer.from_config(cfg, dtype)
-    r.load_scene(torch.from_numpy(sc.tables).cuda(), torch.from_numpy(sc.occ).cuda(),
-                 torch.from_numpy(sc.mlp).cuda())
+    r = Renderer.from_config(cfg, dtype, use_distance=not args.no_dist)
+    r.load_tables(torch.from_numpy(sc.tables).cuda())
+    if pyr:
+        r.load_occupancy_pyramid(torch.from_numpy(sc.occ_fine).cuda())
+    else:
+        r.load_occupancy(torch.from_numpy(sc.occ).cuda())
+    r.load_mlp(torch.from_numpy(sc.mlp).cuda())
     if baked:
         r.load_coarse(torch.from_numpy(sc.block_index).cuda(), torch.from_numpy(sc.atlas).cuda(),
                       sc.default)
@@ -388,7 +400,7 @@ def main():
     gather = n_samples * per_sample
     alg_bytes = gather + 2 * n_reads + n * (24 + 12)
     achieved = alg_bytes / (ms / 1e3) / 1e9
-    traffic = None if baked else committed_traffic(DTYPE_NAME[dtype])
+    traffic = None if (baked or pyr) else committed_traffic(DTYPE_NAME[dtype])
     if baked:
         workload = (f"baked_hd: 8 views x 1920x1080 rays, coarse grid L_C=512 block-sparse "
                     f"({sc.n_blocks} of {sc.block_index.size} blocks of 8^3 vertices), {L} fine hash levels "
@@ -399,9 +411,13 @@ def main():
         workload = ("hd: 8 views x 1920x1080 rays, 16 hash levels 16..4096, 2^19 entries, "
                     f"{DTYPE_NAME[dtype]} tables, contracted scene of 200 blobs, 256^3 "
                     "occupancy + distance grid, <=1024 samples/ray, T<1e-4")
+    if pyr:
+        workload += (", occupancy pyramid 512^3..32^3" +
+                     (" without the distance grid" if args.no_dist else " + 256^3 distance grid"))
+    march_name = ("occupancy pyramid" + ("" if args.no_dist else " + distance grid")) if pyr \
+        else "plain distance-grid marching"
     res = {
-        "metric": ("1080p frames/s (baked model, plain distance-grid marching)" if baked
-                   else "1080p frames/s (plain distance-grid marching)"),
+        "metric": f"1080p frames/s ({'baked model, ' if baked else ''}{march_name})",
         "value": round(fps, 3),
         "unit": "frames/s",
         "n_gpus": 1,

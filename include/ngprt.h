@@ -97,6 +97,13 @@ typedef struct ngprt_desc {
   int32_t mlp_in, mlp_hidden, mlp_out;       /* must be 7, 16, 3 */
   int32_t feature_model;                     /* enum ngprt_feature_model */
   int32_t coarse_res;                        /* L_C of NGPRT_MODEL_BAKED, 1..2048 (else ignored) */
+  int32_t occ_levels;      /* 0: one occupancy grid of occ_res (ngprt_load_occupancy); 2..5: an
+                            * occupancy pyramid of occ_levels levels whose finest has
+                            * occ_fine_res (ngprt_load_occupancy_pyramid) */
+  int32_t occ_fine_res;    /* pyramid: finest resolution, a power of two <= 1024 with
+                            * occ_fine_res >> (occ_levels - 1) >= 32; occ_res must be one of
+                            * the pyramid's resolutions (the distance grid's) */
+  int32_t use_distance;    /* pyramid: 1 = consult the distance grid (Eq. 9), 0 = pyramid only */
 } ngprt_desc;
 
 typedef struct ngprt_ctx ngprt_ctx;
@@ -165,6 +172,23 @@ int ngprt_export_tables(ngprt_ctx* ctx, void* dev_codes, float* dev_scales, void
  * nothing is occupied (Sec. 4.3). */
 int ngprt_load_occupancy(ngprt_ctx* ctx, const uint8_t* dev_occ, const uint8_t* dev_dist,
                          void* stream);
+
+/* Multi-level occupancy (Sec. 4.3: the march that Eq. 9's s_O refers to;
+ * supplement "Real-time Rendering" item 1: five levels 512^3 ... 32^3).
+ * dev_occ_fine: uint8 [F][F][F] (F = occ_fine_res, x fastest, nonzero =
+ * occupied).  Level j (resolution F >> j) marks a voxel occupied when any of
+ * its 8 children is; the distance grid G is built from the level of
+ * resolution occ_res as in ngprt_load_occupancy.  The march reads the levels
+ * coarse to fine at each lattice point not known to be empty; a sample is
+ * taken where the finest level is occupied; otherwise the march skips the
+ * exiting level's voxel (box: to one lattice step before its exit along the
+ * ray; contracted domain: the ball inscribed in it, less voxel/1024) or, when
+ * use_distance is set and the exiting level is coarser than G, by the G rule
+ * if that skips further.  The sampled lattice points are those of an
+ * exhaustive march over the finest level.  Needs occ_levels > 0
+ * (NGPRT_E_UNSUPPORTED otherwise); ngprt_load_occupancy then returns
+ * NGPRT_E_UNSUPPORTED. */
+int ngprt_load_occupancy_pyramid(ngprt_ctx* ctx, const uint8_t* dev_occ_fine, void* stream);
 
 /* Copy the distance grid in use to dev_dist (uint8 [R^3]). */
 int ngprt_export_distance(ngprt_ctx* ctx, uint8_t* dev_dist, void* stream);

@@ -47,7 +47,7 @@ import numpy as np
 
 from .exact32 import F32, exp32, sqrt32
 from .hashgrid import corners32, corners64
-from . import baked, quant
+from . import baked, pyramid, quant
 
 BOX = 0
 CONTRACT = 1
@@ -74,6 +74,10 @@ class OracleInputs:
     block_index: Optional[np.ndarray] = None   # int32 [nb, nb, nb]
     atlas: Optional[np.ndarray] = None         # float32 [n_blocks, 8, 8, 8, C]
     coarse_default: Optional[np.ndarray] = None  # float32 [C]
+    # multi-level occupancy (Eq. 9's s_O branch): uint8 grids [O_0 (finest), O_1, ...];
+    # occ / dist are then the pyramid level of the distance grid's resolution and its G
+    pyramid: Optional[list] = None
+    use_dist: bool = True
     # derived
     stored: Optional[np.ndarray] = None     # stored codes / values [L, T, 9]
     scales: Optional[np.ndarray] = None     # float32 [L, 9] (FP8 only)
@@ -261,6 +265,7 @@ def march(inp: OracleInputs, o: np.ndarray, d: np.ndarray, naive: bool = False,
     T = np.ones(n, dtype=F32)
     nsamp = np.zeros(n, dtype=np.int64)
     nreads = np.zeros(n, dtype=np.int64)
+    nmem = np.zeros(n, dtype=np.int64)          # pyramid: grid words read
     dn2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
     dn = sqrt32(dn2)
     if inp.domain == BOX:
@@ -344,10 +349,17 @@ def march(inp: OracleInputs, o: np.ndarray, d: np.ndarray, naive: bool = False,
         q = np.clip(np.floor(u * RF), 0, R - 1).astype(np.int64)
         vflat = q[:, 0] + R * (q[:, 1] + R * q[:, 2])
         rd = ids[need]
-        nreads[rd] += 1
-        occv = inp.occ_flat[vflat[need]] != 0
-        g = inp.dist_flat[vflat[need]].astype(np.int64)
-        if not naive:
+        if inp.pyramid is not None:
+            occv = _pyramid_read(inp, rd, u[need], pos[need], tk[need], o, d, vflat[need], naive,
+                                 nreads, nmem, k, next_read if inp.domain == BOX else None,
+                                 rho if inp.domain == BOX else None,
+                                 None if inp.domain == BOX else (has_ball, ball_c, ball_r2, margin),
+                                 step, vox)
+        else:
+            nreads[rd] += 1
+            occv = inp.occ_flat[vflat[need]] != 0
+            g = inp.dist_flat[vflat[need]].astype(np.int64)
+        if not naive and inp.pyramid is None:
             if inp.domain == BOX:
                 jf = np.floor(g.astype(F32) * rho[rd])
                 jump = np.where(jf < F32(MAX_LATTICE), jf, F32(MAX_LATTICE)).astype(np.int64)
@@ -396,7 +408,49 @@ def march(inp: OracleInputs, o: np.ndarray, d: np.ndarray, naive: bool = False,
         s_T = np.zeros(0, F32)
     return dict(n_samples=nsamp.astype(np.int32), n_reads=nreads.astype(np.int32),
                 t_final32=T, s_ray=s_ray, s_k=s_k, s_t=s_t, s_pos=s_pos, s_T=s_T,
-                stopped_hi=stopped_hi)
+                stopped_hi=stopped_hi, n_mem=nmem)
+
+
+def _pyramid_read(inp, rd, u, pos, tk, o, d, vflat, naive, nreads, nmem, k, next_read, rho, ball,
+                  step, vox):
+    """Reads and skip decisions of the multi-level occupancy march at the
+    lattice points of rays rd (see oracle.pyramid); returns the sampled mask."""
+    pyr = inp.pyramid
+    R0 = pyr[0].shape[0]
+    nreads[rd] += 1                               # one marching point each
+    if naive:
+        q0 = np.clip(np.floor(u * F32(R0)), 0, R0 - 1).astype(np.int64)
+        nmem[rd] += 1
+        return pyr[0][q0[:, 2], q0[:, 1], q0[:, 0]] != 0
+    lev, reads, qx = pyramid.exit_level(pyr, u)
+    empty = lev >= 0
+    r_lev = np.where(empty, R0 >> np.maximum(lev, 0), R0)
+    use_g = inp.use_dist & empty & (r_lev < inp.R)
+    g = np.where(use_g, inp.dist_flat[vflat].astype(np.int64), 0)
+    nmem[rd] += reads + use_g                     # grid words read
+    h = F32(inp.roi_half)
+    vj = ((h - (-h)) / r_lev.astype(F32)).astype(F32)
+    if ball is None:                              # box domain: lattice jumps
+        with np.errstate(invalid="ignore"):
+            t_exit = pyramid.voxel_exit_t(o[rd], d[rd], qx, -h, vj)
+            jo = np.floor((t_exit - tk) / step)
+            jo = np.where(np.isnan(jo), F32(1.0), jo)
+            jo = np.clip(jo, 1, MAX_LATTICE).astype(np.int64)
+            jg = np.floor(g.astype(F32) * rho[rd])
+            jg = np.where(jg < F32(MAX_LATTICE), jg, F32(MAX_LATTICE)).astype(np.int64)
+        jg = np.where(use_g & (g > 0), jg, 0)
+        jump = np.maximum(jo, jg)
+        next_read[rd[empty]] = k + jump[empty]
+    else:                                         # contracted domain: known-empty balls
+        has_ball, ball_c, ball_r2, margin = ball
+        r_o = pyramid.inscribed_radius(pos, qx, -h, vj) - margin
+        r_g = np.where(use_g & (g > 0), g.astype(F32) * vox - margin, F32(-np.inf)).astype(F32)
+        rb = np.maximum(r_o, r_g).astype(F32)
+        upd = empty & (rb > 0)
+        has_ball[rd] = upd
+        ball_r2[rd[upd]] = (rb * rb)[upd]
+        ball_c[rd[upd]] = pos[upd]
+    return ~empty
 
 
 def mlp64(params: np.ndarray, x: np.ndarray, dims=(7, 16, 16, 3)) -> np.ndarray:
@@ -453,14 +507,16 @@ def render(inp: OracleInputs, o: np.ndarray, d: np.ndarray, naive: bool = False,
     return RenderResult(n_samples=m["n_samples"], n_reads=m["n_reads"],
                         t_final32=m["t_final32"], t_final=T, c_d=c_d, feat=feat,
                         depth=depth, rgb=rgb, s_ray=m["s_ray"], s_k=m["s_k"],
-                        s_t=m["s_t"], s_pos=m["s_pos"], extra={"s_T": m["s_T"]})
+                        s_t=m["s_t"], s_pos=m["s_pos"], extra={"s_T": m["s_T"], "n_mem": m["n_mem"]})
 
 
 def inputs_from_scene(scene, dist: np.ndarray, dtype: int = DT_F32) -> OracleInputs:
     cfg = scene.cfg
     extra = {}
+    if getattr(scene, "occ_fine", None) is not None:
+        extra.update(pyramid=pyramid.build_pyramid(scene.occ_fine, cfg.occ_levels))
     if getattr(scene, "block_index", None) is not None:
-        extra = dict(coarse_res=cfg.coarse_res, block_index=scene.block_index, atlas=scene.atlas,
+        extra.update(coarse_res=cfg.coarse_res, block_index=scene.block_index, atlas=scene.atlas,
                      coarse_default=scene.default)
     return OracleInputs(tables=scene.tables, occ=scene.occ, dist=dist, mlp=scene.mlp,
                         resolutions=list(cfg.resolutions), domain=cfg.domain,

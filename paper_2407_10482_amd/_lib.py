@@ -35,6 +35,9 @@ class NgprtDesc(ctypes.Structure):
         ("mlp_out", ctypes.c_int32),
         ("feature_model", ctypes.c_int32),
         ("coarse_res", ctypes.c_int32),
+        ("occ_levels", ctypes.c_int32),
+        ("occ_fine_res", ctypes.c_int32),
+        ("use_distance", ctypes.c_int32),
     ]
 
 
@@ -57,6 +60,7 @@ SIGNATURES = [
     ("ngprt_load_coarse", ctypes.c_int, [_P, _I64, _P, _P, _P, _P]),
     ("ngprt_load_occupancy", ctypes.c_int, [_P, _P, _P, _P]),
     ("ngprt_export_distance", ctypes.c_int, [_P, _P, _P]),
+    ("ngprt_load_occupancy_pyramid", ctypes.c_int, [_P, _P, _P]),
     ("ngprt_load_mlp", ctypes.c_int, [_P, _P, _P]),
     ("ngprt_render", ctypes.c_int, [_P, _I64, _P, _P, ctypes.POINTER(NgprtOutputs), _P]),
     ("ngprt_debug_eval_points", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P]),
@@ -118,7 +122,7 @@ def check(code: int, ctx=None):
 
 def make_desc(resolutions, log2_table_size, table_dtype, domain, roi_half, occ_res, step,
               max_samples, t_threshold, mlp=(7, 16, 3), feature_model=MODEL_HASH,
-              coarse_res=0) -> NgprtDesc:
+              coarse_res=0, occ_levels=0, occ_fine_res=0, use_distance=1) -> NgprtDesc:
     d = NgprtDesc()
     d.n_levels = len(resolutions)
     for i, r in enumerate(resolutions[:MAX_LEVELS]):
@@ -134,4 +138,7 @@ def make_desc(resolutions, log2_table_size, table_dtype, domain, roi_half, occ_r
     d.mlp_in, d.mlp_hidden, d.mlp_out = mlp
     d.feature_model = int(feature_model)
     d.coarse_res = int(coarse_res)
+    d.occ_levels = int(occ_levels)
+    d.occ_fine_res = int(occ_fine_res)
+    d.use_distance = int(use_distance)
     return d

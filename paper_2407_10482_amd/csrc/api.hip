@@ -50,6 +50,12 @@ SceneArgs scene_args(const ngprt_ctx* ctx) {
   S.thr = d.t_threshold;
   S.max_samples = d.max_samples;
   S.lshift = ctx->logit_shift;
+  S.pyr_n = d.occ_levels > 0 ? d.occ_levels : 0;
+  S.use_dist = d.use_distance;
+  for (int j = 0; j < kMaxPyr; ++j) {
+    S.pyrR[j] = j < S.pyr_n ? (d.occ_fine_res >> j) : 32;
+    S.pyr[j] = j < S.pyr_n ? ctx->pyr[j] : nullptr;
+  }
   S.model = d.feature_model;
   if (d.feature_model == NGPRT_MODEL_BAKED) {
     S.LC = d.coarse_res;
@@ -117,6 +123,16 @@ int ngprt_validate_desc(const ngprt_desc* d) {
     if (d->n_levels > 4) return NGPRT_E_SHAPE;
     if (d->coarse_res < 1 || d->coarse_res > 2048) return NGPRT_E_SHAPE;
   }
+  if (d->occ_levels != 0) {
+    const int F = d->occ_fine_res;
+    if (d->occ_levels < 2 || d->occ_levels > 5) return NGPRT_E_SHAPE;
+    if (F < 32 || F > 1024 || (F & (F - 1)) != 0) return NGPRT_E_SHAPE;
+    if ((F >> (d->occ_levels - 1)) < 32) return NGPRT_E_SHAPE;
+    bool found = false;
+    for (int j = 0; j < d->occ_levels; ++j) found = found || (F >> j) == d->occ_res;
+    if (!found) return NGPRT_E_SHAPE;
+    if (d->use_distance != 0 && d->use_distance != 1) return NGPRT_E_INVALID_ARG;
+  }
   return NGPRT_OK;
 }
 
@@ -136,6 +152,8 @@ void ngprt_destroy(ngprt_ctx* ctx) {
   if (ctx->prop_grad) (void)hipFree(ctx->prop_grad);
   if (ctx->cidx) (void)hipFree(ctx->cidx);
   if (ctx->catlas) (void)hipFree(ctx->catlas);
+  for (int j = 0; j < 5; ++j)
+    if (ctx->pyr[j]) (void)hipFree(ctx->pyr[j]);
   if (switched) (void)hipSetDevice(cur);
   delete ctx;
 }
@@ -242,7 +260,20 @@ int ngprt_export_tables(ngprt_ctx* ctx, void* dev_codes, float* dev_scales, void
 int ngprt_load_occupancy(ngprt_ctx* ctx, const uint8_t* dev_occ, const uint8_t* dev_dist, void* stream) {
   if (!ctx) return NGPRT_E_INVALID_ARG;
   if (!dev_occ) return fail(ctx, NGPRT_E_INVALID_ARG, "dev_occ is NULL");
+  if (ctx->desc.occ_levels != 0)
+    return fail(ctx, NGPRT_E_UNSUPPORTED, "the context marches an occupancy pyramid");
   int rc = launch_build_distance(ctx, dev_occ, dev_dist, (hipStream_t)stream);
+  if (rc == NGPRT_OK) ctx->occ_loaded = true;
+  return rc;
+}
+
+int ngprt_load_occupancy_pyramid(ngprt_ctx* ctx, const uint8_t* dev_occ_fine, void* stream) {
+  if (!ctx) return NGPRT_E_INVALID_ARG;
+  if (ctx->desc.occ_levels == 0)
+    return fail(ctx, NGPRT_E_UNSUPPORTED, "the context marches a single occupancy grid");
+  if (!dev_occ_fine) return fail(ctx, NGPRT_E_INVALID_ARG, "dev_occ_fine is NULL");
+  ctx->occ_loaded = false;
+  int rc = launch_build_pyramid(ctx, dev_occ_fine, (hipStream_t)stream);
   if (rc == NGPRT_OK) ctx->occ_loaded = true;
   return rc;
 }

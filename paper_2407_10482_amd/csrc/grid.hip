@@ -165,4 +165,89 @@ int launch_export_distance(ngprt_ctx* ctx, uint8_t* out, hipStream_t st) {
   return check_launch(ctx, "unpack_dist_kernel");
 }
 
+// ---------------------------------------------------------------------------
+// Multi-level occupancy: bit grids (x fastest, 32 voxels per word; R is a
+// multiple of 32, so voxel v sits in word v >> 5 at bit v & 31).
+__global__ void pyr_pack_kernel(const uint8_t* __restrict__ occ, uint32_t* __restrict__ out,
+                                int64_t n_words) {
+  const int64_t w = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (w >= n_words) return;
+  const uint8_t* src = occ + w * 32;
+  uint32_t bits = 0;
+  for (int i = 0; i < 32; ++i) bits |= (src[i] != 0 ? 1u : 0u) << i;
+  out[w] = bits;
+}
+
+// level of resolution Rc from the level of resolution 2 Rc: a voxel is
+// occupied when any of its 2x2x2 children is
+__global__ void pyr_pool_kernel(const uint32_t* __restrict__ fine, uint32_t* __restrict__ coarse,
+                                int Rc) {
+  const int64_t wpr = Rc >> 5;                       // words per coarse row
+  const int64_t n_words = int64_t(Rc) * Rc * wpr;
+  const int64_t w = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (w >= n_words) return;
+  const int64_t xw = w % wpr;
+  const int64_t y = (w / wpr) % Rc;
+  const int64_t z = w / (wpr * Rc);
+  const int64_t Rf = 2 * int64_t(Rc), wpr_f = Rf >> 5;
+  uint64_t acc = 0;
+  for (int dz = 0; dz < 2; ++dz)
+    for (int dy = 0; dy < 2; ++dy) {
+      const int64_t row = ((2 * z + dz) * Rf + (2 * y + dy)) * wpr_f;
+      acc |= uint64_t(fine[row + 2 * xw]) | (uint64_t(fine[row + 2 * xw + 1]) << 32);
+    }
+  uint32_t bits = 0;
+  for (int i = 0; i < 32; ++i)
+    if ((acc >> (2 * i)) & 3u) bits |= 1u << i;
+  coarse[w] = bits;
+}
+
+__global__ void pyr_unpack_kernel(const uint32_t* __restrict__ bits, uint8_t* __restrict__ out, int64_t n) {
+  const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  out[v] = uint8_t((bits[v >> 5] >> (v & 31)) & 1u);
+}
+
+int launch_build_pyramid(ngprt_ctx* ctx, const uint8_t* occ_fine, hipStream_t st) {
+  const ngprt_desc& d = ctx->desc;
+  const int nl = d.occ_levels;
+  for (int j = 0; j < nl; ++j) {
+    if (!ctx->pyr[j]) {
+      const int64_t Rj = int64_t(d.occ_fine_res) >> j;
+      if (hipMalloc((void**)&ctx->pyr[j], size_t(Rj * Rj * Rj / 32) * sizeof(uint32_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, NGPRT_E_ALLOC, "occupancy pyramid allocation failed");
+      }
+    }
+  }
+  const int64_t R0 = d.occ_fine_res;
+  const int64_t w0 = R0 * R0 * R0 / 32;
+  hipLaunchKernelGGL(pyr_pack_kernel, dim3(blocks_for(w0, 256)), dim3(256), 0, st, occ_fine, ctx->pyr[0], w0);
+  int rc = check_launch(ctx, "pyr_pack_kernel");
+  for (int j = 1; j < nl && rc == NGPRT_OK; ++j) {
+    const int Rc = int(R0 >> j);
+    const int64_t wc = int64_t(Rc) * Rc * Rc / 32;
+    hipLaunchKernelGGL(pyr_pool_kernel, dim3(blocks_for(wc, 256)), dim3(256), 0, st, ctx->pyr[j - 1],
+                       ctx->pyr[j], Rc);
+    rc = check_launch(ctx, "pyr_pool_kernel");
+  }
+  if (rc) return rc;
+  // the distance grid comes from the pyramid level of its resolution
+  int jg = -1;
+  for (int j = 0; j < nl; ++j)
+    if ((R0 >> j) == d.occ_res) jg = j;
+  if (jg < 0) return fail(ctx, NGPRT_E_SHAPE, "occ_res is not a pyramid resolution");
+  const int64_t n = int64_t(d.occ_res) * d.occ_res * d.occ_res;
+  uint8_t* tmp = nullptr;
+  if (hipMallocAsync((void**)&tmp, size_t(n), st) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, NGPRT_E_ALLOC, "pyramid scratch allocation failed");
+  }
+  hipLaunchKernelGGL(pyr_unpack_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, ctx->pyr[jg], tmp, n);
+  rc = check_launch(ctx, "pyr_unpack_kernel");
+  if (rc == NGPRT_OK) rc = launch_build_distance(ctx, tmp, nullptr, st);
+  (void)hipFreeAsync(tmp, st);
+  return rc;
+}
+
 }  // namespace ngprt

@@ -16,6 +16,7 @@ enum { DOM_BOX = 0, DOM_CONTRACT = 1 };
 constexpr int kMaxLevels = NGPRT_MAX_LEVELS;
 constexpr int kMlpParams = 451;
 constexpr int kMaxLattice = 1 << 16;   // hard bound on lattice points per ray
+constexpr int kMaxPyr = 5;             // occupancy pyramid levels
 
 // floats per coarse atlas row of the baked model: 8 + 2L channels rounded up
 // to whole float4 loads (12 for L <= 2, 16 for L = 3, 4)
@@ -51,6 +52,11 @@ struct SceneArgs {
   const int32_t* cidx;            // [nb^3] atlas row of each block or -1
   const float* catlas;            // [n_blocks][512][Cpad]
   float cdef[16];                 // value of every vertex of an empty block
+  // multi-level occupancy (pyr_n > 0): bit grids, level j of resolution pyrR[j]
+  int pyr_n;
+  int use_dist;                   // consult the distance grid (Eq. 9) when the exiting level is coarser
+  int pyrR[kMaxPyr];
+  const uint32_t* pyr[kMaxPyr];   // [R^3 / 32] words, x fastest, bit x & 31
 };
 
 struct RayOut {
@@ -88,6 +94,8 @@ struct ngprt_ctx {
   int64_t n_blocks = 0;
   float cdef[16] = {};
   bool coarse_loaded = false;
+  uint32_t* pyr[5] = {};      // occupancy pyramid bit grids
+  bool pyr_loaded = false;
   bool tables_loaded = false;
   bool occ_loaded = false;
   bool mlp_loaded = false;
@@ -112,6 +120,7 @@ int launch_march(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, int3
                  int32_t* sk, int32_t* ns, int32_t* nr, int naive, hipStream_t s);
 int launch_backward(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const float* grad_rgb,
                     float* gtab, float* gmlp, hipStream_t s);
+int launch_build_pyramid(ngprt_ctx* ctx, const uint8_t* occ_fine, hipStream_t s);
 int launch_pack_atlas(ngprt_ctx* ctx, const float* atlas, int64_t n_blocks, hipStream_t s);
 int launch_gather_probe(ngprt_ctx* ctx, int64_t n, uint32_t seed, int pairs, float* out, hipStream_t s);
 int launch_adam(int64_t n, float* p, const float* g, float* m, float* v, int32_t step, float lr,

@@ -139,6 +139,80 @@ __device__ __forceinline__ bool march_next(const SceneArgs& S, MarchState& m, bo
     m.k = kcur + 1;
     if (!need) continue;
     const uint32_t v = voxel_of(S, p, u);
+    if (S.pyr_n > 0) {
+      // multi-level occupancy (Eq. 9's s_O branch): levels coarse to fine;
+      // reads counts marching points (lattice points checked), whatever the
+      // number of levels read there
+      ++reads;
+      int lev = -1;
+      int qe[3] = {0, 0, 0};
+      for (int j = naive ? 0 : S.pyr_n - 1; j >= 0; --j) {
+        const int Rj = S.pyrR[j];
+        int q[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          int i = (int)floorf(u[a] * (float)Rj);
+          q[a] = i < 0 ? 0 : (i > Rj - 1 ? Rj - 1 : i);
+        }
+        const uint32_t w =
+            S.pyr[j][(size_t(q[2]) * Rj + q[1]) * size_t(Rj >> 5) + size_t(q[0] >> 5)];
+        if (!((w >> (q[0] & 31)) & 1u)) {
+          lev = j;
+          qe[0] = q[0]; qe[1] = q[1]; qe[2] = q[2];
+          break;
+        }
+      }
+      if (lev < 0) {
+        ts = tcur;
+        ks = kcur;
+        if (!naive && DOM == DOM_CONTRACT) m.has_ball = false;
+        return true;
+      }
+      if (naive) continue;
+      const int Rl = S.pyrR[lev];
+      const bool use_g = S.use_dist && Rl < S.R;
+      uint32_t g = 0;
+      if (use_g) g = S.grid[v] & 0xFFu;
+      const float vj = (-S.lo - S.lo) / (float)Rl;
+      if (DOM == DOM_BOX) {
+        float te = __int_as_float(0x7F800000);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          if (m.d[a] != 0.0f) {
+            const float b = S.lo + (float)(qe[a] + (m.d[a] > 0.0f ? 1 : 0)) * vj;
+            te = fminf(te, (b - m.o[a]) / m.d[a]);
+          }
+        }
+        const float jo = floorf((te - tcur) / S.step);
+        int jump = jo >= 1.0f ? (jo < (float)kMaxLattice ? (int)jo : kMaxLattice) : 1;
+        if (use_g && g > 0) {
+          const float jf = floorf((float)g * m.rho);
+          const int jg = jf < (float)kMaxLattice ? (int)jf : kMaxLattice;
+          jump = jg > jump ? jg : jump;
+        }
+        m.k = kcur + jump;
+      } else {
+        float r = __int_as_float(0x7F800000);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const float lower = S.lo + (float)qe[a] * vj;
+          const float upper = S.lo + (float)(qe[a] + 1) * vj;
+          r = fminf(r, fminf(p[a] - lower, upper - p[a]));
+        }
+        const float margin = S.vox * 0.0009765625f;
+        const float ro = r - margin;
+        const float rg = (use_g && g > 0) ? (float)g * S.vox - margin : -__int_as_float(0x7F800000);
+        const float rb = fmaxf(ro, rg);
+        if (rb > 0.0f) {
+          m.br2 = rb * rb;
+          m.bc[0] = p[0]; m.bc[1] = p[1]; m.bc[2] = p[2];
+          m.has_ball = true;
+        } else {
+          m.has_ball = false;
+        }
+      }
+      continue;
+    }
     const uint32_t word = S.grid[v];
     ++reads;
     if (word & 0x100u) {

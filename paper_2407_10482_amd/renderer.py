@@ -38,7 +38,8 @@ class Renderer:
     def __init__(self, resolutions: Sequence[int], log2_table_size: int, table_dtype: int = F32,
                  domain: int = ROI_BOX, roi_half: float = 1.0, occ_res: int = 64,
                  step: float = 1.0 / 256.0, max_samples: int = 1024, t_threshold: float = 1e-4,
-                 feature_model: int = MODEL_HASH, coarse_res: int = 0):
+                 feature_model: int = MODEL_HASH, coarse_res: int = 0, occ_levels: int = 0,
+                 occ_fine_res: int = 0, use_distance: bool = True):
         self.lib = load_library()
         self.resolutions = list(resolutions)
         self.L = len(self.resolutions)
@@ -47,18 +48,22 @@ class Renderer:
         self.table_dtype = table_dtype
         self.feature_model = feature_model
         self.coarse_res = coarse_res
+        self.occ_fine_res = occ_fine_res
         self.desc = _lib.make_desc(resolutions, log2_table_size, table_dtype, domain, roi_half,
                                    occ_res, step, max_samples, t_threshold,
-                                   feature_model=feature_model, coarse_res=coarse_res)
+                                   feature_model=feature_model, coarse_res=coarse_res,
+                                   occ_levels=occ_levels, occ_fine_res=occ_fine_res,
+                                   use_distance=int(bool(use_distance)))
         ctx = ctypes.c_void_p()
         check(self.lib.ngprt_create(ctypes.byref(self.desc), ctypes.byref(ctx)))
         self.ctx = ctx
 
     @classmethod
-    def from_config(cls, cfg, table_dtype: Optional[int] = None) -> "Renderer":
+    def from_config(cls, cfg, table_dtype: Optional[int] = None, use_distance: bool = True) -> "Renderer":
         return cls(cfg.resolutions, cfg.log2_table, cfg.table_dtype if table_dtype is None else table_dtype,
                    cfg.domain, cfg.roi_half, cfg.occ_res, cfg.step, cfg.max_samples, cfg.t_threshold,
-                   getattr(cfg, "model", MODEL_HASH), getattr(cfg, "coarse_res", 0))
+                   getattr(cfg, "model", MODEL_HASH), getattr(cfg, "coarse_res", 0),
+                   getattr(cfg, "occ_levels", 0), getattr(cfg, "occ_fine_res", 0), use_distance)
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -81,6 +86,11 @@ class Renderer:
         if dist is not None:
             _dev(dist, torch.uint8, (self.R, self.R, self.R), "dist")
         check(self.lib.ngprt_load_occupancy(self.ctx, _ptr(occ), _ptr(dist), _stream()), self.ctx)
+
+    def load_occupancy_pyramid(self, occ_fine: torch.Tensor):
+        F = self.occ_fine_res
+        _dev(occ_fine, torch.uint8, (F, F, F), "occ_fine")
+        check(self.lib.ngprt_load_occupancy_pyramid(self.ctx, _ptr(occ_fine), _stream()), self.ctx)
 
     def load_mlp(self, params: torch.Tensor):
         _dev(params, torch.float32, (451,), "mlp params")

@@ -3,7 +3,8 @@ the oracle: workload configs, scene assets and camera rays.  Holds no
 rendering arithmetic."""
 from .configs import (CONFIGS, CONTRACT_STEP, DOMAIN_BOX, DOMAIN_CONTRACT, DTYPE_BF16,
                       DTYPE_F32, DTYPE_FP8, MODEL_BAKED, MODEL_HASH, SceneConfig, baked_hd,
-                      baked_tiny, geometric_resolutions, hd, tiny, train_large)
+                      baked_tiny, geometric_resolutions, hd, hd_pyramid, tiny, tiny_pyramid,
+                      train_large)
 from .scene import Scene, camera_positions, make_scene
 from .cameras import pinhole_rays, random_sphere_cameras, scene_rays, tile_order
 

@@ -22,6 +22,7 @@ channel 8 unused (0): sigma^ ~ N(0, 0.5^2), colour ~ N(0, 0.2^2), specular
 """
 from __future__ import annotations
 
+import dataclasses
 from dataclasses import dataclass
 
 import numpy as np
@@ -41,6 +42,7 @@ class BakedScene:
     default: np.ndarray        # float32 [C]
     blob_mu: np.ndarray
     blob_sigma: np.ndarray
+    occ_fine: np.ndarray = None   # uint8 [F, F, F] finest pyramid level (occ_levels > 0)
 
     @property
     def n_blocks(self) -> int:
@@ -86,7 +88,15 @@ def make_baked_scene(cfg: SceneConfig, seed=None) -> BakedScene:
         raise ValueError("config is not a baked-model config")
     rng_geo = np.random.default_rng(cfg.seed)
     mu, sig = _blobs(cfg, rng_geo)
-    occ = occupancy_from_blobs(cfg, mu, sig)
+    occ_fine = None
+    if cfg.occ_levels > 0:
+        occ_fine = occupancy_from_blobs(dataclasses.replace(cfg, occ_res=cfg.occ_fine_res), mu, sig)
+        occ = occ_fine
+        while occ.shape[0] > cfg.occ_res:
+            R = occ.shape[0] // 2
+            occ = occ.reshape(R, 2, R, 2, R, 2).max(axis=(1, 3, 5)).astype(np.uint8)
+    else:
+        occ = occupancy_from_blobs(cfg, mu, sig)
     nb = n_blocks_per_axis(cfg.coarse_res)
     # candidate blocks: within 4 standard deviations of some blob
     Lc = cfg.coarse_res
@@ -130,4 +140,4 @@ def make_baked_scene(cfg: SceneConfig, seed=None) -> BakedScene:
     tables[:, :, 4:8] = rng_val.normal(0.0, 0.5, size=(L, T, 4))
     mlp = make_mlp(cfg, rng_val)
     return BakedScene(cfg=cfg, tables=tables, occ=occ, mlp=mlp, block_index=index, atlas=atlas,
-                      default=default, blob_mu=mu, blob_sigma=sig)
+                      default=default, blob_mu=mu, blob_sigma=sig, occ_fine=occ_fine)

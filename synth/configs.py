@@ -82,6 +82,8 @@ class SceneConfig:
     resolutions: List[int] = field(default_factory=list)
     model: int = MODEL_HASH
     coarse_res: int = 0        # L_C of the baked model (vertex lattice L_C + 1 per axis)
+    occ_levels: int = 0        # > 0: occupancy pyramid of this many levels, finest occ_fine_res
+    occ_fine_res: int = 0
 
     def __post_init__(self):
         if not self.resolutions:
@@ -166,5 +168,24 @@ def baked_hd(seed: int = 0, table_dtype: int = DTYPE_F32, n_fine: int = 2) -> Sc
     return cfg
 
 
+def tiny_pyramid(seed: int = 0, table_dtype: int = DTYPE_F32) -> SceneConfig:
+    """The tiny scene marched with a 3-level occupancy pyramid 128^3 .. 32^3
+    (samples where the 128^3 level is occupied) and the distance grid at 64^3."""
+    cfg = tiny(seed, table_dtype)
+    cfg.name = "tiny_pyramid"
+    cfg.occ_levels, cfg.occ_fine_res = 3, 128
+    return cfg
+
+
+def hd_pyramid(seed: int = 0, table_dtype: int = DTYPE_F32) -> SceneConfig:
+    """The hd scene marched as in the paper's renderer (supplement "Real-time
+    Rendering" item 1; Sec. 4.3): occupancy pyramid 512^3 .. 32^3 (5 levels)
+    plus the 256^3 distance grid."""
+    cfg = hd(seed, table_dtype)
+    cfg.name = "hd_pyramid"
+    cfg.occ_levels, cfg.occ_fine_res = 5, 512
+    return cfg
+
+
 CONFIGS = {"tiny": tiny, "hd": hd, "train_large": train_large, "baked_tiny": baked_tiny,
-           "baked_hd": baked_hd}
+           "baked_hd": baked_hd, "tiny_pyramid": tiny_pyramid, "hd_pyramid": hd_pyramid}

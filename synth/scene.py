@@ -24,6 +24,7 @@ W0[16][7], b0[16], W1[16][16], b1[16], W2[3][16], b2[3].
 """
 from __future__ import annotations
 
+import dataclasses
 from dataclasses import dataclass
 from typing import Optional
 
@@ -40,6 +41,7 @@ class Scene:
     mlp: np.ndarray           # float32 [n_params]
     blob_mu: np.ndarray       # float64 [B, 3]
     blob_sigma: np.ndarray    # float64 [B]
+    occ_fine: Optional[np.ndarray] = None   # uint8 [F, F, F] finest pyramid level (occ_levels > 0)
 
     @property
     def grid_lo(self) -> float:
@@ -131,8 +133,20 @@ def make_scene(cfg: SceneConfig, seed: Optional[int] = None) -> Scene:
     table values and MLP; blob layout and occupancy always come from cfg.seed)."""
     rng_geo = np.random.default_rng(cfg.seed)
     mu, sig = _blobs(cfg, rng_geo)
-    occ = occupancy_from_blobs(cfg, mu, sig)
+    occ_fine = None
+    if cfg.occ_levels > 0:
+        # the finest pyramid level from the blobs; the grid at occ_res (the
+        # distance grid's) is its OR-pooled level
+        fine_cfg = dataclasses.replace(cfg, occ_res=cfg.occ_fine_res)
+        occ_fine = occupancy_from_blobs(fine_cfg, mu, sig)
+        occ = occ_fine
+        while occ.shape[0] > cfg.occ_res:
+            R = occ.shape[0] // 2
+            occ = occ.reshape(R, 2, R, 2, R, 2).max(axis=(1, 3, 5)).astype(np.uint8)
+    else:
+        occ = occupancy_from_blobs(cfg, mu, sig)
     rng_val = np.random.default_rng(1_000_003 + (cfg.seed if seed is None else seed))
     tables = make_tables(cfg, rng_val)
     mlp = make_mlp(cfg, rng_val)
-    return Scene(cfg=cfg, tables=tables, occ=occ, mlp=mlp, blob_mu=mu, blob_sigma=sig)
+    return Scene(cfg=cfg, tables=tables, occ=occ, mlp=mlp, blob_mu=mu, blob_sigma=sig,
+                 occ_fine=occ_fine)

@@ -33,11 +33,16 @@ def gpu_renderer(name: str, dtype: int = 0, **overrides):
     kw = dict(resolutions=cfg.resolutions, log2_table_size=cfg.log2_table, table_dtype=dtype,
               domain=cfg.domain, roi_half=cfg.roi_half, occ_res=cfg.occ_res, step=cfg.step,
               max_samples=cfg.max_samples, t_threshold=cfg.t_threshold,
-              feature_model=cfg.model, coarse_res=cfg.coarse_res)
+              feature_model=cfg.model, coarse_res=cfg.coarse_res, occ_levels=cfg.occ_levels,
+              occ_fine_res=cfg.occ_fine_res)
     kw.update(overrides)
     r = Renderer(**kw)
-    r.load_scene(torch.from_numpy(sc.tables).cuda(), torch.from_numpy(sc.occ).cuda(),
-                 torch.from_numpy(sc.mlp).cuda())
+    r.load_tables(torch.from_numpy(sc.tables).cuda())
+    if kw["occ_levels"]:
+        r.load_occupancy_pyramid(torch.from_numpy(sc.occ_fine).cuda())
+    else:
+        r.load_occupancy(torch.from_numpy(sc.occ).cuda())
+    r.load_mlp(torch.from_numpy(sc.mlp).cuda())
     if cfg.model == synth.MODEL_BAKED:
         r.load_coarse(torch.from_numpy(sc.block_index).cuda(), torch.from_numpy(sc.atlas).cuda(),
                       sc.default)
