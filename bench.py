@@ -53,6 +53,9 @@ def parse():
     p.add_argument("--occ", choices=["single", "pyramid"], default="single",
                    help="single: one 256^3 occupancy grid + distance grid (the headline); pyramid: "
                         "the paper's 512^3..32^3 occupancy pyramid + 256^3 distance grid")
+    p.add_argument("--mlp", choices=["plain", "view"], default="plain",
+                   help="plain: deferred MLP 7-16-16-3 of (C_d, F) (the headline); view: the "
+                        "view-dependent MLP_psi 23-64-64-3 of (C_d, F, SH(d))")
     p.add_argument("--no-dist", action="store_true",
                    help="pyramid only: march without the distance grid (the ablation of Table 4)")
     p.add_argument("--mode", choices=["render", "train", "proposal"], default="render",
@@ -337,6 +340,8 @@ def main():
         sc = make_baked_scene(cfg)
     else:
         cfg = synth.hd_pyramid(table_dtype=dtype) if pyr else synth.hd(table_dtype=dtype)
+        if args.mlp == "view":
+            cfg.mlp_dims = (23, 64, 64, 3)
         sc = synth.make_scene(cfg)
     cams = synth.camera_positions(cfg)[: args.views]
     o, d, _ = synth.scene_rays(cfg, cams=cams, group=args.group)
@@ -371,6 +376,9 @@ def main():
     n_reads = int(aux["n_reads"].sum().item())
     dist = r.export_distance().cpu().numpy()
     out = {"rgb": torch.empty((n, 3), dtype=torch.float32, device="cuda")}
+    if r.view_mlp:      # MLP_psi runs as a second pass over the C_d and F outputs
+        out.update(c_d=torch.empty((n, 3), dtype=torch.float32, device="cuda"),
+                   feat=torch.empty((n, 4), dtype=torch.float32, device="cuda"))
     for _ in range(args.warmup):
         r.render(go, gd, out=out)
     torch.cuda.synchronize()
@@ -400,7 +408,7 @@ def main():
     gather = n_samples * per_sample
     alg_bytes = gather + 2 * n_reads + n * (24 + 12)
     achieved = alg_bytes / (ms / 1e3) / 1e9
-    traffic = None if (baked or pyr) else committed_traffic(DTYPE_NAME[dtype])
+    traffic = None if (baked or pyr or args.mlp == "view") else committed_traffic(DTYPE_NAME[dtype])
     if baked:
         workload = (f"baked_hd: 8 views x 1920x1080 rays, coarse grid L_C=512 block-sparse "
                     f"({sc.n_blocks} of {sc.block_index.size} blocks of 8^3 vertices), {L} fine hash levels "
@@ -416,6 +424,9 @@ def main():
                      (" without the distance grid" if args.no_dist else " + 256^3 distance grid"))
     march_name = ("occupancy pyramid" + ("" if args.no_dist else " + distance grid")) if pyr \
         else "plain distance-grid marching"
+    if args.mlp == "view":
+        march_name += ", view-dependent MLP"
+        workload += ", view-dependent MLP 23-64-64-3 with SH(d) as a second pass"
     res = {
         "metric": f"1080p frames/s ({'baked model, ' if baked else ''}{march_name})",
         "value": round(fps, 3),

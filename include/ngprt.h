@@ -94,7 +94,9 @@ typedef struct ngprt_desc {
   float step;                                /* lattice step (box: world units; contract: contracted units) */
   int32_t max_samples;                       /* cap on evaluated samples per ray, >= 1 */
   float t_threshold;                         /* stop once T < t_threshold; 0 disables */
-  int32_t mlp_in, mlp_hidden, mlp_out;       /* must be 7, 16, 3 */
+  int32_t mlp_in, mlp_hidden, mlp_out;       /* 7, 16, 3: the deferred MLP of C_d, F;
+                                              * 23, 64, 3: the view-dependent MLP_psi of
+                                              * C_d, F and SH(d) (see ngprt_load_mlp) */
   int32_t feature_model;                     /* enum ngprt_feature_model */
   int32_t coarse_res;                        /* L_C of NGPRT_MODEL_BAKED, 1..2048 (else ignored) */
   int32_t occ_levels;      /* 0: one occupancy grid of occ_res (ngprt_load_occupancy); 2..5: an
@@ -194,7 +196,15 @@ int ngprt_load_occupancy_pyramid(ngprt_ctx* ctx, const uint8_t* dev_occ_fine, vo
 int ngprt_export_distance(ngprt_ctx* ctx, uint8_t* dev_dist, void* stream);
 
 /* Load the deferred MLP (Eq. 5): float32 W0[16][7], b0[16], W1[16][16],
- * b1[16], W2[3][16], b2[3] (451 values, row-major, out x in). */
+ * b1[16], W2[3][16], b2[3] (451 values, row-major, out x in), input
+ * [C_d, F].  With mlp_hidden = 64 it is the view-dependent MLP_psi (Eq. 5;
+ * supplement "Network Design"): W0[64][23], b0[64], W1[64][64], b1[64],
+ * W2[3][64], b2[3] (5891 values), input [C_d, F, SH(d)] with SH(d) the 16
+ * real spherical harmonics of degrees 0..3 of the normalised ray direction
+ * (orthonormal, no Condon-Shortley phase; order l = 0..3, m = -l..l; zero for
+ * a zero or non-finite direction).  That MLP runs as a pass after the march
+ * over the C_d and F outputs, so ngprt_render / ngprt_render_proposal then
+ * need out->c_d and out->feat (NGPRT_E_INVALID_ARG otherwise). */
 int ngprt_load_mlp(ngprt_ctx* ctx, const float* dev_params, void* stream);
 
 /* Render n_rays rays.  dev_origins, dev_dirs: float32 [n][3] (directions

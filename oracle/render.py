@@ -47,7 +47,7 @@ import numpy as np
 
 from .exact32 import F32, exp32, sqrt32
 from .hashgrid import corners32, corners64
-from . import baked, pyramid, quant
+from . import baked, pyramid, quant, sh
 
 BOX = 0
 CONTRACT = 1
@@ -469,6 +469,14 @@ def mlp64(params: np.ndarray, x: np.ndarray, dims=(7, 16, 16, 3)) -> np.ndarray:
     return a2 @ W2.T + b2
 
 
+def deferred_mlp(inp: OracleInputs, c_d, feat, d):
+    """MLP(C_d, F) or, with a 64-unit hidden layer, the view-dependent
+    MLP_psi(C_d, F, SH(d)) (Eq. 5)."""
+    if tuple(inp.mlp_dims) == sh.DIMS_VIEW:
+        return sh.mlp_view64(inp.mlp, c_d, feat, np.asarray(d, np.float64))
+    return mlp64(inp.mlp, np.concatenate([c_d, feat], axis=1), inp.mlp_dims)
+
+
 def composite64(inp: OracleInputs, n: int, s_ray, s_t, fused):
     """Front-to-back compositing of decided samples (float64)."""
     sigma = np.exp(fused[:, 0])
@@ -502,8 +510,7 @@ def render(inp: OracleInputs, o: np.ndarray, d: np.ndarray, naive: bool = False,
     else:
         fz = np.zeros((0, 8))
     c_d, feat, depth, T = composite64(inp, n, m["s_ray"], m["s_t"], fz)
-    rgb = 1.0 / (1.0 + np.exp(-(c_d + mlp64(inp.mlp, np.concatenate([c_d, feat], axis=1),
-                                              inp.mlp_dims))))
+    rgb = 1.0 / (1.0 + np.exp(-(c_d + deferred_mlp(inp, c_d, feat, d))))
     return RenderResult(n_samples=m["n_samples"], n_reads=m["n_reads"],
                         t_final32=m["t_final32"], t_final=T, c_d=c_d, feat=feat,
                         depth=depth, rgb=rgb, s_ray=m["s_ray"], s_k=m["s_k"],
@@ -568,8 +575,7 @@ def render_proposal(inp: OracleInputs, o, d, proposal, conf_threshold=0.9, margi
     else:
         fz = np.zeros((0, 8))
     c_d, feat, depth, T = composite64(inp, n, m["s_ray"], m["s_t"], fz)
-    rgb = 1.0 / (1.0 + np.exp(-(c_d + mlp64(inp.mlp, np.concatenate([c_d, feat], axis=1),
-                                              inp.mlp_dims))))
+    rgb = 1.0 / (1.0 + np.exp(-(c_d + deferred_mlp(inp, c_d, feat, d))))
     res = RenderResult(n_samples=m["n_samples"], n_reads=m["n_reads"], t_final32=m["t_final32"],
                        t_final=T, c_d=c_d, feat=feat, depth=depth, rgb=rgb, s_ray=m["s_ray"],
                        s_k=m["s_k"], s_t=m["s_t"], s_pos=m["s_pos"], extra={"s_T": m["s_T"]})

@@ -56,6 +56,7 @@ SceneArgs scene_args(const ngprt_ctx* ctx) {
     S.pyrR[j] = j < S.pyr_n ? (d.occ_fine_res >> j) : 32;
     S.pyr[j] = j < S.pyr_n ? ctx->pyr[j] : nullptr;
   }
+  S.view_mlp = d.mlp_hidden == 64 ? 1 : 0;
   S.model = d.feature_model;
   if (d.feature_model == NGPRT_MODEL_BAKED) {
     S.LC = d.coarse_res;
@@ -68,6 +69,9 @@ SceneArgs scene_args(const ngprt_ctx* ctx) {
   }
   return S;
 }
+
+static bool is_view_mlp(const ngprt_desc* d) { return d->mlp_hidden == 64; }
+static int mlp_param_count(const ngprt_desc* d) { return is_view_mlp(d) ? kMlpViewParams : kMlpParams; }
 
 static size_t dtype_bytes(int dt) { return dt == DT_F32 ? 4 : (dt == DT_BF16 ? 2 : 1); }
 
@@ -116,7 +120,9 @@ int ngprt_validate_desc(const ngprt_desc* d) {
   if (d->domain == NGPRT_ROI_BOX && d->step < d->roi_half * (1.0f / 65536.0f)) return NGPRT_E_INVALID_ARG;
   if (d->max_samples < 1) return NGPRT_E_INVALID_ARG;
   if (!(d->t_threshold >= 0.0f) || !std::isfinite(d->t_threshold)) return NGPRT_E_INVALID_ARG;
-  if (d->mlp_in != 7 || d->mlp_hidden != 16 || d->mlp_out != 3) return NGPRT_E_UNSUPPORTED;
+  const bool plain_mlp = d->mlp_in == 7 && d->mlp_hidden == 16 && d->mlp_out == 3;
+  const bool view_mlp = d->mlp_in == 23 && d->mlp_hidden == 64 && d->mlp_out == 3;
+  if (!plain_mlp && !view_mlp) return NGPRT_E_UNSUPPORTED;
   if (d->feature_model != NGPRT_MODEL_HASH && d->feature_model != NGPRT_MODEL_BAKED)
     return NGPRT_E_INVALID_ARG;
   if (d->feature_model == NGPRT_MODEL_BAKED) {
@@ -150,6 +156,7 @@ void ngprt_destroy(ngprt_ctx* ctx) {
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->prop_wb) (void)hipFree(ctx->prop_wb);
   if (ctx->prop_grad) (void)hipFree(ctx->prop_grad);
+  if (ctx->mlp_rec) (void)hipFree(ctx->mlp_rec);
   if (ctx->cidx) (void)hipFree(ctx->cidx);
   if (ctx->catlas) (void)hipFree(ctx->catlas);
   for (int j = 0; j < 5; ++j)
@@ -180,7 +187,9 @@ int ngprt_create(const ngprt_desc* desc, ngprt_ctx** out) {
             hipMalloc(&ctx->logit, size_t(L * ctx->T) * eb) == hipSuccess &&
             hipMalloc((void**)&ctx->scales_dev, sizeof(float) * (NGPRT_MAX_LEVELS * 9 + 1)) == hipSuccess &&
             hipMalloc((void**)&ctx->grid, size_t(R * R * R) * sizeof(uint16_t)) == hipSuccess &&
-            hipMalloc((void**)&ctx->mlp, sizeof(float) * kMlpParams) == hipSuccess;
+            hipMalloc((void**)&ctx->mlp, sizeof(float) * mlp_param_count(desc)) == hipSuccess &&
+            (!is_view_mlp(desc) ||
+             hipMalloc((void**)&ctx->mlp_rec, sizeof(float) * kMlpViewRec) == hipSuccess);
   if (ok)
     ok = hipMemcpy(ctx->scales_dev, &ctx->scales_host[0][0], sizeof(float) * NGPRT_MAX_LEVELS * 9,
                    hipMemcpyHostToDevice) == hipSuccess;
@@ -288,9 +297,13 @@ int ngprt_export_distance(ngprt_ctx* ctx, uint8_t* dev_dist, void* stream) {
 int ngprt_load_mlp(ngprt_ctx* ctx, const float* dev_params, void* stream) {
   if (!ctx) return NGPRT_E_INVALID_ARG;
   if (!dev_params) return fail(ctx, NGPRT_E_INVALID_ARG, "dev_params is NULL");
-  if (hipMemcpyAsync(ctx->mlp, dev_params, sizeof(float) * kMlpParams, hipMemcpyDeviceToDevice,
-                     (hipStream_t)stream) != hipSuccess)
+  if (hipMemcpyAsync(ctx->mlp, dev_params, sizeof(float) * mlp_param_count(&ctx->desc),
+                     hipMemcpyDeviceToDevice, (hipStream_t)stream) != hipSuccess)
     return check_launch(ctx, "mlp copy");
+  if (is_view_mlp(&ctx->desc)) {
+    int rc = launch_view_mlp_arrange(ctx, ctx->mlp, (hipStream_t)stream);
+    if (rc) return rc;
+  }
   ctx->mlp_loaded = true;
   return NGPRT_OK;
 }
@@ -313,6 +326,8 @@ int ngprt_render(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins, const
   int rc = check_ready(ctx);
   if (rc) return rc;
   if (!ctx->mlp_loaded) return fail(ctx, NGPRT_E_NOT_LOADED, "mlp not loaded");
+  if (is_view_mlp(&ctx->desc) && (!out->c_d || !out->feat))
+    return fail(ctx, NGPRT_E_INVALID_ARG, "the view-dependent MLP needs the c_d and feat outputs");
   RayOut o{out->rgb,       out->c_d,     out->feat,   out->t_final, out->depth,
            out->n_samples, out->n_reads, out->t_first, out->t_far,   out->t_half};
   return launch_render(ctx, n_rays, dev_origins, dev_dirs, o, nullptr, 0.0f, 0.0f, nullptr,
@@ -332,6 +347,8 @@ int ngprt_render_proposal(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origi
   int rc = check_ready(ctx);
   if (rc) return rc;
   if (!ctx->mlp_loaded) return fail(ctx, NGPRT_E_NOT_LOADED, "mlp not loaded");
+  if (is_view_mlp(&ctx->desc) && (!out->c_d || !out->feat))
+    return fail(ctx, NGPRT_E_INVALID_ARG, "the view-dependent MLP needs the c_d and feat outputs");
   RayOut o{out->rgb,       out->c_d,     out->feat,   out->t_final, out->depth,
            out->n_samples, out->n_reads, out->t_first, out->t_far,   out->t_half};
   return launch_render(ctx, n_rays, dev_origins, dev_dirs, o, dev_proposal, conf_threshold, margin,
@@ -387,6 +404,8 @@ int ngprt_render_backward(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origi
     return fail(ctx, NGPRT_E_DTYPE, "backward needs float32 tables");
   if (ctx->desc.feature_model != NGPRT_MODEL_HASH)
     return fail(ctx, NGPRT_E_UNSUPPORTED, "backward supports the hash feature model only");
+  if (is_view_mlp(&ctx->desc))
+    return fail(ctx, NGPRT_E_UNSUPPORTED, "backward supports the 7-16-16-3 deferred MLP only");
   int rc = check_ready(ctx);
   if (rc) return rc;
   if (!ctx->mlp_loaded) return fail(ctx, NGPRT_E_NOT_LOADED, "mlp not loaded");

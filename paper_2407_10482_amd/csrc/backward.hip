@@ -50,7 +50,7 @@ __device__ __forceinline__ bf32x4 wave_outer_sum(const float* sA, const float* s
   return acc;
 }
 
-template <int DOM, int LMAX>
+template <int DOM, int LMAX, bool PYR>
 __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, const float* __restrict__ O,
                                                        const float* __restrict__ D,
                                                        const float* __restrict__ grad_rgb,
@@ -73,7 +73,7 @@ __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, c
   for (;;) {
     float u[3], ts;
     int ks;
-    bool have = march_next<DOM>(S, m, false, reads, u, ts, ks);
+    bool have = march_next<DOM, PYR>(S, m, false, reads, u, ts, ks);
     if (__ballot(have) == 0) break;
     if (have) {
       float f[8];
@@ -219,7 +219,7 @@ __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, c
   for (;;) {
     float u[3] = {0.f, 0.f, 0.f}, ts;
     int ks;
-    const bool have = march_next<DOM>(S, m, false, reads, u, ts, ks);
+    const bool have = march_next<DOM, PYR>(S, m, false, reads, u, ts, ks);
     if (__ballot(have) == 0) break;
     float gf[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, wl[LMAX], gff = 0.0f;
     if (have) {
@@ -354,13 +354,20 @@ int launch_backward(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, c
   float* partial = reinterpret_cast<float*>(ctx->ws);
   dim3 g = dim3(unsigned(blocks));
   const bool box = ctx->desc.domain == DOM_BOX;
-  if (S.L <= 8) {
-    if (box) hipLaunchKernelGGL((backward_kernel<DOM_BOX, 8>), g, dim3(256), 0, st, S, n, o, d, grad_rgb, gtab, partial, ctx->mlp);
-    else hipLaunchKernelGGL((backward_kernel<DOM_CONTRACT, 8>), g, dim3(256), 0, st, S, n, o, d, grad_rgb, gtab, partial, ctx->mlp);
+#define NGPRT_BW(DOMV, LM, PY)                                                                  \
+  hipLaunchKernelGGL((backward_kernel<DOMV, LM, PY>), g, dim3(256), 0, st, S, n, o, d, grad_rgb, gtab, \
+                     partial, ctx->mlp)
+  if (S.pyr_n > 0) {
+    if (box) NGPRT_BW(DOM_BOX, 16, true);
+    else NGPRT_BW(DOM_CONTRACT, 16, true);
+  } else if (S.L <= 8) {
+    if (box) NGPRT_BW(DOM_BOX, 8, false);
+    else NGPRT_BW(DOM_CONTRACT, 8, false);
   } else {
-    if (box) hipLaunchKernelGGL((backward_kernel<DOM_BOX, 16>), g, dim3(256), 0, st, S, n, o, d, grad_rgb, gtab, partial, ctx->mlp);
-    else hipLaunchKernelGGL((backward_kernel<DOM_CONTRACT, 16>), g, dim3(256), 0, st, S, n, o, d, grad_rgb, gtab, partial, ctx->mlp);
+    if (box) NGPRT_BW(DOM_BOX, 16, false);
+    else NGPRT_BW(DOM_CONTRACT, 16, false);
   }
+#undef NGPRT_BW
   int rc = check_launch(ctx, "backward_kernel");
   if (rc) return rc;
   hipLaunchKernelGGL(reduce_partials_kernel, dim3(2), dim3(256), 0, st, partial, n_waves, gmlp);

@@ -14,7 +14,9 @@ namespace ngprt {
 enum { DT_F32 = 0, DT_BF16 = 1, DT_FP8 = 2 };
 enum { DOM_BOX = 0, DOM_CONTRACT = 1 };
 constexpr int kMaxLevels = NGPRT_MAX_LEVELS;
-constexpr int kMlpParams = 451;
+constexpr int kMlpParams = 451;          // deferred MLP 7 -> 16 -> 16 -> 3
+constexpr int kMlpViewParams = 5891;     // view-dependent MLP 23 -> 64 -> 64 -> 3
+constexpr int kMlpViewRec = 8960;        // its weights arranged for the MFMA sequence
 constexpr int kMaxLattice = 1 << 16;   // hard bound on lattice points per ray
 constexpr int kMaxPyr = 5;             // occupancy pyramid levels
 
@@ -55,6 +57,7 @@ struct SceneArgs {
   // multi-level occupancy (pyr_n > 0): bit grids, level j of resolution pyrR[j]
   int pyr_n;
   int use_dist;                   // consult the distance grid (Eq. 9) when the exiting level is coarser
+  int view_mlp;                   // the deferred MLP is the view-dependent one (a separate pass)
   int pyrR[kMaxPyr];
   const uint32_t* pyr[kMaxPyr];   // [R^3 / 32] words, x fastest, bit x & 31
 };
@@ -84,7 +87,8 @@ struct ngprt_ctx {
   float scales_host[NGPRT_MAX_LEVELS][9];
   float logit_shift = 0.0f;   // largest stored logit (set by load_tables)
   uint16_t* grid = nullptr;   // [R^3]
-  float* mlp = nullptr;       // [451]
+  float* mlp = nullptr;       // [451] or, view-dependent MLP, [5891]
+  float* mlp_rec = nullptr;   // view-dependent MLP: weights in MFMA order [8960]
   void* ws = nullptr;         // workspace (per-wave gradient partials of backward / proposal)
   size_t ws_bytes = 0;
   void* prop_wb = nullptr;    // proposal weights in bfloat16 [7556]
@@ -120,6 +124,9 @@ int launch_march(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, int3
                  int32_t* sk, int32_t* ns, int32_t* nr, int naive, hipStream_t s);
 int launch_backward(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const float* grad_rgb,
                     float* gtab, float* gmlp, hipStream_t s);
+int launch_view_mlp_arrange(ngprt_ctx* ctx, const float* params, hipStream_t s);
+int launch_view_mlp(ngprt_ctx* ctx, int64_t n, const float* d, const float* c_d, const float* feat,
+                    float* rgb, hipStream_t s);
 int launch_build_pyramid(ngprt_ctx* ctx, const uint8_t* occ_fine, hipStream_t s);
 int launch_pack_atlas(ngprt_ctx* ctx, const float* atlas, int64_t n_blocks, hipStream_t s);
 int launch_gather_probe(ngprt_ctx* ctx, int64_t n, uint32_t seed, int pairs, float* out, hipStream_t s);

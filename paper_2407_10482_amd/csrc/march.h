@@ -89,7 +89,9 @@ __device__ __forceinline__ uint32_t voxel_of(const SceneArgs& S, const float p[3
 // Advance this lane's march to its next occupied lattice point.  Returns
 // true with (u, ts, ks) set when a sample was found; sets m.done when the
 // ray leaves the domain.
-template <int DOM>
+// PYR: the scene marches an occupancy pyramid (S.pyr_n > 0) instead of one
+// occupancy grid; a template flag so the single-grid march carries none of it.
+template <int DOM, bool PYR>
 __device__ __forceinline__ bool march_next(const SceneArgs& S, MarchState& m, bool naive,
                                            int& reads, float u[3], float& ts, int& ks) {
   while (!m.done) {
@@ -139,7 +141,7 @@ __device__ __forceinline__ bool march_next(const SceneArgs& S, MarchState& m, bo
     m.k = kcur + 1;
     if (!need) continue;
     const uint32_t v = voxel_of(S, p, u);
-    if (S.pyr_n > 0) {
+    if (PYR) {
       // multi-level occupancy (Eq. 9's s_O branch): levels coarse to fine;
       // reads counts marching points (lattice points checked), whatever the
       // number of levels read there

@@ -112,6 +112,7 @@ __device__ __forceinline__ void wave_mlp(const float* __restrict__ P, const floa
 #define NGPRT_XCD_CHUNK 0
 #endif
 
+// MODEL: bit 0 = baked feature model, bit 1 = occupancy pyramid march
 template <int DOM, int DT, int LMAX, int MODE, int MODEL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NGPRT_RENDER_WAVES_PER_EU)))
 render_kernel(SceneArgs S, int64_t n, const float* __restrict__ O,
@@ -161,19 +162,19 @@ render_kernel(SceneArgs S, int64_t n, const float* __restrict__ O,
   for (;;) {
     float u[3], ts;
     int ks;
-    bool have = march_next<DOM>(S, m, naive != 0, reads, u, ts, ks);
+    bool have = march_next<DOM, (MODEL & 2) != 0>(S, m, naive != 0, reads, u, ts, ks);
     if (EXT && !have && proposed && !fell_back && ns == 0 && m.stopped_at_hi) {
       // nothing sampled before the proposed end: carry on as the plain march
       m.t_hi = __int_as_float(0x7F800000);
       m.done = false;
       m.stopped_at_hi = false;
       fell_back = true;
-      have = march_next<DOM>(S, m, naive != 0, reads, u, ts, ks);
+      have = march_next<DOM, (MODEL & 2) != 0>(S, m, naive != 0, reads, u, ts, ks);
     }
     if (__ballot(have) == 0) break;
     if (have) {
       float f[8];
-      eval_sample<MODEL, DT, LMAX>(S, u, f);
+      eval_sample<MODEL & 1, DT, LMAX>(S, u, f);
       const float sigma = exp32(f[0]);
       const float e = exp32(-(sigma * S.step));
       const float alpha = 1.0f - e;
@@ -230,7 +231,7 @@ render_kernel(SceneArgs S, int64_t n, const float* __restrict__ O,
   xin[6 * 64 + lane] = fv[3];
   xin[7 * 64 + lane] = 0.0f;
   __syncthreads();
-  wave_mlp(mlp, xin, lane, ray_base, n, out.rgb);
+  if (!S.view_mlp) wave_mlp(mlp, xin, lane, ray_base, n, out.rgb);
 }
 
 template <int DT, int LMAX, int MODEL>
@@ -261,8 +262,14 @@ template <int MODE, int DOM, int DT>
 static void dispatch_l(const SceneArgs& S, dim3 g, hipStream_t st, int64_t n, const float* o,
                        const float* d, const RayOut& out, const MarchRecord& rec,
                        const float* mlp, int naive, const ProposalArgs& pa) {
-  if (S.model == 1)
+  if (S.model == 1 && S.pyr_n > 0)
+    hipLaunchKernelGGL((render_kernel<DOM, DT, 4, MODE, 3>), g, dim3(256), 0, st, S, n, o, d, out, rec,
+                       mlp, naive, pa);
+  else if (S.model == 1)
     hipLaunchKernelGGL((render_kernel<DOM, DT, 4, MODE, 1>), g, dim3(256), 0, st, S, n, o, d, out, rec,
+                       mlp, naive, pa);
+  else if (S.pyr_n > 0)
+    hipLaunchKernelGGL((render_kernel<DOM, DT, 16, MODE, 2>), g, dim3(256), 0, st, S, n, o, d, out, rec,
                        mlp, naive, pa);
   else if (S.L <= 8)
     hipLaunchKernelGGL((render_kernel<DOM, DT, 8, MODE, 0>), g, dim3(256), 0, st, S, n, o, d, out, rec,
@@ -304,7 +311,9 @@ int launch_render(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, con
   else
     dispatch<MODE_RENDER>(S, ctx->desc.domain, ctx->desc.table_dtype, dim3(unsigned(blocks)), st, n, o,
                           d, out, rec, ctx->mlp, 0, pa);
-  return check_launch(ctx, "render_kernel");
+  int rc = check_launch(ctx, "render_kernel");
+  if (rc == NGPRT_OK && S.view_mlp) rc = launch_view_mlp(ctx, n, d, out.c_d, out.feat, out.rgb, st);
+  return rc;
 }
 
 int launch_march(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, int32_t cap,

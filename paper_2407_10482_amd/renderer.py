@@ -39,7 +39,7 @@ class Renderer:
                  domain: int = ROI_BOX, roi_half: float = 1.0, occ_res: int = 64,
                  step: float = 1.0 / 256.0, max_samples: int = 1024, t_threshold: float = 1e-4,
                  feature_model: int = MODEL_HASH, coarse_res: int = 0, occ_levels: int = 0,
-                 occ_fine_res: int = 0, use_distance: bool = True):
+                 occ_fine_res: int = 0, use_distance: bool = True, mlp_dims=(7, 16, 16, 3)):
         self.lib = load_library()
         self.resolutions = list(resolutions)
         self.L = len(self.resolutions)
@@ -49,11 +49,16 @@ class Renderer:
         self.feature_model = feature_model
         self.coarse_res = coarse_res
         self.occ_fine_res = occ_fine_res
+        self.mlp_dims = tuple(mlp_dims)
+        self.view_mlp = self.mlp_dims[1] == 64
+        i, h, _, o = self.mlp_dims
+        self.n_mlp = h * i + h + h * h + h + o * h + o
         self.desc = _lib.make_desc(resolutions, log2_table_size, table_dtype, domain, roi_half,
                                    occ_res, step, max_samples, t_threshold,
                                    feature_model=feature_model, coarse_res=coarse_res,
                                    occ_levels=occ_levels, occ_fine_res=occ_fine_res,
-                                   use_distance=int(bool(use_distance)))
+                                   use_distance=int(bool(use_distance)),
+                                   mlp=(self.mlp_dims[0], self.mlp_dims[1], self.mlp_dims[3]))
         ctx = ctypes.c_void_p()
         check(self.lib.ngprt_create(ctypes.byref(self.desc), ctypes.byref(ctx)))
         self.ctx = ctx
@@ -63,7 +68,8 @@ class Renderer:
         return cls(cfg.resolutions, cfg.log2_table, cfg.table_dtype if table_dtype is None else table_dtype,
                    cfg.domain, cfg.roi_half, cfg.occ_res, cfg.step, cfg.max_samples, cfg.t_threshold,
                    getattr(cfg, "model", MODEL_HASH), getattr(cfg, "coarse_res", 0),
-                   getattr(cfg, "occ_levels", 0), getattr(cfg, "occ_fine_res", 0), use_distance)
+                   getattr(cfg, "occ_levels", 0), getattr(cfg, "occ_fine_res", 0), use_distance,
+                   tuple(cfg.mlp_dims))
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -93,7 +99,7 @@ class Renderer:
         check(self.lib.ngprt_load_occupancy_pyramid(self.ctx, _ptr(occ_fine), _stream()), self.ctx)
 
     def load_mlp(self, params: torch.Tensor):
-        _dev(params, torch.float32, (451,), "mlp params")
+        _dev(params, torch.float32, (self.n_mlp,), "mlp params")
         check(self.lib.ngprt_load_mlp(self.ctx, _ptr(params), _stream()), self.ctx)
 
     def load_coarse(self, block_index: torch.Tensor, atlas: torch.Tensor, default):
@@ -136,10 +142,20 @@ class Renderer:
         if out is None:
             out = self.alloc_outputs(n) if aux else {"rgb": torch.empty((n, 3), dtype=torch.float32,
                                                                         device="cuda")}
+        self._view_buffers(out, n)
         o = self._outputs(out)
         check(self.lib.ngprt_render(self.ctx, n, _ptr(origins), _ptr(dirs), ctypes.byref(o),
                                     _stream()), self.ctx)
         return out
+
+    def _view_buffers(self, out, n):
+        """The view-dependent MLP runs over the C_d and F outputs: make sure
+        the caller's output dict has them."""
+        if self.view_mlp:
+            if "c_d" not in out:
+                out["c_d"] = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+            if "feat" not in out:
+                out["feat"] = torch.empty((n, 4), dtype=torch.float32, device="cuda")
 
     OUTPUT_FIELDS = ("rgb", "c_d", "feat", "t_final", "depth", "n_samples", "n_reads", "t_first",
                      "t_far", "t_half")
@@ -173,6 +189,7 @@ class Renderer:
         if out is None:
             out = self.alloc_outputs(n) if aux else {"rgb": torch.empty((n, 3), dtype=torch.float32,
                                                                         device="cuda")}
+        self._view_buffers(out, n)
         fb = out.get("fallback")
         if fb is None and aux:
             fb = out["fallback"] = torch.empty((n,), dtype=torch.int32, device="cuda")

@@ -187,5 +187,14 @@ def hd_pyramid(seed: int = 0, table_dtype: int = DTYPE_F32) -> SceneConfig:
     return cfg
 
 
-CONFIGS = {"tiny": tiny, "hd": hd, "train_large": train_large, "baked_tiny": baked_tiny,
+def tiny_view(seed: int = 0, table_dtype: int = DTYPE_F32) -> SceneConfig:
+    """The tiny scene with the view-dependent MLP_psi (23 -> 64 -> 64 -> 3 of
+    C_d, F and the degree-0..3 spherical harmonics of the view direction)."""
+    cfg = tiny(seed, table_dtype)
+    cfg.name = "tiny_view"
+    cfg.mlp_dims = (23, 64, 64, 3)
+    return cfg
+
+
+CONFIGS = {"tiny_view": tiny_view, "tiny": tiny, "hd": hd, "train_large": train_large, "baked_tiny": baked_tiny,
            "baked_hd": baked_hd, "tiny_pyramid": tiny_pyramid, "hd_pyramid": hd_pyramid}
