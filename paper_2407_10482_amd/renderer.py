@@ -236,7 +236,7 @@ def _renderer_backward(self: Renderer, origins, dirs, grad_rgb, grad_tables, gra
     n = origins.shape[0]
     _dev(grad_rgb, torch.float32, (n, 3), "grad_rgb")
     _dev(grad_tables, torch.float32, (self.L, self.T, 9), "grad_tables")
-    _dev(grad_mlp, torch.float32, (451,), "grad_mlp")
+    _dev(grad_mlp, torch.float32, (self.n_mlp,), "grad_mlp")
     check(self.lib.ngprt_render_backward(self.ctx, n, _ptr(origins), _ptr(dirs), _ptr(grad_rgb),
                                          _ptr(grad_tables), _ptr(grad_mlp), _stream()), self.ctx)
 
