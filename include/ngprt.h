@@ -123,6 +123,10 @@ typedef struct ngprt_outputs {
   float* t_far;      /* [n]    t of the sample after which T < 1e-3 (the last sample's t if
                       *        never; 0 if no sample): the proposal's far-end label */
   float* t_half;     /* [n]    t of the sample after which T < 0.5 (last sample's t if never) */
+  float* dist_loss;  /* [n]    distortion regulariser of the ray (supplement Eq. S2) over its
+                      *        rendering weights w_i on the lattice intervals
+                      *        [k_i step, (k_i + 1) step] (k_i the sample's lattice index):
+                      *        sum_ij w_i w_j |m_i - m_j| + step/3 sum_i w_i^2, m_i = (k_i + 1/2) step */
 } ngprt_outputs;
 
 /* Create a context on the current HIP device.  Validates the descriptor
@@ -267,6 +271,21 @@ int ngprt_debug_march(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins,
 int ngprt_render_backward(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins,
                           const float* dev_dirs, const float* dev_grad_rgb, float* dev_grad_tables,
                           float* dev_grad_mlp, void* stream);
+
+/* ngprt_render_backward with the distortion regulariser (supplement Eq. S2,
+ * the per-ray value ngprt_render writes to out->dist_loss): dev_grad_dist,
+ * float32 [n] (NULL = 0), is dL/d(dist_loss) per ray, so a loss
+ * L_color + eta * sum_rays dist_loss takes dev_grad_dist = eta.  The
+ * regulariser's gradient reaches the tables through the rendering weights
+ * (dL/dw_i = g_r (2 sum_j w_j |m_i - m_j| + 2/3 step w_i)). */
+int ngprt_render_backward_reg(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins,
+                              const float* dev_dirs, const float* dev_grad_rgb, const float* dev_grad_dist,
+                              float* dev_grad_tables, float* dev_grad_mlp, void* stream);
+
+/* Change the lattice step (the paper's marching-step auto-tuning,
+ * supplement Eq. S3, scales it between training batches).  Same checks as
+ * desc.step (NGPRT_E_INVALID_ARG).  Later calls use the new step. */
+int ngprt_set_step(ngprt_ctx* ctx, float step);
 
 /* One Adam update (Kingma & Ba; the paper's training uses beta1 = 0.9,
  * beta2 = 0.99, eps = 1e-8, supplement "Optimization") over n float32

@@ -27,6 +27,7 @@ from __future__ import annotations
 
 import numpy as np
 
+from . import distortion
 from .hashgrid import corners64
 from .render import OracleInputs, grid_coords64, march, mlp64
 
@@ -41,11 +42,30 @@ def _split_mlp(p):
     return W0, b0, W1, b1, W2, b2
 
 
-def frozen_samples(inp: OracleInputs, o, d):
+def frozen_samples(inp: OracleInputs, o, d, with_k: bool = False):
     """Sample lists decided by the forward march (no termination changes
     under the perturbations of a finite-difference check)."""
     m = march(inp, o, d)
+    if with_k:
+        return m["s_ray"], m["s_pos"], m["s_t"], m["s_k"]
     return m["s_ray"], m["s_pos"], m["s_t"]
+
+
+def ray_distortion(n_rays, s_ray, s_k, w, step):
+    """Per-ray distortion regulariser (supplement Eq. S2) on the lattice
+    intervals [k step, (k + 1) step] and dL_dist/dw per sample."""
+    step = float(np.float32(step))
+    loss = np.zeros(n_rays)
+    gw = np.zeros(len(s_ray))
+    if len(s_ray):
+        starts = np.r_[0, np.nonzero(np.diff(s_ray))[0] + 1]
+        ends = np.r_[starts[1:], len(s_ray)]
+        for a, b in zip(starts, ends):
+            t = np.asarray(s_k[a:b], np.float64) * step
+            l, g = distortion.dist_loss_and_grad(w[a:b], t, np.full(b - a, step))
+            loss[s_ray[a]] = l
+            gw[a:b] = g
+    return loss, gw
 
 
 def grid_u(s_pos, roi_half):
@@ -110,8 +130,13 @@ def loss64(tables64, mlp, resolutions, step, n_rays, s_ray, s_pos, target, roi_h
     return float(np.mean((f["rgb"] - target) ** 2))
 
 
-def backward64(tables64, mlp, resolutions, step, n_rays, s_ray, s_pos, grad_rgb, roi_half=1.0):
-    """dL/dtables [L, T, 9] and dL/dmlp [451] for an upstream dL/drgb [n, 3]."""
+def backward64(tables64, mlp, resolutions, step, n_rays, s_ray, s_pos, grad_rgb, roi_half=1.0,
+               grad_dist=None, s_k=None):
+    """dL/dtables [L, T, 9] and dL/dmlp [451] for an upstream dL/drgb [n, 3]
+    and, optionally, dL/d(distortion regulariser) per ray [n] (s_k: the
+    samples' lattice indices).  The regulariser enters as dL/dw_i, which
+    adds g_r dL_dist/dw_i to s_i and g_r sum_i w_i dL_dist/dw_i = 2 g_r L_dist
+    to S."""
     f = forward64(tables64, mlp, resolutions, step, n_rays, s_ray, s_pos, roi_half)
     W0, b0, W1, b1, W2, b2 = _split_mlp(mlp)
     rgb = f["rgb"]
@@ -133,6 +158,11 @@ def backward64(tables64, mlp, resolutions, step, n_rays, s_ray, s_pos, grad_rgb,
     fused, w, Tb, ee, sigma = f["fused"], f["w"], f["Tb"], f["ee"], f["sigma"]
     s = (g_cd[s_ray] * fused[:, 1:4]).sum(axis=1) + (g_f[s_ray] * fused[:, 4:8]).sum(axis=1)
     S = (g_cd * f["c_d"]).sum(axis=1) + (g_f * f["feat"]).sum(axis=1)
+    if grad_dist is not None:
+        dl, gw = ray_distortion(n_rays, s_ray, s_k, w, step)
+        gd = np.asarray(grad_dist, np.float64)
+        s = s + gd[s_ray] * gw
+        S = S + gd * 2.0 * dl
     ws = w * s
     P = np.zeros(len(s_ray))
     if len(s_ray):

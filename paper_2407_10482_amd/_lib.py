@@ -44,7 +44,7 @@ class NgprtDesc(ctypes.Structure):
 class NgprtOutputs(ctypes.Structure):
     _fields_ = [(name, ctypes.c_void_p) for name in
                 ("rgb", "c_d", "feat", "t_final", "depth", "n_samples", "n_reads", "t_first",
-                 "t_far", "t_half")]
+                 "t_far", "t_half", "dist_loss")]
 
 
 # (name, restype, argtypes)
@@ -69,6 +69,8 @@ SIGNATURES = [
     ("ngprt_render_proposal", ctypes.c_int, [_P, _I64, _P, _P, _P, ctypes.c_float, ctypes.c_float,
                                              ctypes.POINTER(NgprtOutputs), _P, _P]),
     ("ngprt_render_backward", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P]),
+    ("ngprt_render_backward_reg", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P]),
+    ("ngprt_set_step", ctypes.c_int, [_P, ctypes.c_float]),
     ("ngprt_adam_step", ctypes.c_int, [_I64, _P, _P, _P, _P, _I32, ctypes.c_float, ctypes.c_float,
                                        ctypes.c_float, ctypes.c_float, _P]),
     ("ngprt_proposal_infer", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P]),

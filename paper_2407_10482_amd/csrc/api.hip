@@ -329,7 +329,7 @@ int ngprt_render(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins, const
   if (is_view_mlp(&ctx->desc) && (!out->c_d || !out->feat))
     return fail(ctx, NGPRT_E_INVALID_ARG, "the view-dependent MLP needs the c_d and feat outputs");
   RayOut o{out->rgb,       out->c_d,     out->feat,   out->t_final, out->depth,
-           out->n_samples, out->n_reads, out->t_first, out->t_far,   out->t_half};
+           out->n_samples, out->n_reads, out->t_first, out->t_far,   out->t_half, out->dist_loss};
   return launch_render(ctx, n_rays, dev_origins, dev_dirs, o, nullptr, 0.0f, 0.0f, nullptr,
                        (hipStream_t)stream);
 }
@@ -350,7 +350,7 @@ int ngprt_render_proposal(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origi
   if (is_view_mlp(&ctx->desc) && (!out->c_d || !out->feat))
     return fail(ctx, NGPRT_E_INVALID_ARG, "the view-dependent MLP needs the c_d and feat outputs");
   RayOut o{out->rgb,       out->c_d,     out->feat,   out->t_final, out->depth,
-           out->n_samples, out->n_reads, out->t_first, out->t_far,   out->t_half};
+           out->n_samples, out->n_reads, out->t_first, out->t_far,   out->t_half, out->dist_loss};
   return launch_render(ctx, n_rays, dev_origins, dev_dirs, o, dev_proposal, conf_threshold, margin,
                        dev_fallback, (hipStream_t)stream);
 }
@@ -392,9 +392,9 @@ int ngprt_debug_march(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins, 
                       dev_n_reads, naive, (hipStream_t)stream);
 }
 
-int ngprt_render_backward(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins, const float* dev_dirs,
-                          const float* dev_grad_rgb, float* dev_grad_tables, float* dev_grad_mlp,
-                          void* stream) {
+int ngprt_render_backward_reg(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins,
+                              const float* dev_dirs, const float* dev_grad_rgb, const float* dev_grad_dist,
+                              float* dev_grad_tables, float* dev_grad_mlp, void* stream) {
   if (!ctx) return NGPRT_E_INVALID_ARG;
   if (n_rays < 0) return fail(ctx, NGPRT_E_INVALID_ARG, "n_rays < 0");
   if (n_rays == 0) return NGPRT_OK;
@@ -409,8 +409,24 @@ int ngprt_render_backward(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origi
   int rc = check_ready(ctx);
   if (rc) return rc;
   if (!ctx->mlp_loaded) return fail(ctx, NGPRT_E_NOT_LOADED, "mlp not loaded");
-  return launch_backward(ctx, n_rays, dev_origins, dev_dirs, dev_grad_rgb, dev_grad_tables, dev_grad_mlp,
-                         (hipStream_t)stream);
+  return launch_backward(ctx, n_rays, dev_origins, dev_dirs, dev_grad_rgb, dev_grad_dist, dev_grad_tables,
+                         dev_grad_mlp, (hipStream_t)stream);
+}
+
+int ngprt_render_backward(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins, const float* dev_dirs,
+                          const float* dev_grad_rgb, float* dev_grad_tables, float* dev_grad_mlp,
+                          void* stream) {
+  return ngprt_render_backward_reg(ctx, n_rays, dev_origins, dev_dirs, dev_grad_rgb, nullptr, dev_grad_tables,
+                                   dev_grad_mlp, stream);
+}
+
+int ngprt_set_step(ngprt_ctx* ctx, float step) {
+  if (!ctx) return NGPRT_E_INVALID_ARG;
+  ngprt_desc d = ctx->desc;
+  d.step = step;
+  if (ngprt_validate_desc(&d) != NGPRT_OK) return fail(ctx, NGPRT_E_INVALID_ARG, "invalid step");
+  ctx->desc.step = step;
+  return NGPRT_OK;
 }
 
 int ngprt_adam_step(int64_t n, float* dev_param, const float* dev_grad, float* dev_m, float* dev_v,

@@ -54,6 +54,7 @@ template <int DOM, int LMAX, bool PYR>
 __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, const float* __restrict__ O,
                                                        const float* __restrict__ D,
                                                        const float* __restrict__ grad_rgb,
+                                                       const float* __restrict__ grad_dist,
                                                        float* __restrict__ gtab, float* __restrict__ partial,
                                                        const float* __restrict__ P) {
   __shared__ float sA_all[4][64 * kPad];
@@ -64,6 +65,11 @@ __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, c
   const bool in_range = ray < n;
   const float* o = O + 3 * (in_range ? ray : 0);
   const float* d = D + 3 * (in_range ? ray : 0);
+
+  // distortion regulariser (dL/d dist_loss of this ray, 0 if none): running
+  // sums of w, w m, w (m W_< - S_<) and w^2 over the samples
+  const float gdist = (grad_dist && in_range) ? grad_dist[ray] : 0.0f;
+  float dW = 0.0f, dS = 0.0f, dP = 0.0f, dQ = 0.0f;
 
   // ---------------- pass 1: forward
   MarchState m;
@@ -83,6 +89,13 @@ __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, c
       const float w = T * (1.0f - e);
       for (int j = 0; j < 3; ++j) cd[j] = __builtin_fmaf(w, f[1 + j], cd[j]);
       for (int j = 0; j < 4; ++j) fv[j] = __builtin_fmaf(w, f[4 + j], fv[j]);
+      if (gdist != 0.0f) {
+        const float mid = ((float)ks + 0.5f) * S.step;
+        dP = __builtin_fmaf(w, mid * dW - dS, dP);
+        dQ = __builtin_fmaf(w, w, dQ);
+        dW = dW + w;
+        dS = __builtin_fmaf(w, mid, dS);
+      }
       T = T * e;
       ++ns;
       if (T < S.thr || ns >= S.max_samples) m.done = true;
@@ -146,7 +159,8 @@ __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, c
   }
   float gcd[3] = {gz[0] + gx[0], gz[1] + gx[1], gz[2] + gx[2]};
   float gfv[4] = {gx[3], gx[4], gx[5], gx[6]};
-  const float Stot = (gcd[0] * cd[0] + gcd[1] * cd[1] + gcd[2] * cd[2]) +
+  const float Ldist = 2.0f * dP + dQ * (S.step * (1.0f / 3.0f));
+  const float Stot = gdist * (2.0f * Ldist) + (gcd[0] * cd[0] + gcd[1] * cd[1] + gcd[2] * cd[2]) +
                      (gfv[0] * fv[0] + gfv[1] * fv[1] + gfv[2] * fv[2] + gfv[3] * fv[3]);
 
   // ---------------- MLP weight gradients: sums over the wave on MFMA
@@ -214,7 +228,7 @@ __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, c
   march_init<DOM>(S, o, d, in_range, m);
   T = 1.0f;
   ns = 0;
-  float Pc = 0.0f;
+  float Pc = 0.0f, rW = 0.0f, rS = 0.0f;
   const size_t T_entries = size_t(1) << S.log2T;
   for (;;) {
     float u[3] = {0.f, 0.f, 0.f}, ts;
@@ -229,8 +243,16 @@ __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, c
       const float sigma = exp32(f[0]);
       const float e = exp32(-(sigma * S.step));
       const float w = T * (1.0f - e);
-      const float s = (gcd[0] * f[1] + gcd[1] * f[2] + gcd[2] * f[3]) +
-                      (gfv[0] * f[4] + gfv[1] * f[5] + gfv[2] * f[6] + gfv[3] * f[7]);
+      float s = (gcd[0] * f[1] + gcd[1] * f[2] + gcd[2] * f[3]) +
+                (gfv[0] * f[4] + gfv[1] * f[5] + gfv[2] * f[6] + gfv[3] * f[7]);
+      if (gdist != 0.0f) {
+        // dL_dist/dw_i = 2 sum_j w_j |m_i - m_j| + 2/3 step w_i (prefix sums over j < i)
+        const float mid = ((float)ks + 0.5f) * S.step;
+        const float pair = (mid * rW - rS) + ((dS - rS - w * mid) - mid * (dW - rW - w));
+        s = __builtin_fmaf(gdist, 2.0f * pair + (2.0f / 3.0f) * S.step * w, s);
+        rW = rW + w;
+        rS = __builtin_fmaf(w, mid, rS);
+      }
       Pc = __builtin_fmaf(w, s, Pc);
       const float Tn = T * e;
       const float gsig = S.step * (Tn * s - (Stot - Pc));
@@ -335,6 +357,7 @@ __global__ void adam_kernel(int64_t n, float* __restrict__ p, const float* __res
 }
 
 int launch_backward(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const float* grad_rgb,
+                    const float* grad_dist,
                     float* gtab, float* gmlp, hipStream_t st) {
   SceneArgs S = scene_args(ctx);
   const int64_t blocks = (n + 255) / 256;
@@ -355,8 +378,8 @@ int launch_backward(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, c
   dim3 g = dim3(unsigned(blocks));
   const bool box = ctx->desc.domain == DOM_BOX;
 #define NGPRT_BW(DOMV, LM, PY)                                                                  \
-  hipLaunchKernelGGL((backward_kernel<DOMV, LM, PY>), g, dim3(256), 0, st, S, n, o, d, grad_rgb, gtab, \
-                     partial, ctx->mlp)
+  hipLaunchKernelGGL((backward_kernel<DOMV, LM, PY>), g, dim3(256), 0, st, S, n, o, d, grad_rgb, grad_dist, \
+                     gtab, partial, ctx->mlp)
   if (S.pyr_n > 0) {
     if (box) NGPRT_BW(DOM_BOX, 16, true);
     else NGPRT_BW(DOM_CONTRACT, 16, true);

@@ -157,6 +157,8 @@ render_kernel(SceneArgs S, int64_t n, const float* __restrict__ O,
   // the sample after which T < 1e-3 (the proposal's far end)
   float t_first = 0.0f, t_last = 0.0f, t_half = 0.0f, t_far = 0.0f;
   bool half_set = false, far_set = false;
+  // distortion regulariser: running sums of w, w m and w (m W_< - S_<), and w^2
+  float dW = 0.0f, dS = 0.0f, dP = 0.0f, dQ = 0.0f;
   int ns = 0, reads = 0;
 
   for (;;) {
@@ -187,6 +189,11 @@ render_kernel(SceneArgs S, int64_t n, const float* __restrict__ O,
       if (MODE == MODE_MARCH && ns < rec.cap) rec.sample_k[ray * rec.cap + ns] = ks;
       T = T * e;
       if (EXT) {
+        const float mid = ((float)ks + 0.5f) * S.step;
+        dP = __builtin_fmaf(w, mid * dW - dS, dP);
+        dQ = __builtin_fmaf(w, w, dQ);
+        dW = dW + w;
+        dS = __builtin_fmaf(w, mid, dS);
         if (ns == 0) t_first = ts;
         t_last = ts;
         if (!half_set && T < 0.5f) { t_half = ts; half_set = true; }
@@ -218,6 +225,7 @@ render_kernel(SceneArgs S, int64_t n, const float* __restrict__ O,
       if (out.t_first) out.t_first[ray] = t_first;
       if (out.t_far) out.t_far[ray] = t_far;
       if (out.t_half) out.t_half[ray] = t_half;
+      if (out.dist_loss) out.dist_loss[ray] = 2.0f * dP + dQ * (S.step * (1.0f / 3.0f));
       if (pa.fallback) pa.fallback[ray] = fell_back ? 1 : 0;
     }
   }
@@ -304,7 +312,7 @@ int launch_render(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, con
   if (blocks > 0x7FFFFFFF) return fail(ctx, NGPRT_E_SHAPE, "too many rays for one launch");
   MarchRecord rec{nullptr, nullptr, nullptr, 0};
   ProposalArgs pa{prop, conf_thr, margin, fallback};
-  const bool ext = prop || out.t_first || out.t_far || out.t_half;
+  const bool ext = prop || out.t_first || out.t_far || out.t_half || out.dist_loss;
   if (ext)
     dispatch<MODE_RENDER_EXT>(S, ctx->desc.domain, ctx->desc.table_dtype, dim3(unsigned(blocks)), st, n,
                               o, d, out, rec, ctx->mlp, 0, pa);

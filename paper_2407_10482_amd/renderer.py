@@ -158,7 +158,7 @@ class Renderer:
                 out["feat"] = torch.empty((n, 4), dtype=torch.float32, device="cuda")
 
     OUTPUT_FIELDS = ("rgb", "c_d", "feat", "t_final", "depth", "n_samples", "n_reads", "t_first",
-                     "t_far", "t_half")
+                     "t_far", "t_half", "dist_loss")
 
     @staticmethod
     def _outputs(out: Dict[str, torch.Tensor]) -> NgprtOutputs:
@@ -231,17 +231,47 @@ class Renderer:
         return sk, ns, nr
 
 
-def _renderer_backward(self: Renderer, origins, dirs, grad_rgb, grad_tables, grad_mlp):
-    """Accumulate dL/dtables [L, T, 9] and dL/dmlp [451] for dL/drgb."""
+def _renderer_backward(self: Renderer, origins, dirs, grad_rgb, grad_tables, grad_mlp, grad_dist=None):
+    """Accumulate dL/dtables [L, T, 9] and dL/dmlp [451] for dL/drgb and,
+    optionally, dL/d(dist_loss) per ray (the distortion regulariser)."""
     n = origins.shape[0]
     _dev(grad_rgb, torch.float32, (n, 3), "grad_rgb")
     _dev(grad_tables, torch.float32, (self.L, self.T, 9), "grad_tables")
     _dev(grad_mlp, torch.float32, (self.n_mlp,), "grad_mlp")
-    check(self.lib.ngprt_render_backward(self.ctx, n, _ptr(origins), _ptr(dirs), _ptr(grad_rgb),
-                                         _ptr(grad_tables), _ptr(grad_mlp), _stream()), self.ctx)
+    if grad_dist is not None:
+        _dev(grad_dist, torch.float32, (n,), "grad_dist")
+    check(self.lib.ngprt_render_backward_reg(self.ctx, n, _ptr(origins), _ptr(dirs), _ptr(grad_rgb),
+                                             _ptr(grad_dist), _ptr(grad_tables), _ptr(grad_mlp), _stream()),
+          self.ctx)
+
+
+def _renderer_set_step(self: Renderer, step: float):
+    check(self.lib.ngprt_set_step(self.ctx, float(step)), self.ctx)
+    self.step = float(step)
 
 
 Renderer.backward = _renderer_backward
+Renderer.set_step = _renderer_set_step
+
+
+class StepAutoTuner:
+    """Marching-step auto-tuning of the paper's training (supplement Eq. S3):
+    after each batch, gamma <- min(1, (1 + kappa) gamma) when the batch's
+    mean evaluated-sample count reaches n_min, else
+    max(gamma_min, (1 - kappa) gamma); the renderer's step is gamma * s0."""
+
+    def __init__(self, renderer: Renderer, s0: float, n_min: float = 3.0, kappa: float = 0.001,
+                 gamma_min: float = 0.2217, gamma: float = 1.0):
+        self.r, self.s0 = renderer, float(s0)
+        self.n_min, self.kappa, self.gamma_min, self.gamma = n_min, kappa, gamma_min, gamma
+
+    def update(self, mean_samples: float) -> float:
+        if mean_samples >= self.n_min:
+            self.gamma = min(1.0, (1.0 + self.kappa) * self.gamma)
+        else:
+            self.gamma = max(self.gamma_min, (1.0 - self.kappa) * self.gamma)
+        self.r.set_step(self.gamma * self.s0)
+        return self.gamma
 
 
 def adam_step(param: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int,
@@ -264,23 +294,32 @@ class RenderFunction(torch.autograd.Function):
     def forward(ctx, tables, mlp, origins, dirs, renderer):
         renderer.load_tables(tables.detach().contiguous())
         renderer.load_mlp(mlp.detach().contiguous())
-        out = renderer.render(origins, dirs, aux=False)
+        n = origins.shape[0]
+        out = {"rgb": torch.empty((n, 3), dtype=torch.float32, device=origins.device),
+               "dist_loss": torch.empty((n,), dtype=torch.float32, device=origins.device)}
+        renderer.render(origins, dirs, out=out)
         ctx.renderer = renderer
         ctx.save_for_backward(origins, dirs)
-        return out["rgb"]
+        return out["rgb"], out["dist_loss"]
 
     @staticmethod
-    def backward(ctx, grad_rgb):
+    def backward(ctx, grad_rgb, grad_dist):
         origins, dirs = ctx.saved_tensors
         r = ctx.renderer
         gt = torch.zeros((r.L, r.T, 9), dtype=torch.float32, device=origins.device)
-        gm = torch.zeros((451,), dtype=torch.float32, device=origins.device)
-        r.backward(origins, dirs, grad_rgb.contiguous().float(), gt, gm)
+        gm = torch.zeros((r.n_mlp,), dtype=torch.float32, device=origins.device)
+        if grad_rgb is None:
+            grad_rgb = torch.zeros((origins.shape[0], 3), dtype=torch.float32, device=origins.device)
+        r.backward(origins, dirs, grad_rgb.contiguous().float(), gt, gm,
+                   None if grad_dist is None else grad_dist.contiguous().float())
         return gt, gm, None, None, None
 
 
-def render_differentiable(renderer: Renderer, tables, mlp, origins, dirs):
-    return RenderFunction.apply(tables, mlp, origins, dirs, renderer)
+def render_differentiable(renderer: Renderer, tables, mlp, origins, dirs, with_dist: bool = False):
+    """rgb (and, with_dist, the per-ray distortion regulariser) as
+    differentiable functions of the tables and the MLP."""
+    rgb, dist = RenderFunction.apply(tables, mlp, origins, dirs, renderer)
+    return (rgb, dist) if with_dist else rgb
 
 
 N_PROPOSAL_PARAMS = 7556

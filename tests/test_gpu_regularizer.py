@@ -1,0 +1,120 @@
+"""GPU distortion regulariser (supplement Eq. S2) and marching-step
+auto-tuning (Eq. S3) through the C ABI, against the float64 oracle."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import distortion
+from oracle.grad import backward64, forward64, frozen_samples, mse_grad, ray_distortion
+from oracle.render import OracleInputs, inputs_from_scene, render
+
+from helpers import gpu_renderer, scene_and_dist, to_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _problem(stride=8):
+    sc, dist = scene_and_dist("tiny")
+    cfg = sc.cfg
+    inp = inputs_from_scene(sc, dist)
+    o, d, _ = synth.scene_rays(cfg)
+    o, d = o[::stride], d[::stride]
+    s_ray, s_pos, _, s_k = frozen_samples(inp, o, d, with_k=True)
+    return cfg, sc, inp, o, d, s_ray, s_pos, s_k
+
+
+def test_render_dist_loss_output():
+    import torch
+    print("[dist loss output]", flush=True)
+    cfg, sc, inp, o, d, s_ray, s_pos, s_k = _problem(4)
+    tab = sc.tables.astype(np.float64)
+    f = forward64(tab, sc.mlp, cfg.resolutions, cfg.step, len(o), s_ray, s_pos)
+    want, _ = ray_distortion(len(o), s_ray, s_k, f["w"], cfg.step)
+    r = gpu_renderer("tiny")
+    go, gd = to_gpu(o, d)
+    out = {"rgb": torch.empty((len(o), 3), device="cuda"), "dist_loss": torch.empty((len(o),), device="cuda")}
+    r.render(go, gd, out=out)
+    got = _np(out["dist_loss"]).astype(np.float64)
+    assert np.abs(got - want).max() <= 1e-5 * max(1.0, np.abs(want).max())
+
+
+def test_backward_with_regulariser_matches_oracle():
+    import torch
+    print("[backward + dist vs oracle]", flush=True)
+    cfg, sc, inp, o, d, s_ray, s_pos, s_k = _problem(8)
+    teacher = synth.make_scene(cfg, seed=1)
+    target = render(inputs_from_scene(teacher, inp.dist), o, d).rgb
+    tab = sc.tables.astype(np.float64)
+    f = forward64(tab, sc.mlp, cfg.resolutions, cfg.step, len(o), s_ray, s_pos)
+    g_rgb = mse_grad(f["rgb"], target)
+    g_dist = np.full(len(o), 0.05)
+    gtab64, gmlp64, _ = backward64(tab, sc.mlp, cfg.resolutions, cfg.step, len(o), s_ray, s_pos, g_rgb,
+                                   grad_dist=g_dist, s_k=s_k)
+    r = gpu_renderer("tiny")
+    go, gd, gg, gdd = to_gpu(o, d, g_rgb.astype(np.float32), g_dist.astype(np.float32))
+    gt = torch.zeros((r.L, r.T, 9), device="cuda")
+    gm = torch.zeros((451,), device="cuda")
+    r.backward(go, gd, gg, gt, gm, gdd)
+    gt, gm = _np(gt), _np(gm)
+    scale = np.abs(gtab64).max()
+    err = np.abs(gt - gtab64)
+    assert np.all(err <= 1e-4 * scale + 1e-3 * np.abs(gtab64)), err.max() / scale
+    assert np.allclose(gm, gmlp64, rtol=1e-3, atol=1e-5 * np.abs(gmlp64).max())
+    # the regulariser changes the table gradient (it is not a no-op)
+    g0, _, _ = backward64(tab, sc.mlp, cfg.resolutions, cfg.step, len(o), s_ray, s_pos, g_rgb)
+    assert np.abs(gtab64 - g0).max() > 10 * 1e-4 * scale
+
+
+def test_autograd_with_regulariser():
+    import torch
+    from paper_2407_10482_amd.renderer import render_differentiable
+    print("[autograd + dist]", flush=True)
+    cfg, sc, inp, o, d, s_ray, s_pos, s_k = _problem(8)
+    r = gpu_renderer("tiny")
+    go, gd = to_gpu(o, d)
+    tables = torch.from_numpy(sc.tables).cuda().requires_grad_(True)
+    mlp = torch.from_numpy(sc.mlp).cuda().requires_grad_(True)
+    rgb, dist = render_differentiable(r, tables, mlp, go, gd, with_dist=True)
+    eta = 0.05
+    loss = (rgb ** 2).mean() + eta * dist.sum()
+    loss.backward()
+    gt = torch.zeros_like(tables)
+    gm = torch.zeros_like(mlp)
+    g_rgb = (2.0 * rgb / rgb.numel()).detach().contiguous()
+    r.backward(go, gd, g_rgb, gt, gm, torch.full((len(o),), eta, device="cuda"))
+    assert torch.allclose(tables.grad, gt, rtol=1e-4, atol=1e-7)
+    assert torch.allclose(mlp.grad, gm, rtol=1e-4, atol=1e-7)
+
+
+def test_set_step_and_autotuner():
+    import torch
+    from paper_2407_10482_amd._lib import NgprtError
+    from paper_2407_10482_amd.renderer import StepAutoTuner
+    print("[set step + auto-tune]", flush=True)
+    sc, dist = scene_and_dist("tiny")
+    cfg = sc.cfg
+    o, d, _ = synth.scene_rays(cfg)
+    o, d = o[::5], d[::5]
+    r = gpu_renderer("tiny")
+    go, gd = to_gpu(o, d)
+    new_step = cfg.step * 0.625
+    r.set_step(new_step)
+    out = r.render(go, gd)
+    inp = OracleInputs(tables=sc.tables, occ=sc.occ, dist=dist, mlp=sc.mlp, resolutions=cfg.resolutions,
+                       domain=cfg.domain, roi_half=cfg.roi_half, step=new_step, max_samples=cfg.max_samples,
+                       t_threshold=cfg.t_threshold)
+    ref = render(inp, o, d)
+    assert np.array_equal(_np(out["n_samples"]), ref.n_samples)
+    assert np.abs(_np(out["rgb"]).astype(np.float64) - ref.rgb).max() < 1e-5
+    with pytest.raises(NgprtError):
+        r.set_step(0.0)
+    tuner = StepAutoTuner(r, cfg.step)
+    g = 1.0
+    for mean in [5.0, 2.0, 2.0, 1.0, 3.0, 4.0] + [0.5] * 50:
+        g = distortion.autotune_gamma(g, mean)
+        assert abs(tuner.update(mean) - g) < 1e-15
+    torch.cuda.synchronize()

@@ -83,3 +83,52 @@ def test_adam_closed_form_first_step():
     p1, m, v = adam_step(p, g, np.zeros(3), np.zeros(3), 1, 0.01)
     # first bias-corrected step: m_hat = g, v_hat = g^2 -> step = lr * g / (|g| + eps)
     assert np.allclose(p1, p - 0.01 * g / (np.abs(g) + 1e-8))
+
+
+def test_distortion_gradient_matches_finite_differences():
+    """The regulariser's gradient through the rendering weights (supplement
+    Eq. S2): a loss sum_r g_r L_dist(r) differentiated analytically against
+    central differences of the table entries."""
+    from oracle.grad import ray_distortion
+    cfg, sc, inp, o, d, s_ray, s_pos, tab, target = _setup(8)
+    s_ray, s_pos, _, s_k = frozen_samples(inp, o, d, with_k=True)
+    n = len(o)
+    gd = np.random.default_rng(3).uniform(0.5, 1.5, size=n)
+    gtab, _, _ = backward64(tab, sc.mlp, cfg.resolutions, cfg.step, n, s_ray, s_pos, np.zeros((n, 3)),
+                            grad_dist=gd, s_k=s_k)
+    rng = np.random.default_rng(4)
+    tch, unt = pick_entries(gtab, 40, 5, rng)
+
+    def loss(t64):
+        f = forward64(t64, sc.mlp, cfg.resolutions, cfg.step, n, s_ray, s_pos)
+        return float((gd * ray_distortion(n, s_ray, s_k, f["w"], cfg.step)[0]).sum())
+    h = 1e-4
+    an, fd = [], []
+    for (l, t, ch) in tch + unt:
+        orig = tab[l, t, ch]
+        tab[l, t, ch] = orig + h
+        lp = loss(tab)
+        tab[l, t, ch] = orig - h
+        lm = loss(tab)
+        tab[l, t, ch] = orig
+        fd.append((lp - lm) / (2 * h))
+        an.append(gtab[l, t, ch])
+    an, fd = np.array(an), np.array(fd)
+    scale = np.abs(an).max()
+    assert scale > 0
+    assert np.all(np.abs(an - fd) <= 1e-4 * scale + 1e-4 * np.abs(fd)), np.abs(an - fd).max() / scale
+    assert np.all(an[len(tch):] == 0.0)
+
+
+def test_ray_distortion_matches_double_sum():
+    from oracle import distortion
+    from oracle.grad import ray_distortion
+    s_ray = np.array([0, 0, 0, 2, 2])
+    s_k = np.array([3, 4, 9, 0, 7])
+    w = np.array([0.2, 0.3, 0.4, 0.6, 0.1])
+    step = 0.01
+    loss, _ = ray_distortion(3, s_ray, s_k, w, step)
+    st = float(np.float32(step))
+    assert abs(loss[0] - distortion.dist_loss_bruteforce(w[:3], s_k[:3] * st, [st] * 3)) < 1e-15
+    assert loss[1] == 0.0
+    assert abs(loss[2] - distortion.dist_loss_bruteforce(w[3:], s_k[3:] * st, [st] * 2)) < 1e-15
