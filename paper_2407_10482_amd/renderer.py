@@ -291,15 +291,21 @@ class RenderFunction(torch.autograd.Function):
     the library and returns dL/dtables and dL/dmlp."""
 
     @staticmethod
-    def forward(ctx, tables, mlp, origins, dirs, renderer):
+    def forward(ctx, tables, mlp, origins, dirs, renderer, with_dist):
         renderer.load_tables(tables.detach().contiguous())
         renderer.load_mlp(mlp.detach().contiguous())
         n = origins.shape[0]
-        out = {"rgb": torch.empty((n, 3), dtype=torch.float32, device=origins.device),
-               "dist_loss": torch.empty((n,), dtype=torch.float32, device=origins.device)}
+        out = {"rgb": torch.empty((n, 3), dtype=torch.float32, device=origins.device)}
+        if with_dist:
+            out["dist_loss"] = torch.empty((n,), dtype=torch.float32, device=origins.device)
         renderer.render(origins, dirs, out=out)
         ctx.renderer = renderer
+        ctx.with_dist = with_dist
         ctx.save_for_backward(origins, dirs)
+        if not with_dist:
+            dist = torch.zeros((n,), dtype=torch.float32, device=origins.device)
+            ctx.mark_non_differentiable(dist)
+            return out["rgb"], dist
         return out["rgb"], out["dist_loss"]
 
     @staticmethod
@@ -310,15 +316,15 @@ class RenderFunction(torch.autograd.Function):
         gm = torch.zeros((r.n_mlp,), dtype=torch.float32, device=origins.device)
         if grad_rgb is None:
             grad_rgb = torch.zeros((origins.shape[0], 3), dtype=torch.float32, device=origins.device)
-        r.backward(origins, dirs, grad_rgb.contiguous().float(), gt, gm,
-                   None if grad_dist is None else grad_dist.contiguous().float())
-        return gt, gm, None, None, None
+        gdist = grad_dist.contiguous().float() if (ctx.with_dist and grad_dist is not None) else None
+        r.backward(origins, dirs, grad_rgb.contiguous().float(), gt, gm, gdist)
+        return gt, gm, None, None, None, None
 
 
 def render_differentiable(renderer: Renderer, tables, mlp, origins, dirs, with_dist: bool = False):
     """rgb (and, with_dist, the per-ray distortion regulariser) as
     differentiable functions of the tables and the MLP."""
-    rgb, dist = RenderFunction.apply(tables, mlp, origins, dirs, renderer)
+    rgb, dist = RenderFunction.apply(tables, mlp, origins, dirs, renderer, with_dist)
     return (rgb, dist) if with_dist else rgb
 
 
