@@ -196,5 +196,27 @@ def tiny_view(seed: int = 0, table_dtype: int = DTYPE_F32) -> SceneConfig:
     return cfg
 
 
-CONFIGS = {"tiny_view": tiny_view, "tiny": tiny, "hd": hd, "train_large": train_large, "baked_tiny": baked_tiny,
+def paper_tiny(seed: int = 0, table_dtype: int = DTYPE_F32) -> SceneConfig:
+    """All of the paper's rendering choices at the tiny scale: the baked
+    feature model (L_C = 64, fine levels 128 and 256), the occupancy pyramid
+    128^3 .. 32^3 with the 64^3 distance grid, and the view-dependent MLP."""
+    cfg = baked_tiny(seed, table_dtype)
+    cfg.name = "paper_tiny"
+    cfg.occ_levels, cfg.occ_fine_res = 3, 128
+    cfg.mlp_dims = (23, 64, 64, 3)
+    return cfg
+
+
+def paper_hd(seed: int = 0, table_dtype: int = DTYPE_F32, n_fine: int = 2) -> SceneConfig:
+    """All of the paper's rendering choices on the hd geometry: baked feature
+    model (L_C = 512, n_fine fine levels), occupancy pyramid 512^3 .. 32^3 +
+    256^3 distance grid, view-dependent MLP."""
+    cfg = baked_hd(seed, table_dtype, n_fine)
+    cfg.name = f"paper_hd_l{n_fine}"
+    cfg.occ_levels, cfg.occ_fine_res = 5, 512
+    cfg.mlp_dims = (23, 64, 64, 3)
+    return cfg
+
+
+CONFIGS = {"paper_tiny": paper_tiny, "paper_hd": paper_hd, "tiny_view": tiny_view, "tiny": tiny, "hd": hd, "train_large": train_large, "baked_tiny": baked_tiny,
            "baked_hd": baked_hd, "tiny_pyramid": tiny_pyramid, "hd_pyramid": hd_pyramid}

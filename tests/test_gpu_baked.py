@@ -147,3 +147,19 @@ def test_baked_hd_full_frame_sampled():
     assert np.array_equal(_np(out["n_reads"])[sel], ref.n_reads)
     assert np.abs(_np(out["rgb"])[sel].astype(np.float64) - ref.rgb).max() < COLOUR_TOL
     assert 5 < ref.n_samples.mean() < 40
+
+
+@pytest.mark.parametrize("dtype", [0, 2])
+def test_paper_configuration_render_parity_tiny(dtype):
+    """Baked feature model + occupancy pyramid with the distance grid +
+    view-dependent MLP together (the paper's rendering choices), tiny scale."""
+    print(f"[paper configuration tiny dtype {dtype}]", flush=True)
+    inp = oracle_inputs("paper_tiny", dtype)
+    sc, _ = scene_and_dist("paper_tiny")
+    o, d, _ = synth.scene_rays(sc.cfg)
+    r = gpu_renderer("paper_tiny", dtype)
+    go, gd = to_gpu(o, d)
+    out = r.render(go, gd)
+    ref = render(inp, o, d)
+    assert ref.n_samples.mean() > 5
+    _check_render(out, ref)
