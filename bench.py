@@ -366,12 +366,15 @@ def main():
         cfg = synth.baked_hd(table_dtype=dtype, n_fine=args.fine_levels)
         if pyr:
             cfg.occ_levels, cfg.occ_fine_res = 5, 512
+        if args.mlp == "view":
+            cfg.mlp_dims = (23, 64, 64, 3)
         sc = make_baked_scene(cfg)
     else:
         cfg = synth.hd_pyramid(table_dtype=dtype) if pyr else synth.hd(table_dtype=dtype)
         if args.mlp == "view":
             cfg.mlp_dims = (23, 64, 64, 3)
         sc = synth.make_scene(cfg)
+    assert (args.mlp == "view") == (tuple(cfg.mlp_dims) == (23, 64, 64, 3))
     cams = synth.camera_positions(cfg)[: args.views]
     o, d, _ = synth.scene_rays(cfg, cams=cams, group=args.group)
     print(f"# scene + rays generated in {time.time() - t0:.1f} s ({len(o)} rays)", file=sys.stderr,
