@@ -146,34 +146,23 @@ __device__ __forceinline__ bool march_next(const SceneArgs& S, MarchState& m, bo
       // reads counts marching points (lattice points checked), whatever the
       // number of levels read there
       ++reads;
-      // the voxel of level j is the finest level's index >> j (the levels'
-      // resolutions are powers of two, so floor(u R_j) = floor(u R_0) >> j);
-      // every level's word is loaded at once (independent loads), then the
-      // exiting level is the coarsest unoccupied one (emptiness is monotone
-      // from coarse to fine, as each level is the OR of its children)
-      const int R0 = S.pyrR[0];
-      int q0[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        int i = (int)floorf(u[a] * (float)R0);
-        q0[a] = i < 0 ? 0 : (i > R0 - 1 ? R0 - 1 : i);
-      }
-      const int jtop = naive ? 0 : S.pyr_n - 1;
-      uint32_t occ_bits = 0;
-#pragma unroll
-      for (int j = 0; j < kMaxPyr; ++j) {
-        if (j <= jtop) {
-          const uint32_t Rj = uint32_t(S.pyrR[j]);
-          const uint32_t x = uint32_t(q0[0]) >> j, y = uint32_t(q0[1]) >> j, z = uint32_t(q0[2]) >> j;
-          const uint32_t w = S.pyr[j][((size_t(z) * Rj + y) * Rj + x) >> 5];
-          occ_bits |= ((w >> (x & 31u)) & 1u) << j;
-        }
-      }
-      const uint32_t empty = ~occ_bits & ((2u << jtop) - 1u);
-      const int lev = empty ? 31 - __clz(empty) : -1;
+      int lev = -1;
       int qe[3] = {0, 0, 0};
-      if (lev >= 0) {
-        qe[0] = q0[0] >> lev; qe[1] = q0[1] >> lev; qe[2] = q0[2] >> lev;
+      for (int j = naive ? 0 : S.pyr_n - 1; j >= 0; --j) {
+        const int Rj = S.pyrR[j];
+        int q[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          int i = (int)floorf(u[a] * (float)Rj);
+          q[a] = i < 0 ? 0 : (i > Rj - 1 ? Rj - 1 : i);
+        }
+        const uint32_t w =
+            S.pyr[j][(size_t(q[2]) * Rj + q[1]) * size_t(Rj >> 5) + size_t(q[0] >> 5)];
+        if (!((w >> (q[0] & 31)) & 1u)) {
+          lev = j;
+          qe[0] = q[0]; qe[1] = q[1]; qe[2] = q[2];
+          break;
+        }
       }
       if (lev < 0) {
         ts = tcur;
