@@ -139,3 +139,78 @@ def fused64(inp, u: np.ndarray):
         fused[:, 1:] += gb[:, None] * v[:, 1:]
         gws.append(gw)
     return fused, np.stack(gws, axis=1)
+
+
+# --------------------------------------------------------------------------
+# float64 forward intermediates and the adjoint of the feature construction
+# (for the training extension; the sample list is frozen)
+
+
+def forward64_parts(atlas64, default, block_index, Lc, fine64, resolutions, u):
+    """fused [m, 8] and the intermediates the adjoint needs, at float64 grid
+    coordinates u (fine64: [L, T, >=8] float64 fine tables)."""
+    u = np.asarray(u, dtype=np.float64)
+    m = u.shape[0]
+    T = fine64.shape[1]
+    p = u * Lc
+    i0 = np.clip(np.floor(p), 0, Lc - 1).astype(np.int64)
+    f = p - i0
+    C = atlas64.shape[-1]
+    co = np.zeros((m, C))
+    cv, cw, cb = [], [], []
+    for c in range(8):
+        b = ((c >> 0) & 1, (c >> 1) & 1, (c >> 2) & 1)
+        wc = np.ones(m)
+        for a in range(3):
+            wc = wc * (f[:, a] if b[a] else 1.0 - f[:, a])
+        vx, vy, vz = i0[:, 0] + b[0], i0[:, 1] + b[1], i0[:, 2] + b[2]
+        bid = block_index[vz >> 3, vy >> 3, vx >> 3]
+        if atlas64.shape[0]:
+            rows = atlas64[np.maximum(bid, 0), vz & 7, vy & 7, vx & 7]
+            vals = np.where((bid >= 0)[:, None], rows, np.asarray(default, np.float64)[None, :])
+        else:
+            vals = np.broadcast_to(np.asarray(default, np.float64), (m, C))
+        co += wc[:, None] * vals
+        cv.append(np.stack([vx, vy, vz], axis=1))
+        cw.append(wc)
+        cb.append(bid)
+    fused = co[:, :8].copy()
+    fidx, fw, fval, gws, gbs = [], [], [], [], []
+    for l, N in enumerate(resolutions):
+        idx, w = corners64(u, N, T)
+        v = np.einsum("mc,mcd->md", w, fine64[l][idx][:, :, :8])
+        gw = 1.0 / (1.0 + np.exp(-co[:, 8 + 2 * l]))
+        gb = 1.0 / (1.0 + np.exp(-co[:, 9 + 2 * l]))
+        fused[:, 0] += gw * v[:, 0]
+        fused[:, 1:] += gb[:, None] * v[:, 1:]
+        fidx.append(idx); fw.append(w); fval.append(v); gws.append(gw); gbs.append(gb)
+    return fused, dict(co=co, cv=np.stack(cv, 1), cw=np.stack(cw, 1), cb=np.stack(cb, 1),
+                       fidx=fidx, fw=fw, fval=fval, gw=gws, gb=gbs)
+
+
+def scatter64(parts, g_fused, n_blocks, C, fine_shape):
+    """Adjoint of the feature construction: dL/d(atlas) [n_blocks, 8, 8, 8, C]
+    and dL/d(fine tables) [L, T, 9] (channel 8 zero) from dL/dfused [m, 8].
+    f_0 = co_0 + sum_l g(omega_l) s_l, f_j = co_j + sum_l g(beta_l) v_lj:
+    dco_j = df_j (j < 8); dco_omega_l = df_0 s_l g'(omega_l);
+    dco_beta_l = sum_{j>=1} df_j v_lj g'(beta_l); dv_l0 = df_0 g(omega_l);
+    dv_lj = df_j g(beta_l).  Empty-block vertices (the default vector) take
+    no gradient."""
+    m = g_fused.shape[0]
+    g_co = np.zeros((m, C))
+    g_co[:, :8] = g_fused
+    g_fine = np.zeros(fine_shape)
+    for l in range(len(parts["fidx"])):
+        gw, gb, v = parts["gw"][l], parts["gb"][l], parts["fval"][l]
+        g_co[:, 8 + 2 * l] = g_fused[:, 0] * v[:, 0] * gw * (1.0 - gw)
+        g_co[:, 9 + 2 * l] = (g_fused[:, 1:] * v[:, 1:]).sum(axis=1) * gb * (1.0 - gb)
+        gv = np.concatenate([(g_fused[:, 0] * gw)[:, None], g_fused[:, 1:] * gb[:, None]], axis=1)
+        for c in range(8):
+            np.add.at(g_fine[l][:, :8], parts["fidx"][l][:, c], parts["fw"][l][:, c][:, None] * gv)
+    g_atlas = np.zeros((n_blocks, 8, 8, 8, C))
+    for c in range(8):
+        bid = parts["cb"][:, c]
+        ok = bid >= 0
+        vx, vy, vz = parts["cv"][ok, c, 0], parts["cv"][ok, c, 1], parts["cv"][ok, c, 2]
+        np.add.at(g_atlas, (bid[ok], vz & 7, vy & 7, vx & 7), parts["cw"][ok, c][:, None] * g_co[ok])
+    return g_atlas, g_fine

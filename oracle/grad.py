@@ -27,7 +27,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import distortion
+from . import baked, distortion
 from .hashgrid import corners64
 from .render import OracleInputs, grid_coords64, march, mlp64
 
@@ -86,16 +86,25 @@ def _levels64(tables64, resolutions, T, u):
     return np.stack(vals, axis=1), np.stack(idxs, axis=1), np.stack(ws, axis=1)
 
 
-def forward64(tables64, mlp, resolutions, step, n_rays, s_ray, s_pos, roi_half=1.0):
-    """Float64 forward on a frozen sample list; returns rgb and intermediates."""
+def forward64(tables64, mlp, resolutions, step, n_rays, s_ray, s_pos, roi_half=1.0, coarse=None):
+    """Float64 forward on a frozen sample list; returns rgb and intermediates.
+    coarse: None (hash model: tables64 are the hash levels, fused by softmax)
+    or dict(atlas=, default=, block_index=, res=) for the baked model
+    (tables64 are then the fine levels; see oracle.baked)."""
     T = tables64.shape[1]
     u = grid_u(s_pos, roi_half)
-    lv, idx, wc = _levels64(tables64, resolutions, T, u)
-    a = lv[:, :, 8]
-    a = a - a.max(axis=1, keepdims=True)
-    e = np.exp(a)
-    wl = e / e.sum(axis=1, keepdims=True)
-    fused = np.einsum("ml,mlc->mc", wl, lv[:, :, :8])
+    if coarse is not None:
+        fused, parts = baked.forward64_parts(coarse["atlas"], coarse["default"], coarse["block_index"],
+                                             coarse["res"], tables64, resolutions, u)
+        lv = idx = wc = wl = None
+    else:
+        parts = None
+        lv, idx, wc = _levels64(tables64, resolutions, T, u)
+        a = lv[:, :, 8]
+        a = a - a.max(axis=1, keepdims=True)
+        e = np.exp(a)
+        wl = e / e.sum(axis=1, keepdims=True)
+        fused = np.einsum("ml,mlc->mc", wl, lv[:, :, :8])
     sigma = np.exp(fused[:, 0])
     delta = float(np.float32(step))
     ee = np.exp(-sigma * delta)
@@ -122,7 +131,8 @@ def forward64(tables64, mlp, resolutions, step, n_rays, s_ray, s_pos, roi_half=1
     o = h2 @ W2.T + b2
     rgb = 1.0 / (1.0 + np.exp(-(c_d + o)))
     return dict(rgb=rgb, c_d=c_d, feat=feat, x=x, z1=z1, h1=h1, z2=z2, h2=h2, fused=fused,
-                sigma=sigma, ee=ee, Tb=Tb, w=w, wl=wl, lv=lv, idx=idx, wc=wc, delta=delta)
+                sigma=sigma, ee=ee, Tb=Tb, w=w, wl=wl, lv=lv, idx=idx, wc=wc, delta=delta,
+                parts=parts)
 
 
 def loss64(tables64, mlp, resolutions, step, n_rays, s_ray, s_pos, target, roi_half=1.0):
@@ -131,13 +141,14 @@ def loss64(tables64, mlp, resolutions, step, n_rays, s_ray, s_pos, target, roi_h
 
 
 def backward64(tables64, mlp, resolutions, step, n_rays, s_ray, s_pos, grad_rgb, roi_half=1.0,
-               grad_dist=None, s_k=None):
+               grad_dist=None, s_k=None, coarse=None):
     """dL/dtables [L, T, 9] and dL/dmlp [451] for an upstream dL/drgb [n, 3]
     and, optionally, dL/d(distortion regulariser) per ray [n] (s_k: the
     samples' lattice indices).  The regulariser enters as dL/dw_i, which
     adds g_r dL_dist/dw_i to s_i and g_r sum_i w_i dL_dist/dw_i = 2 g_r L_dist
-    to S."""
-    f = forward64(tables64, mlp, resolutions, step, n_rays, s_ray, s_pos, roi_half)
+    to S.  With `coarse` (the baked model) the first result is the pair
+    (dL/datlas [n_blocks, 8, 8, 8, C], dL/dfine tables [L, T, 9])."""
+    f = forward64(tables64, mlp, resolutions, step, n_rays, s_ray, s_pos, roi_half, coarse)
     W0, b0, W1, b1, W2, b2 = _split_mlp(mlp)
     rgb = f["rgb"]
     gz = grad_rgb * rgb * (1.0 - rgb)
@@ -176,6 +187,11 @@ def backward64(tables64, mlp, resolutions, step, n_rays, s_ray, s_pos, grad_rgb,
     g_fused[:, 0] = g_sigma * sigma
     g_fused[:, 1:4] = w[:, None] * g_cd[s_ray]
     g_fused[:, 4:8] = w[:, None] * g_f[s_ray]
+    if coarse is not None:
+        atlas = coarse["atlas"]
+        g_atlas, g_fine = baked.scatter64(f["parts"], g_fused, atlas.shape[0], atlas.shape[-1],
+                                          tables64.shape)
+        return (g_atlas, g_fine), gmlp, f
     wl, lv = f["wl"], f["lv"]
     g_v = wl[:, :, None] * g_fused[:, None, :]                   # [m, L, 8]
     g_w = np.einsum("mc,mlc->ml", g_fused, lv[:, :, :8])

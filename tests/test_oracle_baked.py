@@ -188,3 +188,50 @@ def test_baked_scene_march_skip_equals_naive():
     b = render(inp, o[sel], d[sel], naive=True)
     assert np.array_equal(a.s_ray, b.s_ray) and np.array_equal(a.s_k, b.s_k)
     assert 10 < a.n_samples.mean() < 30
+
+
+def test_baked_gradient_matches_finite_differences():
+    """The adjoint of the baked feature construction (coarse atlas rows,
+    sigmoid gates, fine tables) through compositing and the MLP, against
+    central differences of an MSE loss in float64."""
+    import synth
+    from synth.baked import make_baked_scene
+    from oracle.grad import backward64, forward64, frozen_samples, mse_grad
+    from oracle.render import inputs_from_scene
+    cfg = synth.baked_tiny()
+    sc = make_baked_scene(cfg)
+    inp = inputs_from_scene(sc, distance_grid_edt(sc.occ))
+    o, d, _ = synth.scene_rays(cfg)
+    o, d = o[::16], d[::16]
+    s_ray, s_pos, _ = frozen_samples(inp, o, d)
+    n = len(o)
+    atlas = sc.atlas.astype(np.float64)
+    fine = sc.tables.astype(np.float64)
+    coarse = dict(atlas=atlas, default=sc.default.astype(np.float64), block_index=sc.block_index,
+                  res=cfg.coarse_res)
+    target = np.random.default_rng(0).random((n, 3))
+
+    def loss():
+        f = forward64(fine, sc.mlp, cfg.resolutions, cfg.step, n, s_ray, s_pos, coarse=coarse)
+        return float(np.mean((f["rgb"] - target) ** 2))
+    f = forward64(fine, sc.mlp, cfg.resolutions, cfg.step, n, s_ray, s_pos, coarse=coarse)
+    (g_atlas, g_fine), _, _ = backward64(fine, sc.mlp, cfg.resolutions, cfg.step, n, s_ray, s_pos,
+                                         mse_grad(f["rgb"], target), coarse=coarse)
+    rng = np.random.default_rng(1)
+    h = 1e-5
+    checked = 0
+    for arr, g in ((atlas, g_atlas), (fine, g_fine)):
+        nz = np.argwhere(g != 0)
+        for e in nz[rng.choice(len(nz), size=25, replace=False)]:
+            e = tuple(e)
+            orig = arr[e]
+            arr[e] = orig + h
+            lp = loss()
+            arr[e] = orig - h
+            lm = loss()
+            arr[e] = orig
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - g[e]) <= 1e-4 * np.abs(g).max() + 1e-4 * abs(fd), (e, fd, g[e])
+            checked += 1
+    assert checked == 50
+    assert np.all(g_fine[..., 8] == 0)
