@@ -78,35 +78,49 @@ def bench_train(args):
     import torch
 
     import synth
-    from paper_2407_10482_amd.renderer import Renderer, adam_step, render_differentiable
+    from paper_2407_10482_amd.renderer import (Renderer, adam_step, render_differentiable,
+                                               render_differentiable_baked)
 
-    cfg = synth.CONFIGS[args.train_size]()
-    sc = synth.make_scene(cfg)
-    teacher = synth.make_scene(cfg, seed=1)
+    baked = args.model == "baked"
+    if baked:
+        from synth.baked import make_baked_scene
+        if args.train_size != "tiny":
+            raise SystemExit("--mode train --model baked trains the baked model of the tiny scene only")
+        cfg = synth.baked_tiny()
+        sc, teacher = make_baked_scene(cfg), make_baked_scene(cfg, seed=1)
+    else:
+        cfg = synth.CONFIGS[args.train_size]()
+        sc, teacher = synth.make_scene(cfg), synth.make_scene(cfg, seed=1)
     cams = synth.random_sphere_cameras(16, 1.0, seed=123)
     o, d, _ = synth.scene_rays(cfg, cams=cams, width=128, height=128)
     torch.cuda.set_device(0)
     r = Renderer.from_config(cfg)
     r.load_scene(torch.from_numpy(teacher.tables).cuda(), torch.from_numpy(sc.occ).cuda(),
                  torch.from_numpy(sc.mlp).cuda())
+    if baked:
+        r.load_coarse(torch.from_numpy(sc.block_index).cuda(), torch.from_numpy(teacher.atlas).cuda(),
+                      teacher.default)
     go, gd = torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda()
     target = r.render(go, gd, aux=False)["rgb"].clone()
-    tables = torch.from_numpy(sc.tables).cuda().requires_grad_(True)
-    mlp = torch.from_numpy(sc.mlp).cuda().requires_grad_(True)
-    mt, vt = torch.zeros_like(tables), torch.zeros_like(tables)
-    mm, vm = torch.zeros_like(mlp), torch.zeros_like(mlp)
+    params = [torch.from_numpy(sc.tables).cuda().requires_grad_(True)]
+    if baked:
+        params.append(torch.from_numpy(sc.atlas).cuda().requires_grad_(True))
+    params.append(torch.from_numpy(sc.mlp).cuda().requires_grad_(True))
+    moments = [(torch.zeros_like(p), torch.zeros_like(p)) for p in params]
     state = {"step": 0, "loss": []}
 
     def step():
-        rgb = render_differentiable(r, tables, mlp, go, gd)
+        if baked:
+            rgb = render_differentiable_baked(r, *params, go, gd)
+        else:
+            rgb = render_differentiable(r, *params, go, gd)
         loss = torch.mean((rgb - target) ** 2)
         loss.backward()
         state["step"] += 1
         with torch.no_grad():
-            adam_step(tables, tables.grad, mt, vt, state["step"], 0.01)
-            adam_step(mlp, mlp.grad, mm, vm, state["step"], 0.01)
-        tables.grad = None
-        mlp.grad = None
+            for p, (m, v) in zip(params, moments):
+                adam_step(p, p.grad, m, v, state["step"], 0.01)
+                p.grad = None
         return loss
 
     first = step().item()
@@ -120,7 +134,7 @@ def bench_train(args):
     end.record()
     torch.cuda.synchronize()
     ms = start.elapsed_time(end) / args.steps
-    n_params = tables.numel() + mlp.numel()
+    n_params = sum(p.numel() for p in params)
     return {
         "metric": "training steps/s (render + backward + Adam)",
         "value": round(1e3 / ms, 3),
@@ -128,7 +142,10 @@ def bench_train(args):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{cfg.name}: {cfg.n_levels} levels {cfg.n_min}..{cfg.n_max}, "
+        "config": {"workload": f"{cfg.name}: "
+                               + (f"coarse grid L_C = {cfg.coarse_res} ({sc.atlas.shape[0]} blocks of 8^3) + "
+                                  if baked else "")
+                               + f"{cfg.n_levels} levels {cfg.n_min}..{cfg.n_max}, "
                                f"2^{cfg.log2_table} entries, 2^18 rays from 16 cameras x 128^2, "
                                "MSE vs a seed-1 teacher, Adam lr 0.01",
                    "rays_per_step": len(o), "parameters": n_params},

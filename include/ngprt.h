@@ -282,6 +282,24 @@ int ngprt_render_backward_reg(ngprt_ctx* ctx, int64_t n_rays, const float* dev_o
                               const float* dev_dirs, const float* dev_grad_rgb, const float* dev_grad_dist,
                               float* dev_grad_tables, float* dev_grad_mlp, void* stream);
 
+/* ngprt_render_backward_reg for the baked feature model (Sec. 4.1 Eq. 6,
+ * Sec. 4.2 Eq. 7-8): f = f~ + [sum_l g(omega_l) sigma^_l, sum_l g(beta_l)
+ * c^_l, sum_l g(beta_l) v^_l], g the sigmoid.  Accumulates (+=)
+ * dL/d(fine tables) into dev_grad_tables, float32 [L][T][9] (channel 8 is
+ * not written: the baked model has no per-level logit), and dL/d(atlas)
+ * into dev_grad_atlas, float32 [n_blocks][8][8][8][8 + 2L] in the layout
+ * ngprt_load_coarse takes (NULL allowed when n_blocks = 0); the default
+ * vector of empty blocks takes no gradient; dL/dmlp into dev_grad_mlp
+ * [451].  The caller zeroes all three; the updated atlas is handed back
+ * with ngprt_load_coarse (the library keeps a padded copy).  Atomics make
+ * the low bits order-dependent, as for the hash model.  Needs float32
+ * tables (NGPRT_E_DTYPE), NGPRT_MODEL_BAKED and the 7-16-16-3 MLP
+ * (NGPRT_E_UNSUPPORTED otherwise); same workspace note. */
+int ngprt_render_backward_baked(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins,
+                                const float* dev_dirs, const float* dev_grad_rgb, const float* dev_grad_dist,
+                                float* dev_grad_tables, float* dev_grad_atlas, float* dev_grad_mlp,
+                                void* stream);
+
 /* Change the lattice step (the paper's marching-step auto-tuning,
  * supplement Eq. S3, scales it between training batches).  Same checks as
  * desc.step (NGPRT_E_INVALID_ARG).  Later calls use the new step. */

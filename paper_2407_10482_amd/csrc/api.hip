@@ -233,16 +233,22 @@ int ngprt_load_coarse(ngprt_ctx* ctx, int64_t n_blocks, const int32_t* dev_block
     if (idx[size_t(i)] < -1 || idx[size_t(i)] >= n_blocks)
       return fail(ctx, NGPRT_E_INVALID_ARG, "block index entry outside [-1, n_blocks)");
   const int C = 8 + 2 * d.n_levels, Cpad = coarse_row_floats(d.n_levels);
-  if (ctx->cidx) (void)hipFree(ctx->cidx);
-  if (ctx->catlas) (void)hipFree(ctx->catlas);
-  ctx->cidx = nullptr;
-  ctx->catlas = nullptr;
   ctx->coarse_loaded = false;
-  if (hipMalloc((void**)&ctx->cidx, sizeof(int32_t) * n_idx) != hipSuccess ||
-      (n_blocks > 0 &&
-       hipMalloc((void**)&ctx->catlas, sizeof(float) * size_t(n_blocks) * 512 * Cpad) != hipSuccess)) {
-    (void)hipGetLastError();
-    return fail(ctx, NGPRT_E_ALLOC, "coarse grid allocation failed");
+  // same block count as the loaded grid (a training step's update): keep the
+  // allocations; the index grid's size is fixed by the descriptor
+  const bool reuse = ctx->cidx != nullptr && ctx->n_blocks == n_blocks && (n_blocks == 0 || ctx->catlas);
+  if (!reuse) {
+    if (ctx->cidx) (void)hipFree(ctx->cidx);
+    if (ctx->catlas) (void)hipFree(ctx->catlas);
+    ctx->cidx = nullptr;
+    ctx->catlas = nullptr;
+    ctx->n_blocks = -1;
+    if (hipMalloc((void**)&ctx->cidx, sizeof(int32_t) * n_idx) != hipSuccess ||
+        (n_blocks > 0 &&
+         hipMalloc((void**)&ctx->catlas, sizeof(float) * size_t(n_blocks) * 512 * Cpad) != hipSuccess)) {
+      (void)hipGetLastError();
+      return fail(ctx, NGPRT_E_ALLOC, "coarse grid allocation failed");
+    }
   }
   if (hipMemcpyAsync(ctx->cidx, idx.data(), sizeof(int32_t) * n_idx, hipMemcpyHostToDevice, st) !=
       hipSuccess)
@@ -410,7 +416,29 @@ int ngprt_render_backward_reg(ngprt_ctx* ctx, int64_t n_rays, const float* dev_o
   if (rc) return rc;
   if (!ctx->mlp_loaded) return fail(ctx, NGPRT_E_NOT_LOADED, "mlp not loaded");
   return launch_backward(ctx, n_rays, dev_origins, dev_dirs, dev_grad_rgb, dev_grad_dist, dev_grad_tables,
-                         dev_grad_mlp, (hipStream_t)stream);
+                         nullptr, dev_grad_mlp, (hipStream_t)stream);
+}
+
+int ngprt_render_backward_baked(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins, const float* dev_dirs,
+                                const float* dev_grad_rgb, const float* dev_grad_dist, float* dev_grad_tables,
+                                float* dev_grad_atlas, float* dev_grad_mlp, void* stream) {
+  if (!ctx) return NGPRT_E_INVALID_ARG;
+  if (n_rays < 0) return fail(ctx, NGPRT_E_INVALID_ARG, "n_rays < 0");
+  if (n_rays == 0) return NGPRT_OK;
+  if (!dev_origins || !dev_dirs || !dev_grad_rgb || !dev_grad_tables || !dev_grad_mlp)
+    return fail(ctx, NGPRT_E_INVALID_ARG, "NULL pointer");
+  if (ctx->desc.table_dtype != NGPRT_F32)
+    return fail(ctx, NGPRT_E_DTYPE, "backward needs float32 tables");
+  if (ctx->desc.feature_model != NGPRT_MODEL_BAKED)
+    return fail(ctx, NGPRT_E_UNSUPPORTED, "ngprt_render_backward_baked needs the baked feature model");
+  if (is_view_mlp(&ctx->desc))
+    return fail(ctx, NGPRT_E_UNSUPPORTED, "backward supports the 7-16-16-3 deferred MLP only");
+  int rc = check_ready(ctx);
+  if (rc) return rc;
+  if (!ctx->mlp_loaded) return fail(ctx, NGPRT_E_NOT_LOADED, "mlp not loaded");
+  if (ctx->n_blocks > 0 && !dev_grad_atlas) return fail(ctx, NGPRT_E_INVALID_ARG, "NULL pointer");
+  return launch_backward(ctx, n_rays, dev_origins, dev_dirs, dev_grad_rgb, dev_grad_dist, dev_grad_tables,
+                         dev_grad_atlas, dev_grad_mlp, (hipStream_t)stream);
 }
 
 int ngprt_render_backward(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins, const float* dev_dirs,

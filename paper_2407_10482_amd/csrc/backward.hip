@@ -49,12 +49,168 @@ __device__ __forceinline__ bf32x4 wave_outer_sum(const float* sA, const float* s
   return acc;
 }
 
-template <int DOM, int LMAX, bool PYR>
+// Adjoint of the baked feature construction at one sample (Sec. 4.2 Eq. 7-8):
+// with f_0 = f~_0 + sum_l g(omega_l) s_l and f_j = f~_j + sum_l g(beta_l) v_lj
+// (j >= 1), dL/df (gf) gives
+//   fine level l:  dL/dv_l0 = gf_0 g(omega_l),  dL/dv_lj = gf_j g(beta_l),
+//   coarse row:    dL/df~_j = gf_j,
+//                  dL/domega_l = gf_0 s_l g'(omega_l),
+//                  dL/dbeta_l = sum_{j>=1} gf_j v_lj g'(beta_l),
+// each spread trilinearly over its 8 corners; g' = g (1 - g).  Vertices of
+// empty blocks take the default vector and receive no gradient.  Every lane
+// of the wave takes part (have = false: no contribution) so that equal
+// entries are summed across the wave before one lane issues their atomics.
+// gtab: [L][T][9] (channel 8, the hash model's logit, untouched); gatlas:
+// [n_blocks][8][8][8][C], C = 8 + 2 L.
+template <int LMAX>
+__device__ __forceinline__ void baked_scatter(const SceneArgs& S, const float u[3], bool have, const float gf[8],
+                                              float* __restrict__ gtab, float* __restrict__ gatlas) {
+  static_assert(LMAX <= 4, "the coarse row holds at most 16 channels");
+  constexpr int CMAX = 8 + 2 * LMAX;
+  const int C = 8 + 2 * S.L;
+  int i0[3];
+  float fr[3], gr[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float p = u[a] * S.LCf;
+    int i = (int)floorf(p);
+    i = i < 0 ? 0 : (i > S.LC - 1 ? S.LC - 1 : i);
+    i0[a] = i;
+    fr[a] = __builtin_fmaf(u[a], S.LCf, -(float)i);
+    gr[a] = 1.0f - fr[a];
+  }
+  // interpolated attention parameters (coarse channels 8 .. 8 + 2L)
+  float ap[2 * LMAX];
+#pragma unroll
+  for (int j = 0; j < 2 * LMAX; ++j) ap[j] = 0.0f;
+  if (have) {
+#pragma unroll 1
+    for (int k = 0; k < 8; ++k) {
+      const int bx = k & 1, by = (k >> 1) & 1, bz = (k >> 2) & 1;
+      const int vx = i0[0] + bx, vy = i0[1] + by, vz = i0[2] + bz;
+      const int bid = S.cidx[((vz >> 3) * S.nb + (vy >> 3)) * S.nb + (vx >> 3)];
+      const float wk = ((bx ? fr[0] : gr[0]) * (by ? fr[1] : gr[1])) * (bz ? fr[2] : gr[2]);
+      float v[8];
+      if (bid >= 0) {
+        const float4* row = reinterpret_cast<const float4*>(
+            S.catlas + (size_t(bid) * 512 + size_t(((vz & 7) * 8 + (vy & 7)) * 8 + (vx & 7))) * S.Cpad);
+        const float4 q2 = row[2];
+        const float4 q3 = S.Cpad > 12 ? row[3] : make_float4(0.f, 0.f, 0.f, 0.f);
+        v[0] = q2.x; v[1] = q2.y; v[2] = q2.z; v[3] = q2.w;
+        v[4] = q3.x; v[5] = q3.y; v[6] = q3.z; v[7] = q3.w;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = S.cdef[8 + j];
+      }
+#pragma unroll
+      for (int j = 0; j < 2 * LMAX; ++j) ap[j] = __builtin_fmaf(wk, v[j], ap[j]);
+    }
+  }
+  float gco[CMAX];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) gco[j] = have ? gf[j] : 0.0f;
+#pragma unroll
+  for (int j = 8; j < CMAX; ++j) gco[j] = 0.0f;
+  const size_t T_entries = size_t(1) << S.log2T;
+  // fine levels: values for the gate gradients, then the 8-channel scatter
+#pragma unroll
+  for (int l = 0; l < LMAX; ++l) {
+    if (l >= S.L) break;
+    Corners c;
+    level_corners(u, S.N[l], S.Nf[l], S.mask, c);
+    float gv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) gv[j] = 0.0f;
+    if (have) {
+      const void* fb = feat_level<DT_F32>(S.feat, l, S.log2T);
+      float acc[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[j] = 0.0f;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        float v[8];
+        Store<DT_F32>::feat(fb, c.idx[k], v);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[j] = __builtin_fmaf(c.w[k], v[j], acc[j]);
+      }
+      const float gw = sigmoid32(ap[2 * l]), gb = sigmoid32(ap[2 * l + 1]);
+      float tb = 0.0f;
+#pragma unroll
+      for (int j = 1; j < 8; ++j) tb = __builtin_fmaf(gf[j], acc[j], tb);
+      gco[8 + 2 * l] = gf[0] * acc[0] * (gw * (1.0f - gw));
+      gco[9 + 2 * l] = tb * (gb * (1.0f - gb));
+      gv[0] = gf[0] * gw;
+#pragma unroll
+      for (int j = 1; j < 8; ++j) gv[j] = gf[j] * gb;
+    }
+    float* gbase = gtab + (size_t(l) * T_entries) * 9;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      bool pending = have;
+      uint64_t pm = __ballot(pending);
+      while (pm) {
+        const int leader = __ffsll((unsigned long long)pm) - 1;
+        const uint32_t key = __shfl(c.idx[k], leader, 64);
+        const bool mine = pending && c.idx[k] == key;
+        float x[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) x[j] = mine ? c.w[k] * gv[j] : 0.0f;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) x[j] += __shfl_xor(x[j], off, 64);
+        }
+        if ((threadIdx.x & 63) == leader) {
+          float* dst = gbase + size_t(key) * 9;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) unsafeAtomicAdd(dst + j, x[j]);
+        }
+        pending = pending && !mine;
+        pm = __ballot(pending);
+      }
+    }
+  }
+  // coarse rows: one vertex = (atlas row, local offset)
+#pragma unroll 1
+  for (int k = 0; k < 8; ++k) {
+    const int bx = k & 1, by = (k >> 1) & 1, bz = (k >> 2) & 1;
+    const int vx = i0[0] + bx, vy = i0[1] + by, vz = i0[2] + bz;
+    const int bid = have ? S.cidx[((vz >> 3) * S.nb + (vy >> 3)) * S.nb + (vx >> 3)] : -1;
+    const int loc = ((vz & 7) * 8 + (vy & 7)) * 8 + (vx & 7);
+    const float wk = ((bx ? fr[0] : gr[0]) * (by ? fr[1] : gr[1])) * (bz ? fr[2] : gr[2]);
+    bool pending = bid >= 0;
+    uint64_t pm = __ballot(pending);
+    while (pm) {
+      const int leader = __ffsll((unsigned long long)pm) - 1;
+      const int kb = __shfl(bid, leader, 64), kl = __shfl(loc, leader, 64);
+      const bool mine = pending && bid == kb && loc == kl;
+      float x[CMAX];
+#pragma unroll
+      for (int j = 0; j < CMAX; ++j) x[j] = mine ? wk * gco[j] : 0.0f;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int j = 0; j < CMAX; ++j) x[j] += __shfl_xor(x[j], off, 64);
+      }
+      if ((threadIdx.x & 63) == leader) {
+        float* dst = gatlas + (size_t(kb) * 512 + size_t(kl)) * size_t(C);
+#pragma unroll
+        for (int j = 0; j < CMAX; ++j)
+          if (j < C) unsafeAtomicAdd(dst + j, x[j]);
+      }
+      pending = pending && !mine;
+      pm = __ballot(pending);
+    }
+  }
+}
+
+template <int DOM, int LMAX, bool PYR, int MODEL>
 __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, const float* __restrict__ O,
                                                        const float* __restrict__ D,
                                                        const float* __restrict__ grad_rgb,
                                                        const float* __restrict__ grad_dist,
-                                                       float* __restrict__ gtab, float* __restrict__ partial,
+                                                       float* __restrict__ gtab, float* __restrict__ gatlas,
+                                                       float* __restrict__ partial,
                                                        const float* __restrict__ P) {
   __shared__ float sA_all[4][64 * kPad];
   __shared__ float sB_all[4][64 * kPad];
@@ -82,7 +238,7 @@ __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, c
     if (__ballot(have) == 0) break;
     if (have) {
       float f[8];
-      eval_fused<DT_F32, LMAX>(S, u, f);
+      eval_sample<MODEL, DT_F32, LMAX>(S, u, f);
       const float sigma = exp32(f[0]);
       const float e = exp32(-(sigma * S.step));
       const float w = T * (1.0f - e);
@@ -237,8 +393,12 @@ __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, c
     float gf[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, wl[LMAX], gff = 0.0f;
     if (have) {
       float f[8];
-      int32_t idx_unused[LMAX * 8];
-      eval_fused<DT_F32, LMAX, true>(S, u, f, wl, idx_unused);
+      if constexpr (MODEL == 1) {
+        eval_baked<DT_F32, LMAX>(S, u, f);
+      } else {
+        int32_t idx_unused[LMAX * 8];
+        eval_fused<DT_F32, LMAX, true>(S, u, f, wl, idx_unused);
+      }
       const float sigma = exp32(f[0]);
       const float e = exp32(-(sigma * S.step));
       const float w = T * (1.0f - e);
@@ -266,6 +426,10 @@ __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, c
     } else {
 #pragma unroll
       for (int l = 0; l < LMAX; ++l) wl[l] = 0.0f;
+    }
+    if constexpr (MODEL == 1) {
+      baked_scatter<LMAX>(S, u, have, gf, gtab, gatlas);
+      continue;
     }
 #pragma unroll
     for (int l = 0; l < LMAX; ++l) {
@@ -348,8 +512,7 @@ __global__ void adam_kernel(int64_t n, float* __restrict__ p, const float* __res
 }
 
 int launch_backward(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const float* grad_rgb,
-                    const float* grad_dist,
-                    float* gtab, float* gmlp, hipStream_t st) {
+                    const float* grad_dist, float* gtab, float* gatlas, float* gmlp, hipStream_t st) {
   SceneArgs S = scene_args(ctx);
   const int64_t blocks = (n + 255) / 256;
   if (blocks > 0x7FFFFFFF) return fail(ctx, NGPRT_E_SHAPE, "too many rays for one launch");
@@ -368,18 +531,26 @@ int launch_backward(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, c
   float* partial = reinterpret_cast<float*>(ctx->ws);
   dim3 g = dim3(unsigned(blocks));
   const bool box = ctx->desc.domain == DOM_BOX;
-#define NGPRT_BW(DOMV, LM, PY)                                                                  \
-  hipLaunchKernelGGL((backward_kernel<DOMV, LM, PY>), g, dim3(256), 0, st, S, n, o, d, grad_rgb, grad_dist, \
-                     gtab, partial, ctx->mlp)
-  if (S.pyr_n > 0) {
-    if (box) NGPRT_BW(DOM_BOX, 16, true);
-    else NGPRT_BW(DOM_CONTRACT, 16, true);
+#define NGPRT_BW(DOMV, LM, PY, MD)                                                                 \
+  hipLaunchKernelGGL((backward_kernel<DOMV, LM, PY, MD>), g, dim3(256), 0, st, S, n, o, d, grad_rgb,   \
+                     grad_dist, gtab, gatlas, partial, ctx->mlp)
+  if (S.model == NGPRT_MODEL_BAKED) {
+    if (S.pyr_n > 0) {
+      if (box) NGPRT_BW(DOM_BOX, 4, true, 1);
+      else NGPRT_BW(DOM_CONTRACT, 4, true, 1);
+    } else {
+      if (box) NGPRT_BW(DOM_BOX, 4, false, 1);
+      else NGPRT_BW(DOM_CONTRACT, 4, false, 1);
+    }
+  } else if (S.pyr_n > 0) {
+    if (box) NGPRT_BW(DOM_BOX, 16, true, 0);
+    else NGPRT_BW(DOM_CONTRACT, 16, true, 0);
   } else if (S.L <= 8) {
-    if (box) NGPRT_BW(DOM_BOX, 8, false);
-    else NGPRT_BW(DOM_CONTRACT, 8, false);
+    if (box) NGPRT_BW(DOM_BOX, 8, false, 0);
+    else NGPRT_BW(DOM_CONTRACT, 8, false, 0);
   } else {
-    if (box) NGPRT_BW(DOM_BOX, 16, false);
-    else NGPRT_BW(DOM_CONTRACT, 16, false);
+    if (box) NGPRT_BW(DOM_BOX, 16, false, 0);
+    else NGPRT_BW(DOM_CONTRACT, 16, false, 0);
   }
 #undef NGPRT_BW
   int rc = check_launch(ctx, "backward_kernel");

@@ -112,6 +112,9 @@ class Renderer:
         if n_blocks:
             _dev(atlas, torch.float32, (n_blocks, 8, 8, 8, C), "atlas")
         dflt = (ctypes.c_float * C)(*[float(x) for x in default])
+        self.n_blocks = int(n_blocks)
+        self._coarse_index = block_index
+        self._coarse_default = [float(x) for x in default]
         check(self.lib.ngprt_load_coarse(self.ctx, n_blocks, _ptr(block_index),
                                          _ptr(atlas) if n_blocks else None, dflt, _stream()), self.ctx)
 
@@ -245,12 +248,32 @@ def _renderer_backward(self: Renderer, origins, dirs, grad_rgb, grad_tables, gra
           self.ctx)
 
 
+def _renderer_backward_baked(self: Renderer, origins, dirs, grad_rgb, grad_tables, grad_atlas, grad_mlp,
+                             grad_dist=None):
+    """Baked model: accumulate dL/d(fine tables) [L, T, 9] (channel 8 not
+    written), dL/d(atlas) [n_blocks, 8, 8, 8, 8 + 2L] and dL/dmlp [451]."""
+    n = origins.shape[0]
+    _dev(grad_rgb, torch.float32, (n, 3), "grad_rgb")
+    _dev(grad_tables, torch.float32, (self.L, self.T, 9), "grad_tables")
+    _dev(grad_mlp, torch.float32, (self.n_mlp,), "grad_mlp")
+    nblk = getattr(self, "n_blocks", 0)
+    if nblk:
+        _dev(grad_atlas, torch.float32, (nblk, 8, 8, 8, 8 + 2 * self.L), "grad_atlas")
+    if grad_dist is not None:
+        _dev(grad_dist, torch.float32, (n,), "grad_dist")
+    check(self.lib.ngprt_render_backward_baked(self.ctx, n, _ptr(origins), _ptr(dirs), _ptr(grad_rgb),
+                                               _ptr(grad_dist), _ptr(grad_tables),
+                                               _ptr(grad_atlas) if nblk else None, _ptr(grad_mlp), _stream()),
+          self.ctx)
+
+
 def _renderer_set_step(self: Renderer, step: float):
     check(self.lib.ngprt_set_step(self.ctx, float(step)), self.ctx)
     self.step = float(step)
 
 
 Renderer.backward = _renderer_backward
+Renderer.backward_baked = _renderer_backward_baked
 Renderer.set_step = _renderer_set_step
 
 
@@ -319,6 +342,54 @@ class RenderFunction(torch.autograd.Function):
         gdist = grad_dist.contiguous().float() if (ctx.with_dist and grad_dist is not None) else None
         r.backward(origins, dirs, grad_rgb.contiguous().float(), gt, gm, gdist)
         return gt, gm, None, None, None, None
+
+
+class BakedRenderFunction(torch.autograd.Function):
+    """rgb = render(fine tables, atlas, mlp; rays) for the baked feature
+    model, with the library's hand-written backward.  The block index grid
+    and the default vector are those of the renderer's last load_coarse;
+    forward re-loads the fine tables, the atlas and the MLP."""
+
+    @staticmethod
+    def forward(ctx, tables, atlas, mlp, origins, dirs, renderer, with_dist):
+        renderer.load_tables(tables.detach().contiguous())
+        renderer.load_coarse(renderer._coarse_index, atlas.detach().contiguous(), renderer._coarse_default)
+        renderer.load_mlp(mlp.detach().contiguous())
+        n = origins.shape[0]
+        out = {"rgb": torch.empty((n, 3), dtype=torch.float32, device=origins.device)}
+        if with_dist:
+            out["dist_loss"] = torch.empty((n,), dtype=torch.float32, device=origins.device)
+        renderer.render(origins, dirs, out=out)
+        ctx.renderer = renderer
+        ctx.with_dist = with_dist
+        ctx.atlas_shape = tuple(atlas.shape)
+        ctx.save_for_backward(origins, dirs)
+        if not with_dist:
+            dist = torch.zeros((n,), dtype=torch.float32, device=origins.device)
+            ctx.mark_non_differentiable(dist)
+            return out["rgb"], dist
+        return out["rgb"], out["dist_loss"]
+
+    @staticmethod
+    def backward(ctx, grad_rgb, grad_dist):
+        origins, dirs = ctx.saved_tensors
+        r = ctx.renderer
+        gt = torch.zeros((r.L, r.T, 9), dtype=torch.float32, device=origins.device)
+        ga = torch.zeros(ctx.atlas_shape, dtype=torch.float32, device=origins.device)
+        gm = torch.zeros((r.n_mlp,), dtype=torch.float32, device=origins.device)
+        if grad_rgb is None:
+            grad_rgb = torch.zeros((origins.shape[0], 3), dtype=torch.float32, device=origins.device)
+        gdist = grad_dist.contiguous().float() if (ctx.with_dist and grad_dist is not None) else None
+        r.backward_baked(origins, dirs, grad_rgb.contiguous().float(), gt, ga, gm, gdist)
+        return gt, ga, gm, None, None, None, None
+
+
+def render_differentiable_baked(renderer: Renderer, tables, atlas, mlp, origins, dirs, with_dist: bool = False):
+    """Baked model: rgb (and, with_dist, the distortion regulariser) as
+    differentiable functions of the fine tables, the coarse atlas and the
+    MLP (load_coarse must have set the block index grid first)."""
+    rgb, dist = BakedRenderFunction.apply(tables, atlas, mlp, origins, dirs, renderer, with_dist)
+    return (rgb, dist) if with_dist else rgb
 
 
 def render_differentiable(renderer: Renderer, tables, mlp, origins, dirs, with_dist: bool = False):

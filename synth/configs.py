@@ -196,6 +196,15 @@ def tiny_view(seed: int = 0, table_dtype: int = DTYPE_F32) -> SceneConfig:
     return cfg
 
 
+def baked_tiny_pyramid(seed: int = 0, table_dtype: int = DTYPE_F32) -> SceneConfig:
+    """baked_tiny marched through the occupancy pyramid 128^3 .. 32^3 (the
+    plain deferred MLP: a training configuration of the baked model)."""
+    cfg = baked_tiny(seed, table_dtype)
+    cfg.name = "baked_tiny_pyramid"
+    cfg.occ_levels, cfg.occ_fine_res = 3, 128
+    return cfg
+
+
 def paper_tiny(seed: int = 0, table_dtype: int = DTYPE_F32) -> SceneConfig:
     """All of the paper's rendering choices at the tiny scale: the baked
     feature model (L_C = 64, fine levels 128 and 256), the occupancy pyramid
@@ -219,4 +228,5 @@ def paper_hd(seed: int = 0, table_dtype: int = DTYPE_F32, n_fine: int = 2) -> Sc
 
 
 CONFIGS = {"paper_tiny": paper_tiny, "paper_hd": paper_hd, "tiny_view": tiny_view, "tiny": tiny, "hd": hd, "train_large": train_large, "baked_tiny": baked_tiny,
+           "baked_tiny_pyramid": baked_tiny_pyramid,
            "baked_hd": baked_hd, "tiny_pyramid": tiny_pyramid, "hd_pyramid": hd_pyramid}
