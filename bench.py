@@ -29,6 +29,9 @@ KERNEL_SOURCES = ["paper_2407_10482_amd/csrc/" + f for f in
                   ("render.hip", "device.h", "march.h", "internal.h")] + ["paper_2407_10482_amd/build.py"]
 BYTES_PER_ENTRY = {0: 36, 1: 18, 2: 9}     # 8 feature channels + 1 logit per entry
 DTYPE_NAME = {0: "f32", 1: "bf16", 2: "fp8"}
+AGG_NAME = {"separate_v": "sigmoid-gated separate attention (Separate-Att (V))",
+            "shared_v": "Shared-Att (V)", "separate_inv": "Separate-Att (Inv)",
+            "shared_inv": "Shared-Att (Inv)", "sum": "SUM aggregation"}
 
 
 def parse():
@@ -50,6 +53,10 @@ def parse():
                    help="hash: 16 hash levels fused by softmax attention (the headline); baked: "
                         "the paper's coarse grid + sigmoid-gated fine levels")
     p.add_argument("--fine-levels", type=int, default=2, help="baked model: fine levels (1..4)")
+    p.add_argument("--agg", choices=["separate_v", "shared_v", "separate_inv", "shared_inv", "sum"],
+                   default="separate_v",
+                   help="baked model: fusion of the fine levels (Table 3's variants; separate_v is the "
+                        "paper's sigmoid-gated separate attention)")
     p.add_argument("--occ", choices=["single", "pyramid"], default="single",
                    help="single: one 256^3 occupancy grid + distance grid (the headline); pyramid: "
                         "the paper's 512^3..32^3 occupancy pyramid + 256^3 distance grid")
@@ -380,7 +387,7 @@ def main():
     pyr = args.occ == "pyramid"
     if baked:
         from synth.baked import make_baked_scene
-        cfg = synth.baked_hd(table_dtype=dtype, n_fine=args.fine_levels)
+        cfg = synth.with_aggregation(synth.baked_hd(table_dtype=dtype, n_fine=args.fine_levels), args.agg)
         if pyr:
             cfg.occ_levels, cfg.occ_fine_res = 5, 512
         if args.mlp == "view":
@@ -463,7 +470,7 @@ def main():
         workload = (f"baked_hd: 8 views x 1920x1080 rays, coarse grid L_C=512 block-sparse "
                     f"({sc.n_blocks} of {sc.block_index.size} blocks of 8^3 vertices), {L} fine hash levels "
                     f"{cfg.resolutions[0]}..{cfg.resolutions[-1]}, 2^22 entries, {DTYPE_NAME[dtype]} fine "
-                    "tables, sigmoid-gated separate attention, contracted scene of 200 blobs, 256^3 "
+                    f"tables, {AGG_NAME[args.agg]}, contracted scene of 200 blobs, 256^3 "
                     "occupancy + distance grid, <=1024 samples/ray, T<1e-4")
     else:
         workload = ("hd: 8 views x 1920x1080 rays, 16 hash levels 16..4096, 2^19 entries, "

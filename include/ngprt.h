@@ -82,6 +82,24 @@ enum ngprt_feature_model {
   NGPRT_MODEL_BAKED = 1
 };
 
+/* How NGPRT_MODEL_BAKED fuses the fine levels (the aggregation variants the
+ * paper ablates in Sec. 5.2, Table 3).  g is the sigmoid; s_l = sigma^_l,
+ * c_l = [c^_l, v^_l]. */
+enum ngprt_aggregation {
+  /* Separate-Att (V), the paper's design (Eq. 7-8): omega_l, beta_l stored
+   * per coarse vertex; f^ = [sum g(omega_l) s_l, sum g(beta_l) c_l]. */
+  NGPRT_AGG_SEPARATE_V = 0,
+  /* Shared-Att (V): one a_l per coarse vertex gates both modalities. */
+  NGPRT_AGG_SHARED_V = 1,
+  /* Separate-Att (Inv): omega_l, beta_l are scene constants
+   * (desc.gate_params = [omega_1, beta_1, ..., omega_L, beta_L]). */
+  NGPRT_AGG_SEPARATE_INV = 2,
+  /* Shared-Att (Inv): a_l scene constants (desc.gate_params = [a_1..a_L]). */
+  NGPRT_AGG_SHARED_INV = 3,
+  /* SUM (MERF's aggregation): f^ = sum_l f^_l, no gates. */
+  NGPRT_AGG_SUM = 4
+};
+
 /* Scene descriptor (copied by ngprt_create). */
 typedef struct ngprt_desc {
   int32_t n_levels;                          /* L, 1..16 */
@@ -106,6 +124,11 @@ typedef struct ngprt_desc {
                             * occ_fine_res >> (occ_levels - 1) >= 32; occ_res must be one of
                             * the pyramid's resolutions (the distance grid's) */
   int32_t use_distance;    /* pyramid: 1 = consult the distance grid (Eq. 9), 0 = pyramid only */
+  int32_t aggregation;     /* NGPRT_MODEL_BAKED: enum ngprt_aggregation (0 for the hash model);
+                            * other than NGPRT_AGG_SEPARATE_V needs float32 tables and has no
+                            * backward */
+  float gate_params[8];    /* NGPRT_AGG_SEPARATE_INV / _SHARED_INV: the 2L / L attention
+                            * parameters before their sigmoid, finite; else ignored */
 } ngprt_desc;
 
 typedef struct ngprt_ctx ngprt_ctx;
@@ -159,6 +182,8 @@ int ngprt_load_tables(ngprt_ctx* ctx, const float* dev_tables, void* stream);
  *                   block), C = 8 + 2L channels [sigma~, r, g, b, s0..s3,
  *                   omega_1, beta_1, ..., omega_L, beta_L] (attention
  *                   parameters before their sigmoid); NULL if n_blocks = 0.
+ *                   NGPRT_AGG_SHARED_V: C = 8 + L, [f~, a_1..a_L];
+ *                   the constant-gate and SUM aggregations: C = 8, [f~].
  *  host_default     float32 [C]: the value of every vertex of an empty block.
  * The fine levels are loaded by ngprt_load_tables in the same [L][T][9]
  * layout as the hash model, channel 8 unused.  Synchronises the stream.

@@ -18,6 +18,12 @@ Interpolation uses the hash levels' cell convention: p = u L_C,
 i0 = clamp(floor(p), 0, L_C - 1), corners i0 + {0, 1}^3, f = u L_C - i0
 rounded once.
 
+Aggregation variants (Sec. 5.2, Table 3): Separate-Att (V) is the design
+above; Shared-Att (V) stores one a_l per vertex and gates density and
+colour with g(a_l); the (Inv) variants take omega_l, beta_l (or a_l) as
+scene constants instead of interpolated values; SUM drops the gates
+(f^ = sum_l f^_l).  The coarse grid then holds 8 + L or 8 channels.
+
 Float32 decision chain (bit-exact with the GPU): coarse channels
 acc = acc + w_c v_c (c = 0..7, plain float32 operations); fine level l as
 the hash levels (density channel acc = acc + w_c v_c; FP8 then times the
@@ -96,6 +102,28 @@ def sigmoid32(a: np.ndarray) -> np.ndarray:
     return (F32(1.0) / (F32(1.0) + exp32(-a))).astype(F32)
 
 
+SEPARATE_V, SHARED_V, SEPARATE_INV, SHARED_INV, SUM = 0, 1, 2, 3, 4
+
+
+def gate_params(inp, co: np.ndarray, l: int):
+    """Attention parameters (omega_l, beta_l) of fine level l per point, before
+    the sigmoid, under the scene's aggregation; None for SUM (gates 1)."""
+    agg = getattr(inp, "aggregation", SEPARATE_V)
+    m = co.shape[0]
+    if agg == SEPARATE_V:
+        return co[:, 8 + 2 * l], co[:, 9 + 2 * l]
+    if agg == SHARED_V:
+        return co[:, 8 + l], co[:, 8 + l]
+    p = np.asarray(inp.gate_params, dtype=co.dtype)
+    if agg == SEPARATE_INV:
+        return np.full(m, p[2 * l], co.dtype), np.full(m, p[2 * l + 1], co.dtype)
+    if agg == SHARED_INV:
+        return np.full(m, p[l], co.dtype), np.full(m, p[l], co.dtype)
+    if agg == SUM:
+        return None
+    raise ValueError("unknown aggregation")
+
+
 def fused32(inp, u: np.ndarray):
     """Float32 decision chain: fused channels [m, 8] (channel 0 bit-exact,
     colour channels to rounding), density gates g_omega [m, L], fine corner
@@ -113,8 +141,11 @@ def fused32(inp, u: np.ndarray):
             acc = acc + w[:, c:c + 1] * g[:, c, :8]
         if inp.scales is not None:
             acc = inp.scales[l][None, :8] * acc
-        gw = sigmoid32(co[:, 8 + 2 * l])
-        gb = sigmoid32(co[:, 9 + 2 * l])
+        a = gate_params(inp, co, l)
+        if a is None:
+            gw = gb = np.ones(m, dtype=F32)
+        else:
+            gw, gb = sigmoid32(a[0]), sigmoid32(a[1])
         fused[:, 0] = fused[:, 0] + gw * acc[:, 0]
         fused[:, 1:] = fused[:, 1:] + gb[:, None] * acc[:, 1:]
         gws.append(gw)
@@ -133,8 +164,11 @@ def fused64(inp, u: np.ndarray):
         v = np.zeros((m, 8))
         for c in range(8):
             v += w[:, c:c + 1] * inp.val64[l][idx[:, c], :8]
-        gw = 1.0 / (1.0 + np.exp(-co[:, 8 + 2 * l]))
-        gb = 1.0 / (1.0 + np.exp(-co[:, 9 + 2 * l]))
+        a = gate_params(inp, co, l)
+        if a is None:
+            gw = gb = np.ones(m)
+        else:
+            gw, gb = 1.0 / (1.0 + np.exp(-a[0])), 1.0 / (1.0 + np.exp(-a[1]))
         fused[:, 0] += gw * v[:, 0]
         fused[:, 1:] += gb[:, None] * v[:, 1:]
         gws.append(gw)

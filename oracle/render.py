@@ -74,6 +74,9 @@ class OracleInputs:
     block_index: Optional[np.ndarray] = None   # int32 [nb, nb, nb]
     atlas: Optional[np.ndarray] = None         # float32 [n_blocks, 8, 8, 8, C]
     coarse_default: Optional[np.ndarray] = None  # float32 [C]
+    # fusion of the fine levels (Table 3's variants; 0 = Separate-Att (V))
+    aggregation: int = 0
+    gate_params: tuple = ()                      # constant gates of the Inv variants
     # multi-level occupancy (Eq. 9's s_O branch): uint8 grids [O_0 (finest), O_1, ...];
     # occ / dist are then the pyramid level of the distance grid's resolution and its G
     pyramid: Optional[list] = None
@@ -125,7 +128,7 @@ class OracleInputs:
 
     @property
     def coarse_channels(self):
-        return 8 + 2 * self.L
+        return 8 + {0: 2 * self.L, 1: self.L}.get(self.aggregation, 0)
 
 
 # --------------------------------------------------------------------------
@@ -524,7 +527,8 @@ def inputs_from_scene(scene, dist: np.ndarray, dtype: int = DT_F32) -> OracleInp
         extra.update(pyramid=pyramid.build_pyramid(scene.occ_fine, cfg.occ_levels))
     if getattr(scene, "block_index", None) is not None:
         extra.update(coarse_res=cfg.coarse_res, block_index=scene.block_index, atlas=scene.atlas,
-                     coarse_default=scene.default)
+                     coarse_default=scene.default, aggregation=getattr(cfg, "aggregation", 0),
+                     gate_params=tuple(np.asarray(getattr(cfg, "gate_params", ()), F32)))
     return OracleInputs(tables=scene.tables, occ=scene.occ, dist=dist, mlp=scene.mlp,
                         resolutions=list(cfg.resolutions), domain=cfg.domain,
                         roi_half=cfg.roi_half, step=cfg.step, max_samples=cfg.max_samples,

@@ -16,6 +16,7 @@ STATUS = {0: "NGPRT_OK", -1: "NGPRT_E_INVALID_ARG", -2: "NGPRT_E_SHAPE", -3: "NG
 F32, BF16, FP8E4M3 = 0, 1, 2
 ROI_BOX, ROI_CONTRACT = 0, 1
 MODEL_HASH, MODEL_BAKED = 0, 1
+AGG_SEPARATE_V, AGG_SHARED_V, AGG_SEPARATE_INV, AGG_SHARED_INV, AGG_SUM = 0, 1, 2, 3, 4
 
 
 class NgprtDesc(ctypes.Structure):
@@ -38,6 +39,8 @@ class NgprtDesc(ctypes.Structure):
         ("occ_levels", ctypes.c_int32),
         ("occ_fine_res", ctypes.c_int32),
         ("use_distance", ctypes.c_int32),
+        ("aggregation", ctypes.c_int32),
+        ("gate_params", ctypes.c_float * 8),
     ]
 
 
@@ -125,7 +128,8 @@ def check(code: int, ctx=None):
 
 def make_desc(resolutions, log2_table_size, table_dtype, domain, roi_half, occ_res, step,
               max_samples, t_threshold, mlp=(7, 16, 3), feature_model=MODEL_HASH,
-              coarse_res=0, occ_levels=0, occ_fine_res=0, use_distance=1) -> NgprtDesc:
+              coarse_res=0, occ_levels=0, occ_fine_res=0, use_distance=1, aggregation=AGG_SEPARATE_V,
+              gate_params=()) -> NgprtDesc:
     d = NgprtDesc()
     d.n_levels = len(resolutions)
     for i, r in enumerate(resolutions[:MAX_LEVELS]):
@@ -144,4 +148,12 @@ def make_desc(resolutions, log2_table_size, table_dtype, domain, roi_half, occ_r
     d.occ_levels = int(occ_levels)
     d.occ_fine_res = int(occ_fine_res)
     d.use_distance = int(use_distance)
+    d.aggregation = int(aggregation)
+    for i, g in enumerate(list(gate_params)[:8]):
+        d.gate_params[i] = float(g)
     return d
+
+
+def coarse_channels(n_levels: int, aggregation: int = AGG_SEPARATE_V) -> int:
+    """Channels per coarse vertex of the baked model under an aggregation."""
+    return 8 + {AGG_SEPARATE_V: 2 * n_levels, AGG_SHARED_V: n_levels}.get(aggregation, 0)

@@ -62,10 +62,30 @@ SceneArgs scene_args(const ngprt_ctx* ctx) {
     S.LC = d.coarse_res;
     S.LCf = float(d.coarse_res);
     S.nb = (d.coarse_res + 1 + 7) / 8;
-    S.Cpad = coarse_row_floats(d.n_levels);
+    S.Cpad = coarse_row_floats(coarse_channels(d));
     S.cidx = ctx->cidx;
     S.catlas = ctx->catlas;
     for (int j = 0; j < 16; ++j) S.cdef[j] = ctx->cdef[j];
+    S.gen = d.aggregation != NGPRT_AGG_SEPARATE_V ? 1 : 0;
+    for (int l = 0; l < 4; ++l) {
+      int iw = 8 + 2 * l, ib = 9 + 2 * l;      // Separate-Att (V)
+      float cw = 0.0f, cb = 0.0f;
+      switch (d.aggregation) {
+        case NGPRT_AGG_SHARED_V: iw = ib = 8 + l; break;
+        case NGPRT_AGG_SEPARATE_INV:
+          iw = ib = -1;
+          cw = d.gate_params[2 * l];
+          cb = d.gate_params[2 * l + 1];
+          break;
+        case NGPRT_AGG_SHARED_INV: iw = ib = -1; cw = cb = d.gate_params[l]; break;
+        case NGPRT_AGG_SUM: iw = ib = -1; cw = cb = INFINITY; break;
+        default: break;
+      }
+      S.gidx[l][0] = iw;
+      S.gidx[l][1] = ib;
+      S.gconst[l][0] = cw;
+      S.gconst[l][1] = cb;
+    }
   }
   return S;
 }
@@ -128,6 +148,14 @@ int ngprt_validate_desc(const ngprt_desc* d) {
   if (d->feature_model == NGPRT_MODEL_BAKED) {
     if (d->n_levels > 4) return NGPRT_E_SHAPE;
     if (d->coarse_res < 1 || d->coarse_res > 2048) return NGPRT_E_SHAPE;
+    if (d->aggregation < NGPRT_AGG_SEPARATE_V || d->aggregation > NGPRT_AGG_SUM) return NGPRT_E_INVALID_ARG;
+    if (d->aggregation != NGPRT_AGG_SEPARATE_V && d->table_dtype != NGPRT_F32) return NGPRT_E_UNSUPPORTED;
+    const int n_const = d->aggregation == NGPRT_AGG_SEPARATE_INV ? 2 * d->n_levels
+                        : d->aggregation == NGPRT_AGG_SHARED_INV ? d->n_levels : 0;
+    for (int j = 0; j < n_const; ++j)
+      if (!std::isfinite(d->gate_params[j])) return NGPRT_E_INVALID_ARG;
+  } else if (d->aggregation != NGPRT_AGG_SEPARATE_V) {
+    return NGPRT_E_INVALID_ARG;
   }
   if (d->occ_levels != 0) {
     const int F = d->occ_fine_res;
@@ -232,7 +260,7 @@ int ngprt_load_coarse(ngprt_ctx* ctx, int64_t n_blocks, const int32_t* dev_block
   for (int64_t i = 0; i < n_idx; ++i)
     if (idx[size_t(i)] < -1 || idx[size_t(i)] >= n_blocks)
       return fail(ctx, NGPRT_E_INVALID_ARG, "block index entry outside [-1, n_blocks)");
-  const int C = 8 + 2 * d.n_levels, Cpad = coarse_row_floats(d.n_levels);
+  const int C = coarse_channels(d), Cpad = coarse_row_floats(C);
   ctx->coarse_loaded = false;
   // same block count as the loaded grid (a training step's update): keep the
   // allocations; the index grid's size is fixed by the descriptor
@@ -431,6 +459,8 @@ int ngprt_render_backward_baked(ngprt_ctx* ctx, int64_t n_rays, const float* dev
     return fail(ctx, NGPRT_E_DTYPE, "backward needs float32 tables");
   if (ctx->desc.feature_model != NGPRT_MODEL_BAKED)
     return fail(ctx, NGPRT_E_UNSUPPORTED, "ngprt_render_backward_baked needs the baked feature model");
+  if (ctx->desc.aggregation != NGPRT_AGG_SEPARATE_V)
+    return fail(ctx, NGPRT_E_UNSUPPORTED, "the baked backward supports Separate-Att (V) only");
   if (is_view_mlp(&ctx->desc))
     return fail(ctx, NGPRT_E_UNSUPPORTED, "backward supports the 7-16-16-3 deferred MLP only");
   int rc = check_ready(ctx);

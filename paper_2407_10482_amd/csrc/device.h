@@ -250,7 +250,12 @@ __device__ __forceinline__ void eval_fused(const SceneArgs& S, const float u[3],
 // f_0 = f~_0, then f_0 = f_0 + g_omega_l * sigma^_l in level order.
 __device__ __forceinline__ float sigmoid32(float a) { return 1.0f / (1.0f + exp32(-a)); }
 
-template <int DT, int LMAX, bool DEBUG = false>
+//
+// GEN: the aggregation variants of the ablation (Shared-Att, spatially
+// invariant parameters, SUM): level l's two gate parameters are coarse
+// channel S.gidx[l][m] or, where that is -1, the constant S.gconst[l][m];
+// rows may then be 8 floats.
+template <int DT, int LMAX, bool DEBUG = false, bool GEN = false>
 __device__ __forceinline__ void eval_baked(const SceneArgs& S, const float u[3], float fused[8],
                                            float* wout = nullptr, int32_t* idxout = nullptr) {
   static_assert(LMAX <= 4, "the coarse row holds at most 16 channels");
@@ -285,7 +290,8 @@ __device__ __forceinline__ void eval_baked(const SceneArgs& S, const float u[3],
     if (bid >= 0) {
       const float4* row = reinterpret_cast<const float4*>(
           S.catlas + (size_t(bid) * 512 + size_t(((vz & 7) * 8 + (vy & 7)) * 8 + (vx & 7))) * S.Cpad);
-      float4 q0 = row[0], q1 = row[1], q2 = row[2];
+      float4 q0 = row[0], q1 = row[1];
+      float4 q2 = (!GEN || S.Cpad > 8) ? row[2] : make_float4(0.f, 0.f, 0.f, 0.f);
       float4 q3 = wide ? row[3] : make_float4(0.f, 0.f, 0.f, 0.f);
       v[0] = q0.x; v[1] = q0.y; v[2] = q0.z; v[3] = q0.w;
       v[4] = q1.x; v[5] = q1.y; v[6] = q1.z; v[7] = q1.w;
@@ -330,11 +336,24 @@ __device__ __forceinline__ void eval_baked(const SceneArgs& S, const float u[3],
 #pragma unroll
         for (int j = 0; j < 8; ++j) acc[j] = S.scale[l][j] * acc[j];
       }
-      float aw = co[8], ab = co[9];
+      float aw, ab;
+      if constexpr (GEN) {
+        const int iw = S.gidx[l][0], ib = S.gidx[l][1];
+        aw = S.gconst[l][0];
+        ab = S.gconst[l][1];
 #pragma unroll
-      for (int q = 1; q < LMAX; ++q) {
-        aw = l == q ? co[8 + 2 * q] : aw;
-        ab = l == q ? co[9 + 2 * q] : ab;
+        for (int j = 8; j < CMAX; ++j) {
+          aw = iw == j ? co[j] : aw;
+          ab = ib == j ? co[j] : ab;
+        }
+      } else {
+        aw = co[8];
+        ab = co[9];
+#pragma unroll
+        for (int q = 1; q < LMAX; ++q) {
+          aw = l == q ? co[8 + 2 * q] : aw;
+          ab = l == q ? co[9 + 2 * q] : ab;
+        }
       }
       const float gw = sigmoid32(aw);
       const float gb = sigmoid32(ab);
@@ -358,11 +377,12 @@ __device__ __forceinline__ void eval_baked(const SceneArgs& S, const float u[3],
 }
 
 // One sample's fused deferred feature under the scene's feature model.
+// MODEL: bit 0 = baked, bit 2 = its ablation aggregations (GEN).
 template <int MODEL, int DT, int LMAX, bool DEBUG = false>
 __device__ __forceinline__ void eval_sample(const SceneArgs& S, const float u[3], float fused[8],
                                             float* wout = nullptr, int32_t* idxout = nullptr) {
-  if constexpr (MODEL == 1)
-    eval_baked<DT, LMAX, DEBUG>(S, u, fused, wout, idxout);
+  if constexpr ((MODEL & 1) != 0)
+    eval_baked<DT, LMAX, DEBUG, (MODEL & 4) != 0>(S, u, fused, wout, idxout);
   else
     eval_fused<DT, LMAX, DEBUG>(S, u, fused, wout, idxout);
 }

@@ -20,9 +20,16 @@ constexpr int kMlpViewRec = 8960;        // its weights arranged for the MFMA se
 constexpr int kMaxLattice = 1 << 16;   // hard bound on lattice points per ray
 constexpr int kMaxPyr = 5;             // occupancy pyramid levels
 
-// floats per coarse atlas row of the baked model: 8 + 2L channels rounded up
-// to whole float4 loads (12 for L <= 2, 16 for L = 3, 4)
-inline int coarse_row_floats(int L) { return (8 + 2 * L + 3) / 4 * 4; }
+// channels per coarse vertex of the baked model: f~ (8) and the attention
+// parameters stored per vertex (2L separate, L shared, none for constant
+// gates or SUM)
+inline int coarse_channels(const ngprt_desc& d) {
+  return 8 + (d.aggregation == NGPRT_AGG_SEPARATE_V ? 2 * d.n_levels
+              : d.aggregation == NGPRT_AGG_SHARED_V ? d.n_levels : 0);
+}
+// floats per coarse atlas row: C channels rounded up to whole float4 loads
+// (8, 12 or 16)
+inline int coarse_row_floats(int C) { return (C + 3) / 4 * 4; }
 
 // Scene constants passed by value to kernels (lands in scalar registers).
 struct SceneArgs {
@@ -54,6 +61,13 @@ struct SceneArgs {
   const int32_t* cidx;            // [nb^3] atlas row of each block or -1
   const float* catlas;            // [n_blocks][512][Cpad]
   float cdef[16];                 // value of every vertex of an empty block
+  // aggregation other than Separate-Att (V) (gen = 1): fine level l's gate
+  // parameters are coarse channel gidx[l][0 / 1] (density / colour), or
+  // the constant gconst[l][0 / 1] where that index is -1 (SUM: +inf, so
+  // the sigmoid is exactly 1)
+  int gen;
+  int gidx[4][2];
+  float gconst[4][2];
   // multi-level occupancy (pyr_n > 0): bit grids, level j of resolution pyrR[j]
   int pyr_n;
   int use_dist;                   // consult the distance grid (Eq. 9) when the exiting level is coarser

@@ -112,7 +112,8 @@ __device__ __forceinline__ void wave_mlp(const float* __restrict__ P, const floa
 #define NGPRT_XCD_CHUNK 0
 #endif
 
-// MODEL: bit 0 = baked feature model, bit 1 = occupancy pyramid march
+// MODEL: bit 0 = baked feature model, bit 1 = occupancy pyramid march,
+// bit 2 = the baked model's ablation aggregations
 template <int DOM, int DT, int LMAX, int MODE, int MODEL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NGPRT_RENDER_WAVES_PER_EU)))
 render_kernel(SceneArgs S, int64_t n, const float* __restrict__ O,
@@ -176,7 +177,7 @@ render_kernel(SceneArgs S, int64_t n, const float* __restrict__ O,
     if (__ballot(have) == 0) break;
     if (have) {
       float f[8];
-      eval_sample<MODEL & 1, DT, LMAX>(S, u, f);
+      eval_sample<MODEL & 5, DT, LMAX>(S, u, f);
       const float sigma = exp32(f[0]);
       const float e = exp32(-(sigma * S.step));
       const float alpha = 1.0f - e;
@@ -270,7 +271,17 @@ template <int MODE, int DOM, int DT>
 static void dispatch_l(const SceneArgs& S, dim3 g, hipStream_t st, int64_t n, const float* o,
                        const float* d, const RayOut& out, const MarchRecord& rec,
                        const float* mlp, int naive, const ProposalArgs& pa) {
-  if (S.model == 1 && S.pyr_n > 0)
+  if (S.model == 1 && S.gen) {
+    // the ablation aggregations: float32 tables only (checked at create)
+    if constexpr (DT == DT_F32) {
+      if (S.pyr_n > 0)
+        hipLaunchKernelGGL((render_kernel<DOM, DT, 4, MODE, 7>), g, dim3(256), 0, st, S, n, o, d, out, rec,
+                           mlp, naive, pa);
+      else
+        hipLaunchKernelGGL((render_kernel<DOM, DT, 4, MODE, 5>), g, dim3(256), 0, st, S, n, o, d, out, rec,
+                           mlp, naive, pa);
+    }
+  } else if (S.model == 1 && S.pyr_n > 0)
     hipLaunchKernelGGL((render_kernel<DOM, DT, 4, MODE, 3>), g, dim3(256), 0, st, S, n, o, d, out, rec,
                        mlp, naive, pa);
   else if (S.model == 1)
@@ -353,7 +364,11 @@ int launch_eval_points(ngprt_ctx* ctx, int64_t n, const float* pos, int32_t* idx
     else if (S.L <= 8) NGPRT_EV(DTV, 8, 0); \
     else NGPRT_EV(DTV, 16, 0);              \
   }
-  NGPRT_EV_DT(DT_F32)
+  if (S.model == 1 && S.gen)   // the ablation aggregations: float32 tables only (checked at create)
+    NGPRT_EV(DT_F32, 4, 5);
+  else {
+    NGPRT_EV_DT(DT_F32)
+  }
   NGPRT_EV_DT(DT_BF16)
   NGPRT_EV_DT(DT_FP8)
 #undef NGPRT_EV_DT

@@ -247,7 +247,7 @@ __global__ void pack_atlas_kernel(const float* __restrict__ src, float* __restri
 }
 
 int launch_pack_atlas(ngprt_ctx* ctx, const float* atlas, int64_t n_blocks, hipStream_t st) {
-  const int C = 8 + 2 * ctx->desc.n_levels, Cpad = coarse_row_floats(ctx->desc.n_levels);
+  const int C = coarse_channels(ctx->desc), Cpad = coarse_row_floats(C);
   const int64_t total = n_blocks * 512 * Cpad;
   const int64_t blocks = (total + 255) / 256;
   if (blocks > 0x7FFFFFFF) return fail(ctx, NGPRT_E_SHAPE, "atlas too large");

@@ -39,7 +39,8 @@ class Renderer:
                  domain: int = ROI_BOX, roi_half: float = 1.0, occ_res: int = 64,
                  step: float = 1.0 / 256.0, max_samples: int = 1024, t_threshold: float = 1e-4,
                  feature_model: int = MODEL_HASH, coarse_res: int = 0, occ_levels: int = 0,
-                 occ_fine_res: int = 0, use_distance: bool = True, mlp_dims=(7, 16, 16, 3)):
+                 occ_fine_res: int = 0, use_distance: bool = True, mlp_dims=(7, 16, 16, 3),
+                 aggregation: int = _lib.AGG_SEPARATE_V, gate_params=()):
         self.lib = load_library()
         self.resolutions = list(resolutions)
         self.L = len(self.resolutions)
@@ -49,6 +50,7 @@ class Renderer:
         self.feature_model = feature_model
         self.coarse_res = coarse_res
         self.occ_fine_res = occ_fine_res
+        self.aggregation = int(aggregation)
         self.mlp_dims = tuple(mlp_dims)
         self.view_mlp = self.mlp_dims[1] == 64
         i, h, _, o = self.mlp_dims
@@ -58,7 +60,8 @@ class Renderer:
                                    feature_model=feature_model, coarse_res=coarse_res,
                                    occ_levels=occ_levels, occ_fine_res=occ_fine_res,
                                    use_distance=int(bool(use_distance)),
-                                   mlp=(self.mlp_dims[0], self.mlp_dims[1], self.mlp_dims[3]))
+                                   mlp=(self.mlp_dims[0], self.mlp_dims[1], self.mlp_dims[3]),
+                                   aggregation=aggregation, gate_params=gate_params)
         ctx = ctypes.c_void_p()
         check(self.lib.ngprt_create(ctypes.byref(self.desc), ctypes.byref(ctx)))
         self.ctx = ctx
@@ -69,7 +72,8 @@ class Renderer:
                    cfg.domain, cfg.roi_half, cfg.occ_res, cfg.step, cfg.max_samples, cfg.t_threshold,
                    getattr(cfg, "model", MODEL_HASH), getattr(cfg, "coarse_res", 0),
                    getattr(cfg, "occ_levels", 0), getattr(cfg, "occ_fine_res", 0), use_distance,
-                   tuple(cfg.mlp_dims))
+                   tuple(cfg.mlp_dims), getattr(cfg, "aggregation", _lib.AGG_SEPARATE_V),
+                   tuple(getattr(cfg, "gate_params", ())))
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -104,9 +108,10 @@ class Renderer:
 
     def load_coarse(self, block_index: torch.Tensor, atlas: torch.Tensor, default):
         """Baked model: block index grid int32 [nb]^3, atlas float32
-        [n_blocks, 8, 8, 8, C], default vector (C floats, host)."""
+        [n_blocks, 8, 8, 8, C], default vector (C floats, host); C = 8 + 2L
+        (8 + L for Shared-Att (V), 8 for constant gates and SUM)."""
         nb = (self.coarse_res + 1 + 7) // 8
-        C = 8 + 2 * self.L
+        C = _lib.coarse_channels(self.L, self.aggregation)
         _dev(block_index, torch.int32, (nb, nb, nb), "block_index")
         n_blocks = atlas.shape[0]
         if n_blocks:

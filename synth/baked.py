@@ -124,7 +124,9 @@ def make_baked_scene(cfg: SceneConfig, seed=None) -> BakedScene:
     n_blocks = len(blocks)
     index = np.full((nb, nb, nb), -1, dtype=np.int32)
     index[blocks[:, 0], blocks[:, 1], blocks[:, 2]] = np.arange(n_blocks, dtype=np.int32)
-    C = cfg.coarse_channels
+    # every aggregation draws the same values (8 + 2L channels) and keeps its
+    # own channels, so the variants share f~ and the fine tables
+    C = 8 + 2 * cfg.n_levels
     rng_val = np.random.default_rng(2_000_003 + (cfg.seed if seed is None else seed))
     atlas = np.empty((n_blocks, BLOCK, BLOCK, BLOCK, C), dtype=np.float32)
     atlas[..., 0] = np.log(cfg.density_scale * rho + 1e-4)
@@ -139,5 +141,13 @@ def make_baked_scene(cfg: SceneConfig, seed=None) -> BakedScene:
     tables[:, :, 1:4] = rng_val.normal(0.0, 0.2, size=(L, T, 3))
     tables[:, :, 4:8] = rng_val.normal(0.0, 0.5, size=(L, T, 4))
     mlp = make_mlp(cfg, rng_val)
+    keep_ch = list(range(8))
+    if cfg.aggregation == 0:
+        keep_ch += list(range(8, C))
+    elif cfg.aggregation == 1:                           # Shared-Att (V): a_l = the omega_l draw
+        keep_ch += [8 + 2 * l for l in range(cfg.n_levels)]
+    if len(keep_ch) != C:
+        atlas = np.ascontiguousarray(atlas[..., keep_ch])
+        default = np.ascontiguousarray(default[keep_ch])
     return BakedScene(cfg=cfg, tables=tables, occ=occ, mlp=mlp, block_index=index, atlas=atlas,
                       default=default, blob_mu=mu, blob_sigma=sig, occ_fine=occ_fine)

@@ -29,6 +29,7 @@ end points are exact; the integer list is handed to the renderer explicitly.
 """
 from __future__ import annotations
 
+import dataclasses
 import math
 from dataclasses import dataclass, field
 from typing import List, Tuple
@@ -84,6 +85,8 @@ class SceneConfig:
     coarse_res: int = 0        # L_C of the baked model (vertex lattice L_C + 1 per axis)
     occ_levels: int = 0        # > 0: occupancy pyramid of this many levels, finest occ_fine_res
     occ_fine_res: int = 0
+    aggregation: int = 0       # baked model: fusion of the fine levels (0 = Separate-Att (V))
+    gate_params: Tuple[float, ...] = ()   # constant gates of the (Inv) aggregations
 
     def __post_init__(self):
         if not self.resolutions:
@@ -91,8 +94,9 @@ class SceneConfig:
 
     @property
     def coarse_channels(self) -> int:
-        """8 feature channels + (omega, beta) per fine level."""
-        return 8 + 2 * self.n_levels
+        """8 feature channels + (omega, beta) per fine level (one a per
+        level for Shared-Att (V); none for constant gates and SUM)."""
+        return 8 + {0: 2 * self.n_levels, 1: self.n_levels}.get(self.aggregation, 0)
 
     @property
     def table_size(self) -> int:
@@ -196,6 +200,23 @@ def tiny_view(seed: int = 0, table_dtype: int = DTYPE_F32) -> SceneConfig:
     return cfg
 
 
+AGGREGATIONS = {"separate_v": 0, "shared_v": 1, "separate_inv": 2, "shared_inv": 3, "sum": 4}
+# constant attention parameters of the (Inv) variants (fixed, spread over the
+# sigmoid's useful range)
+_GATE_CONSTANTS = (0.6, -0.4, -0.9, 1.3, 0.2, 0.8, -1.2, 0.5)
+
+
+def with_aggregation(cfg: SceneConfig, name: str) -> SceneConfig:
+    """The same scene fused by another of Table 3's aggregations."""
+    agg = AGGREGATIONS[name]
+    cfg = dataclasses.replace(cfg, aggregation=agg)
+    L = cfg.n_levels
+    cfg.gate_params = {2: _GATE_CONSTANTS[:2 * L], 3: _GATE_CONSTANTS[:L]}.get(agg, ())
+    if agg:
+        cfg.name = f"{cfg.name}_{name}"
+    return cfg
+
+
 def baked_tiny_pyramid(seed: int = 0, table_dtype: int = DTYPE_F32) -> SceneConfig:
     """baked_tiny marched through the occupancy pyramid 128^3 .. 32^3 (the
     plain deferred MLP: a training configuration of the baked model)."""
@@ -229,4 +250,10 @@ def paper_hd(seed: int = 0, table_dtype: int = DTYPE_F32, n_fine: int = 2) -> Sc
 
 CONFIGS = {"paper_tiny": paper_tiny, "paper_hd": paper_hd, "tiny_view": tiny_view, "tiny": tiny, "hd": hd, "train_large": train_large, "baked_tiny": baked_tiny,
            "baked_tiny_pyramid": baked_tiny_pyramid,
+           "baked_tiny_shared_v": lambda **k: with_aggregation(baked_tiny(**k), "shared_v"),
+           "baked_tiny_separate_inv": lambda **k: with_aggregation(baked_tiny(**k), "separate_inv"),
+           "baked_tiny_shared_inv": lambda **k: with_aggregation(baked_tiny(**k), "shared_inv"),
+           "baked_tiny_sum": lambda **k: with_aggregation(baked_tiny(**k), "sum"),
+           "baked_tiny_pyramid_shared_inv":
+               lambda **k: with_aggregation(baked_tiny_pyramid(**k), "shared_inv"),
            "baked_hd": baked_hd, "tiny_pyramid": tiny_pyramid, "hd_pyramid": hd_pyramid}

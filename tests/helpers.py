@@ -34,7 +34,8 @@ def gpu_renderer(name: str, dtype: int = 0, **overrides):
               domain=cfg.domain, roi_half=cfg.roi_half, occ_res=cfg.occ_res, step=cfg.step,
               max_samples=cfg.max_samples, t_threshold=cfg.t_threshold,
               feature_model=cfg.model, coarse_res=cfg.coarse_res, occ_levels=cfg.occ_levels,
-              occ_fine_res=cfg.occ_fine_res, mlp_dims=tuple(cfg.mlp_dims))
+              occ_fine_res=cfg.occ_fine_res, mlp_dims=tuple(cfg.mlp_dims),
+              aggregation=cfg.aggregation, gate_params=tuple(cfg.gate_params))
     kw.update(overrides)
     r = Renderer(**kw)
     r.load_tables(torch.from_numpy(sc.tables).cuda())

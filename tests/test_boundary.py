@@ -79,6 +79,36 @@ def test_validate_desc_baked_model(lib):
     assert lib.ngprt_validate_desc(ctypes.byref(d)) == -2
 
 
+def test_validate_desc_aggregation(lib):
+    """Table 3's aggregations: baked model only, float32 tables, finite
+    constant gates for the (Inv) variants."""
+    cfg = synth.baked_hd(n_fine=4)
+
+    def desc(agg, dtype=0, params=()):
+        return _lib.make_desc(cfg.resolutions, cfg.log2_table, dtype, cfg.domain, cfg.roi_half,
+                              cfg.occ_res, cfg.step, cfg.max_samples, cfg.t_threshold,
+                              feature_model=_lib.MODEL_BAKED, coarse_res=cfg.coarse_res,
+                              aggregation=agg, gate_params=params)
+    for agg in range(5):
+        assert lib.ngprt_validate_desc(ctypes.byref(desc(agg, params=[0.5] * 8))) == 0
+    assert lib.ngprt_validate_desc(ctypes.byref(desc(5))) == -1
+    assert lib.ngprt_validate_desc(ctypes.byref(desc(-1))) == -1
+    assert lib.ngprt_validate_desc(ctypes.byref(desc(0, dtype=1))) == 0
+    for agg in range(1, 5):
+        assert lib.ngprt_validate_desc(ctypes.byref(desc(agg, dtype=1, params=[0.5] * 8))) == -7
+    bad = [0.5] * 8
+    bad[7] = float("nan")                 # Separate-Att (Inv) at L = 4 reads all 8
+    assert lib.ngprt_validate_desc(ctypes.byref(desc(2, params=bad))) == -1
+    assert lib.ngprt_validate_desc(ctypes.byref(desc(3, params=bad))) == 0    # reads 4
+    bad[3] = float("inf")
+    assert lib.ngprt_validate_desc(ctypes.byref(desc(3, params=bad))) == -1
+    d = _good_desc()                      # hash model: aggregation must stay 0
+    d.aggregation = 4
+    assert lib.ngprt_validate_desc(ctypes.byref(d)) == -1
+    assert _lib.coarse_channels(4, 0) == 16 and _lib.coarse_channels(4, 1) == 12
+    assert all(_lib.coarse_channels(4, a) == 8 for a in (2, 3, 4))
+
+
 def test_validate_desc_accepts_workloads(lib):
     assert lib.ngprt_validate_desc(ctypes.byref(_good_desc())) == 0
     cfg = synth.hd()

@@ -128,6 +128,80 @@ def test_separate_attention_closed_forms(omega, beta):
         np.testing.assert_allclose(fused, coarse, atol=1e-12)
 
 
+def _fine_by_hand(inp, u):
+    """Per-level trilinear values [L, m, 8] of the fine tables, written out
+    from the hash definition (x * 1 ^ y * 2654435761 ^ z * 805459861 mod T)."""
+    out = []
+    for l, N in enumerate(inp.resolutions):
+        p = u * N
+        i0 = np.clip(np.floor(p), 0, N - 1).astype(np.int64)
+        f = p - i0
+        v = np.zeros((len(u), 8))
+        for c in range(8):
+            b = (c & 1, (c >> 1) & 1, (c >> 2) & 1)
+            w = np.prod([f[:, a] if b[a] else 1 - f[:, a] for a in range(3)], axis=0)
+            cx, cy, cz = (i0[:, a] + b[a] for a in range(3))
+            h = (cx ^ ((cy * 2654435761) % 2 ** 32) ^ ((cz * 805459861) % 2 ** 32)) % inp.T
+            v += w[:, None] * inp.tables[l][h, :8]
+        out.append(v)
+    return out
+
+
+@pytest.mark.parametrize("agg", [baked.SHARED_V, baked.SEPARATE_INV, baked.SHARED_INV, baked.SUM])
+def test_aggregation_variants_closed_forms(agg):
+    """Table 3's other aggregations against the coarse grid interpolated by
+    scipy on the dense vertex array and fine values written out by hand:
+    Shared-Att (V) gates both modalities with g(a_l) of the interpolated a_l;
+    the (Inv) variants use constant parameters; SUM adds the levels."""
+    rng = np.random.default_rng(7)
+    L = 2
+    C = 8 + (L if agg == baked.SHARED_V else 0)
+    index, atlas, default = _grid(rng, L=L, C=C)
+    inp = _inputs(index, atlas, default, L=L)
+    consts = (0.7, -1.1, 0.3, 1.9)
+    inp.aggregation = agg
+    inp.gate_params = consts[:2 * L] if agg == baked.SEPARATE_INV else consts[:L]
+    u = rng.random((300, 3))
+    fused, _ = fused64(inp, u)
+    dense = _dense(index, atlas, default)
+    p = u * LC
+    co = np.stack([map_coordinates(dense[..., c], [p[:, 2], p[:, 1], p[:, 0]], order=1, mode="nearest")
+                   for c in range(C)], axis=1)
+    sig = lambda a: 1.0 / (1.0 + np.exp(-np.asarray(a, np.float64)))
+    want = co[:, :8].copy()
+    for l, v in enumerate(_fine_by_hand(inp, u)):
+        if agg == baked.SHARED_V:
+            gw = gb = sig(co[:, 8 + l])
+        elif agg == baked.SEPARATE_INV:
+            gw, gb = sig(consts[2 * l]), sig(consts[2 * l + 1])
+        elif agg == baked.SHARED_INV:
+            gw = gb = sig(consts[l])
+        else:
+            gw = gb = 1.0
+        want[:, 0] += gw * v[:, 0]
+        want[:, 1:] += np.reshape(gb, (-1, 1)) * v[:, 1:]
+    np.testing.assert_allclose(fused, want, rtol=0, atol=1e-9)
+    # the float32 chain follows the same aggregation
+    f32, _, _ = fused32(inp, u.astype(F32))
+    assert np.abs(f32 - fused64(inp, u.astype(F32).astype(np.float64))[0]).max() < 2e-5
+
+
+def test_sum_equals_saturated_separate_gates_in_float32():
+    """SUM takes gates of exactly 1, which is what the float32 sigmoid of
+    +40 rounds to: the two float32 chains agree bit for bit."""
+    rng = np.random.default_rng(8)
+    index, atlas, default = _grid(rng, empty_frac=0.0)
+    atlas[..., 8:] = 40.0
+    default[8:] = 40.0
+    sep = _inputs(index, atlas, default)
+    summ = _inputs(index, np.ascontiguousarray(atlas[..., :8]), np.ascontiguousarray(default[:8]))
+    summ.aggregation = baked.SUM
+    u = rng.random((500, 3)).astype(F32)
+    a, _, _ = fused32(sep, u)
+    b, _, _ = fused32(summ, u)
+    assert np.array_equal(a, b)
+
+
 def test_float32_chain_tracks_float64():
     rng = np.random.default_rng(3)
     index, atlas, default = _grid(rng)
