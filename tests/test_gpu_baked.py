@@ -163,3 +163,33 @@ def test_paper_configuration_render_parity_tiny(dtype):
     ref = render(inp, o, d)
     assert ref.n_samples.mean() > 5
     _check_render(out, ref)
+
+
+def test_baked_reload_coarse_reuse_and_realloc():
+    """Re-loading the coarse grid: same block count (the allocations are
+    kept, as in a training step), then another count (re-allocated), then
+    the original again; every render matches the oracle of what is loaded."""
+    import torch
+    print("[baked coarse reload]", flush=True)
+    sc, _ = scene_and_dist("baked_tiny")
+    cfg = sc.cfg
+    o, d, _ = synth.scene_rays(cfg)
+    o, d = o[::7], d[::7]
+    go, gd = to_gpu(o, d)
+    r = gpu_renderer("baked_tiny")
+    idx = torch.from_numpy(sc.block_index).cuda()
+    first = _np(r.render(go, gd)["rgb"])
+    inp = oracle_inputs("baked_tiny")
+    scaled = (sc.atlas * np.float32(0.5)).astype(F32)
+    r.load_coarse(idx, torch.from_numpy(scaled).cuda(), sc.default)          # same n_blocks
+    inp.atlas = scaled
+    _check_render(r.render(go, gd), render(inp, o, d))
+    keep = sc.block_index >= 0
+    fewer = np.where(keep & (sc.block_index < 100), sc.block_index, -1).astype(np.int32)
+    r.load_coarse(torch.from_numpy(fewer).cuda(), torch.from_numpy(sc.atlas[:100].copy()).cuda(),
+                  sc.default)                                                   # 100 blocks
+    inp.block_index, inp.atlas = fewer, sc.atlas[:100]
+    _check_render(r.render(go, gd), render(inp, o, d))
+    r.load_coarse(idx, torch.from_numpy(sc.atlas).cuda(), sc.default)          # back to all
+    again = _np(r.render(go, gd)["rgb"])
+    assert np.array_equal(first.view(np.uint32), again.view(np.uint32))
