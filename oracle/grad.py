@@ -123,13 +123,15 @@ def forward64(tables64, mlp, resolutions, step, n_rays, s_ray, s_pos, roi_half=1
     np.add.at(c_d, s_ray, w[:, None] * fused[:, 1:4])
     np.add.at(feat, s_ray, w[:, None] * fused[:, 4:8])
     x = np.concatenate([c_d, feat], axis=1)
-    W0, b0, W1, b1, W2, b2 = _split_mlp(mlp)
-    z1 = x @ W0.T + b0
-    h1 = np.maximum(z1, 0)
-    z2 = h1 @ W1.T + b1
-    h2 = np.maximum(z2, 0)
-    o = h2 @ W2.T + b2
-    rgb = 1.0 / (1.0 + np.exp(-(c_d + o)))
+    z1 = h1 = z2 = h2 = rgb = None
+    if mlp is not None:                      # None: the caller handles the MLP (view-dependent)
+        W0, b0, W1, b1, W2, b2 = _split_mlp(mlp)
+        z1 = x @ W0.T + b0
+        h1 = np.maximum(z1, 0)
+        z2 = h1 @ W1.T + b1
+        h2 = np.maximum(z2, 0)
+        o = h2 @ W2.T + b2
+        rgb = 1.0 / (1.0 + np.exp(-(c_d + o)))
     return dict(rgb=rgb, c_d=c_d, feat=feat, x=x, z1=z1, h1=h1, z2=z2, h2=h2, fused=fused,
                 sigma=sigma, ee=ee, Tb=Tb, w=w, wl=wl, lv=lv, idx=idx, wc=wc, delta=delta,
                 parts=parts)
@@ -141,30 +143,38 @@ def loss64(tables64, mlp, resolutions, step, n_rays, s_ray, s_pos, target, roi_h
 
 
 def backward64(tables64, mlp, resolutions, step, n_rays, s_ray, s_pos, grad_rgb, roi_half=1.0,
-               grad_dist=None, s_k=None, coarse=None):
+               grad_dist=None, s_k=None, coarse=None, upstream=None):
     """dL/dtables [L, T, 9] and dL/dmlp [451] for an upstream dL/drgb [n, 3]
     and, optionally, dL/d(distortion regulariser) per ray [n] (s_k: the
     samples' lattice indices).  The regulariser enters as dL/dw_i, which
     adds g_r dL_dist/dw_i to s_i and g_r sum_i w_i dL_dist/dw_i = 2 g_r L_dist
     to S.  With `coarse` (the baked model) the first result is the pair
-    (dL/datlas [n_blocks, 8, 8, 8, C], dL/dfine tables [L, T, 9])."""
-    f = forward64(tables64, mlp, resolutions, step, n_rays, s_ray, s_pos, roi_half, coarse)
-    W0, b0, W1, b1, W2, b2 = _split_mlp(mlp)
-    rgb = f["rgb"]
-    gz = grad_rgb * rgb * (1.0 - rgb)
-    g_o = gz
-    gW2 = g_o.T @ f["h2"]
-    gb2 = g_o.sum(axis=0)
-    gz2 = (g_o @ W2) * (f["z2"] > 0)
-    gW1 = gz2.T @ f["h1"]
-    gb1 = gz2.sum(axis=0)
-    gz1 = (gz2 @ W1) * (f["z1"] > 0)
-    gW0 = gz1.T @ f["x"]
-    gb0 = gz1.sum(axis=0)
-    gx = gz1 @ W0
-    g_cd = gz + gx[:, :3]
-    g_f = gx[:, 3:]
-    gmlp = np.concatenate([gW0.ravel(), gb0, gW1.ravel(), gb1, gW2.ravel(), gb2])
+    (dL/datlas [n_blocks, 8, 8, 8, C], dL/dfine tables [L, T, 9]).  With
+    `upstream` = (dL/dC_d [n, 3], dL/dF [n, 4]) the MLP is skipped (grad_rgb
+    unused, dL/dmlp None): the view-dependent MLP's adjoint supplies them."""
+    f = forward64(tables64, None if upstream is not None else mlp, resolutions, step, n_rays, s_ray,
+                  s_pos, roi_half, coarse)
+    if upstream is not None:
+        # dL/dC_d [n, 3] and dL/dF [n, 4] given (the view-dependent MLP's adjoint)
+        g_cd, g_f = (np.asarray(a, np.float64) for a in upstream)
+        gmlp = None
+    else:
+        W0, b0, W1, b1, W2, b2 = _split_mlp(mlp)
+        rgb = f["rgb"]
+        gz = grad_rgb * rgb * (1.0 - rgb)
+        g_o = gz
+        gW2 = g_o.T @ f["h2"]
+        gb2 = g_o.sum(axis=0)
+        gz2 = (g_o @ W2) * (f["z2"] > 0)
+        gW1 = gz2.T @ f["h1"]
+        gb1 = gz2.sum(axis=0)
+        gz1 = (gz2 @ W1) * (f["z1"] > 0)
+        gW0 = gz1.T @ f["x"]
+        gb0 = gz1.sum(axis=0)
+        gx = gz1 @ W0
+        g_cd = gz + gx[:, :3]
+        g_f = gx[:, 3:]
+        gmlp = np.concatenate([gW0.ravel(), gb0, gW1.ravel(), gb1, gW2.ravel(), gb2])
 
     fused, w, Tb, ee, sigma = f["fused"], f["w"], f["Tb"], f["ee"], f["sigma"]
     s = (g_cd[s_ray] * fused[:, 1:4]).sum(axis=1) + (g_f[s_ray] * fused[:, 4:8]).sum(axis=1)

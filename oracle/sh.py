@@ -79,3 +79,36 @@ def mlp_view64(params: np.ndarray, c_d: np.ndarray, feat: np.ndarray, d: np.ndar
     a1 = np.maximum(x @ W0.T + b0, 0.0)
     a2 = np.maximum(a1 @ W1.T + b1, 0.0)
     return a2 @ W2.T + b2
+
+
+def _split_view(params):
+    p = np.asarray(params, dtype=np.float64)
+    i, h1, h2, o = DIMS_VIEW
+    sizes = [h1 * i, h1, h2 * h1, h2, o * h2, o]
+    parts, off = [], 0
+    for s in sizes:
+        parts.append(p[off:off + s])
+        off += s
+    W0, b0, W1, b1, W2, b2 = parts
+    return W0.reshape(h1, i), b0, W1.reshape(h2, h1), b1, W2.reshape(o, h2), b2
+
+
+def mlp_view_backward64(params, c_d, feat, d, grad_rgb):
+    """Adjoint of rgb = sigmoid(C_d + MLP_psi(C_d, F, SH(d))) in float64 for an
+    upstream dL/drgb [m, 3]: dL/dC_d [m, 3], dL/dF [m, 4] and dL/dpsi [5891]
+    (same flattened order as the parameters).  SH(d) is a constant input."""
+    W0, b0, W1, b1, W2, b2 = _split_view(params)
+    x = np.concatenate([np.asarray(c_d, np.float64), np.asarray(feat, np.float64), sh16(d)], axis=1)
+    z1 = x @ W0.T + b0
+    a1 = np.maximum(z1, 0.0)
+    z2 = a1 @ W1.T + b1
+    a2 = np.maximum(z2, 0.0)
+    out = a2 @ W2.T + b2
+    rgb = 1.0 / (1.0 + np.exp(-(x[:, :3] + out)))
+    gz = np.asarray(grad_rgb, np.float64) * rgb * (1.0 - rgb)       # dL/d(C_d + out)
+    g2 = (gz @ W2) * (z2 > 0)
+    g1 = (g2 @ W1) * (z1 > 0)
+    gx = g1 @ W0
+    g_params = np.concatenate([(g1.T @ x).ravel(), g1.sum(0), (g2.T @ a1).ravel(), g2.sum(0),
+                               (gz.T @ a2).ravel(), gz.sum(0)])
+    return gz + gx[:, :3], gx[:, 3:7], g_params
