@@ -86,7 +86,7 @@ def bench_train(args):
 
     import synth
     from paper_2407_10482_amd.renderer import (Renderer, adam_step, render_differentiable,
-                                               render_differentiable_baked)
+                                               render_differentiable_baked, render_differentiable_view)
 
     baked = args.model == "baked"
     if baked:
@@ -94,10 +94,15 @@ def bench_train(args):
         if args.train_size != "tiny":
             raise SystemExit("--mode train --model baked trains the baked model of the tiny scene only")
         cfg = synth.baked_tiny()
+        if args.mlp == "view":
+            cfg.mlp_dims = (23, 64, 64, 3)
         sc, teacher = make_baked_scene(cfg), make_baked_scene(cfg, seed=1)
     else:
         cfg = synth.CONFIGS[args.train_size]()
+        if args.mlp == "view":
+            cfg.mlp_dims = (23, 64, 64, 3)
         sc, teacher = synth.make_scene(cfg), synth.make_scene(cfg, seed=1)
+    view = args.mlp == "view"
     cams = synth.random_sphere_cameras(16, 1.0, seed=123)
     o, d, _ = synth.scene_rays(cfg, cams=cams, width=128, height=128)
     torch.cuda.set_device(0)
@@ -117,7 +122,10 @@ def bench_train(args):
     state = {"step": 0, "loss": []}
 
     def step():
-        if baked:
+        if view:
+            rgb = render_differentiable_view(r, params[0], params[-1], go, gd,
+                                             atlas=params[1] if baked else None)
+        elif baked:
             rgb = render_differentiable_baked(r, *params, go, gd)
         else:
             rgb = render_differentiable(r, *params, go, gd)
@@ -153,8 +161,9 @@ def bench_train(args):
                                + (f"coarse grid L_C = {cfg.coarse_res} ({sc.atlas.shape[0]} blocks of 8^3) + "
                                   if baked else "")
                                + f"{cfg.n_levels} levels {cfg.n_min}..{cfg.n_max}, "
-                               f"2^{cfg.log2_table} entries, 2^18 rays from 16 cameras x 128^2, "
-                               "MSE vs a seed-1 teacher, Adam lr 0.01",
+                               f"2^{cfg.log2_table} entries, "
+                               + ("view-dependent MLP 23-64-64-3, " if view else "")
+                               + "2^18 rays from 16 cameras x 128^2, MSE vs a seed-1 teacher, Adam lr 0.01",
                    "rays_per_step": len(o), "parameters": n_params},
         "loss_first": first, "loss_last": loss.item(),
     }

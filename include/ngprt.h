@@ -325,6 +325,29 @@ int ngprt_render_backward_baked(ngprt_ctx* ctx, int64_t n_rays, const float* dev
                                 float* dev_grad_tables, float* dev_grad_atlas, float* dev_grad_mlp,
                                 void* stream);
 
+/* Backward of the view-dependent MLP (Eq. 5; supplement "Network Design"),
+ * rgb = sigmoid(C_d + MLP_psi(C_d, F, SH(d))), for contexts with the
+ * 23-64-64-3 MLP (NGPRT_E_UNSUPPORTED otherwise).  Inputs per ray: the
+ * directions, C_d [n][3] and F [n][4] as ngprt_render wrote them, dL/drgb
+ * [n][3].  Writes dL/dC_d and dL/dF to dev_grad_cf, float32 [n][7]
+ * (C_d first), and accumulates (+=) dL/dpsi into dev_grad_mlp [5891] (the
+ * caller zeroes it; partial sums per 64 rays added in a fixed order).  SH(d)
+ * is a constant input.  May grow the library workspace. */
+int ngprt_view_mlp_backward(ngprt_ctx* ctx, int64_t n_rays, const float* dev_dirs, const float* dev_c_d,
+                            const float* dev_feat, const float* dev_grad_rgb, float* dev_grad_cf,
+                            float* dev_grad_mlp, void* stream);
+
+/* The render backward from dL/dC_d and dL/dF per ray (dev_grad_cf, float32
+ * [n][7], e.g. from ngprt_view_mlp_backward) instead of dL/drgb: the MLP
+ * is not involved.  Accumulates (+=) dL/dtables into dev_grad_tables [L][T][9]
+ * and, for NGPRT_MODEL_BAKED, dL/datlas into dev_grad_atlas (layouts and
+ * conditions as ngprt_render_backward_reg / ngprt_render_backward_baked;
+ * dev_grad_atlas is ignored for the hash model).  dev_grad_dist as in
+ * ngprt_render_backward_reg. */
+int ngprt_render_backward_features(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins,
+                                   const float* dev_dirs, const float* dev_grad_cf, const float* dev_grad_dist,
+                                   float* dev_grad_tables, float* dev_grad_atlas, void* stream);
+
 /* Change the lattice step (the paper's marching-step auto-tuning,
  * supplement Eq. S3, scales it between training batches).  Same checks as
  * desc.step (NGPRT_E_INVALID_ARG).  Later calls use the new step. */

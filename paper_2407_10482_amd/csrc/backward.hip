@@ -209,6 +209,7 @@ __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, c
                                                        const float* __restrict__ D,
                                                        const float* __restrict__ grad_rgb,
                                                        const float* __restrict__ grad_dist,
+                                                       const float* __restrict__ ups,
                                                        float* __restrict__ gtab, float* __restrict__ gatlas,
                                                        float* __restrict__ partial,
                                                        const float* __restrict__ P) {
@@ -257,124 +258,136 @@ __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, c
     }
   }
 
-  // ---------------- deferred MLP forward + backward (per lane)
-  float x[8] = {cd[0], cd[1], cd[2], fv[0], fv[1], fv[2], fv[3], 1.0f};
-  float z1[16], h1[16], z2[16], h2[16], oo[3];
+  float gcd[3], gfv[4];
+  if (ups) {
+    // dL/dC_d and dL/dF given per ray (the view-dependent MLP's adjoint):
+    // no MLP here, no MLP partials
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    float a = P[112 + i];
+    for (int j = 0; j < 3; ++j) gcd[j] = in_range ? ups[ray * 7 + j] : 0.0f;
 #pragma unroll
-    for (int k = 0; k < 7; ++k) a = __builtin_fmaf(P[i * 7 + k], x[k], a);
-    z1[i] = a;
-    h1[i] = fmaxf(a, 0.0f);
+    for (int j = 0; j < 4; ++j) gfv[j] = in_range ? ups[ray * 7 + 3 + j] : 0.0f;
+  } else {
+    // ---------------- deferred MLP forward + backward (per lane)
+    float x[8] = {cd[0], cd[1], cd[2], fv[0], fv[1], fv[2], fv[3], 1.0f};
+    float z1[16], h1[16], z2[16], h2[16], oo[3];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      float a = P[112 + i];
+#pragma unroll
+      for (int k = 0; k < 7; ++k) a = __builtin_fmaf(P[i * 7 + k], x[k], a);
+      z1[i] = a;
+      h1[i] = fmaxf(a, 0.0f);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      float a = P[384 + i];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) a = __builtin_fmaf(P[128 + i * 16 + k], h1[k], a);
+      z2[i] = a;
+      h2[i] = fmaxf(a, 0.0f);
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      float a = P[448 + i];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) a = __builtin_fmaf(P[400 + i * 16 + k], h2[k], a);
+      oo[i] = a;
+    }
+    float gz[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const float C = 1.0f / (1.0f + __expf(-(cd[j] + oo[j])));
+      const float g = in_range ? grad_rgb[ray * 3 + j] : 0.0f;
+      gz[j] = g * C * (1.0f - C);
+    }
+    float gz2[16], gz1[16], gx[7];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      float a = 0.0f;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) a = __builtin_fmaf(P[400 + i * 16 + k], gz[i], a);
+      gz2[k] = z2[k] > 0.0f ? a : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      float a = 0.0f;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) a = __builtin_fmaf(P[128 + i * 16 + k], gz2[i], a);
+      gz1[k] = z1[k] > 0.0f ? a : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+      float a = 0.0f;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) a = __builtin_fmaf(P[i * 7 + k], gz1[i], a);
+      gx[k] = a;
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) gcd[j] = gz[j] + gx[j];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) gfv[j] = gx[3 + j];
+
+    // ---------------- MLP weight gradients: sums over the wave on MFMA
+    float* sA = sA_all[wave];
+    float* sB = sB_all[wave];
+    float* part = partial + (int64_t(blockIdx.x) * 4 + wave) * kMlpParams;
+    const int qi = lane >> 4, col = lane & 15;
+    // W0 (16 x 7) and b0 (column 7 of x is 1)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) sA[lane * kPad + i] = gz1[i];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) sB[lane * kPad + j] = j < 8 ? x[j < 8 ? j : 0] : 0.0f;
+    __syncthreads();
+    {
+      bf32x4 r = wave_outer_sum(sA, sB, lane);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = 4 * qi + q;
+        if (col < 7) part[i * 7 + col] = r[q];
+        else if (col == 7) part[112 + i] = r[q];
+      }
+    }
+    __syncthreads();
+    // W1 (16 x 16) and b1
+#pragma unroll
+    for (int i = 0; i < 16; ++i) sA[lane * kPad + i] = gz2[i];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) sB[lane * kPad + j] = h1[j];
+    __syncthreads();
+    {
+      bf32x4 r = wave_outer_sum(sA, sB, lane);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) part[128 + (4 * qi + q) * 16 + col] = r[q];
+      if (lane < 16) {
+        float a = 0.0f;
+        for (int rr = 0; rr < 64; ++rr) a += sA[rr * kPad + lane];
+        part[384 + lane] = a;
+      }
+    }
+    __syncthreads();
+    // W2 (3 x 16) and b2
+#pragma unroll
+    for (int i = 0; i < 16; ++i) sA[lane * kPad + i] = i < 3 ? gz[i < 3 ? i : 0] : 0.0f;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) sB[lane * kPad + j] = h2[j];
+    __syncthreads();
+    {
+      bf32x4 r = wave_outer_sum(sA, sB, lane);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = 4 * qi + q;
+        if (i < 3) part[400 + i * 16 + col] = r[q];
+      }
+      if (lane < 3) {
+        float a = 0.0f;
+        for (int rr = 0; rr < 64; ++rr) a += sA[rr * kPad + lane];
+        part[448 + lane] = a;
+      }
+    }
   }
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    float a = P[384 + i];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) a = __builtin_fmaf(P[128 + i * 16 + k], h1[k], a);
-    z2[i] = a;
-    h2[i] = fmaxf(a, 0.0f);
-  }
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    float a = P[448 + i];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) a = __builtin_fmaf(P[400 + i * 16 + k], h2[k], a);
-    oo[i] = a;
-  }
-  float gz[3];
-#pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    const float C = 1.0f / (1.0f + __expf(-(cd[j] + oo[j])));
-    const float g = in_range ? grad_rgb[ray * 3 + j] : 0.0f;
-    gz[j] = g * C * (1.0f - C);
-  }
-  float gz2[16], gz1[16], gx[7];
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    float a = 0.0f;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) a = __builtin_fmaf(P[400 + i * 16 + k], gz[i], a);
-    gz2[k] = z2[k] > 0.0f ? a : 0.0f;
-  }
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    float a = 0.0f;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) a = __builtin_fmaf(P[128 + i * 16 + k], gz2[i], a);
-    gz1[k] = z1[k] > 0.0f ? a : 0.0f;
-  }
-#pragma unroll
-  for (int k = 0; k < 7; ++k) {
-    float a = 0.0f;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) a = __builtin_fmaf(P[i * 7 + k], gz1[i], a);
-    gx[k] = a;
-  }
-  float gcd[3] = {gz[0] + gx[0], gz[1] + gx[1], gz[2] + gx[2]};
-  float gfv[4] = {gx[3], gx[4], gx[5], gx[6]};
   const float Ldist = 2.0f * dP + dQ * (S.step * (1.0f / 3.0f));
   const float Stot = gdist * (2.0f * Ldist) + (gcd[0] * cd[0] + gcd[1] * cd[1] + gcd[2] * cd[2]) +
                      (gfv[0] * fv[0] + gfv[1] * fv[1] + gfv[2] * fv[2] + gfv[3] * fv[3]);
-
-  // ---------------- MLP weight gradients: sums over the wave on MFMA
-  float* sA = sA_all[wave];
-  float* sB = sB_all[wave];
-  float* part = partial + (int64_t(blockIdx.x) * 4 + wave) * kMlpParams;
-  const int qi = lane >> 4, col = lane & 15;
-  // W0 (16 x 7) and b0 (column 7 of x is 1)
-#pragma unroll
-  for (int i = 0; i < 16; ++i) sA[lane * kPad + i] = gz1[i];
-#pragma unroll
-  for (int j = 0; j < 16; ++j) sB[lane * kPad + j] = j < 8 ? x[j < 8 ? j : 0] : 0.0f;
-  __syncthreads();
-  {
-    bf32x4 r = wave_outer_sum(sA, sB, lane);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int i = 4 * qi + q;
-      if (col < 7) part[i * 7 + col] = r[q];
-      else if (col == 7) part[112 + i] = r[q];
-    }
-  }
-  __syncthreads();
-  // W1 (16 x 16) and b1
-#pragma unroll
-  for (int i = 0; i < 16; ++i) sA[lane * kPad + i] = gz2[i];
-#pragma unroll
-  for (int j = 0; j < 16; ++j) sB[lane * kPad + j] = h1[j];
-  __syncthreads();
-  {
-    bf32x4 r = wave_outer_sum(sA, sB, lane);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) part[128 + (4 * qi + q) * 16 + col] = r[q];
-    if (lane < 16) {
-      float a = 0.0f;
-      for (int rr = 0; rr < 64; ++rr) a += sA[rr * kPad + lane];
-      part[384 + lane] = a;
-    }
-  }
-  __syncthreads();
-  // W2 (3 x 16) and b2
-#pragma unroll
-  for (int i = 0; i < 16; ++i) sA[lane * kPad + i] = i < 3 ? gz[i < 3 ? i : 0] : 0.0f;
-#pragma unroll
-  for (int j = 0; j < 16; ++j) sB[lane * kPad + j] = h2[j];
-  __syncthreads();
-  {
-    bf32x4 r = wave_outer_sum(sA, sB, lane);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int i = 4 * qi + q;
-      if (i < 3) part[400 + i * 16 + col] = r[q];
-    }
-    if (lane < 3) {
-      float a = 0.0f;
-      for (int rr = 0; rr < 64; ++rr) a += sA[rr * kPad + lane];
-      part[448 + lane] = a;
-    }
-  }
 
   // ---------------- pass 2: re-march and scatter
   // Every lane takes part in each iteration (lanes without a sample carry a
@@ -512,7 +525,8 @@ __global__ void adam_kernel(int64_t n, float* __restrict__ p, const float* __res
 }
 
 int launch_backward(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const float* grad_rgb,
-                    const float* grad_dist, float* gtab, float* gatlas, float* gmlp, hipStream_t st) {
+                    const float* grad_dist, const float* ups, float* gtab, float* gatlas, float* gmlp,
+                    hipStream_t st) {
   SceneArgs S = scene_args(ctx);
   const int64_t blocks = (n + 255) / 256;
   if (blocks > 0x7FFFFFFF) return fail(ctx, NGPRT_E_SHAPE, "too many rays for one launch");
@@ -533,7 +547,7 @@ int launch_backward(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, c
   const bool box = ctx->desc.domain == DOM_BOX;
 #define NGPRT_BW(DOMV, LM, PY, MD)                                                                 \
   hipLaunchKernelGGL((backward_kernel<DOMV, LM, PY, MD>), g, dim3(256), 0, st, S, n, o, d, grad_rgb,   \
-                     grad_dist, gtab, gatlas, partial, ctx->mlp)
+                     grad_dist, ups, gtab, gatlas, partial, ctx->mlp)
   if (S.model == NGPRT_MODEL_BAKED) {
     if (S.pyr_n > 0) {
       if (box) NGPRT_BW(DOM_BOX, 4, true, 1);
@@ -554,7 +568,7 @@ int launch_backward(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, c
   }
 #undef NGPRT_BW
   int rc = check_launch(ctx, "backward_kernel");
-  if (rc) return rc;
+  if (rc || ups) return rc;
   hipLaunchKernelGGL(reduce_partials_kernel, dim3(2), dim3(256), 0, st, partial, n_waves, gmlp);
   return check_launch(ctx, "reduce_partials_kernel");
 }

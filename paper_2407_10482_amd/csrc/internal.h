@@ -138,7 +138,10 @@ int launch_eval_points(ngprt_ctx* ctx, int64_t n, const float* pos, int32_t* idx
 int launch_march(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, int32_t cap,
                  int32_t* sk, int32_t* ns, int32_t* nr, int naive, hipStream_t s);
 int launch_backward(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const float* grad_rgb,
-                    const float* grad_dist, float* gtab, float* gatlas, float* gmlp, hipStream_t s);
+                    const float* grad_dist, const float* ups, float* gtab, float* gatlas, float* gmlp,
+                    hipStream_t s);
+int launch_view_mlp_backward(ngprt_ctx* ctx, int64_t n, const float* d, const float* c_d, const float* feat,
+                             const float* grad_rgb, float* grad_cf, float* gmlp, hipStream_t s);
 int launch_view_mlp_arrange(ngprt_ctx* ctx, const float* params, hipStream_t s);
 int launch_view_mlp(ngprt_ctx* ctx, int64_t n, const float* d, const float* c_d, const float* feat,
                     float* rgb, hipStream_t s);

@@ -159,6 +159,209 @@ __global__ void __launch_bounds__(256) view_mlp_kernel(int64_t n, const float* _
   }
 }
 
+// ---------------------------------------------------------------------------
+// Backward of the view-dependent MLP (a training extension).  One wave =
+// one workgroup = 64 rays, a lane per ray; the weights come from the
+// flattened parameters by uniform (scalar) loads.  Per lane: the forward
+// again (activation rows a1, a2 in LDS, ReLU masks as bits), gz = dL/drgb
+// * rgb (1 - rgb), g2 = (W2^T gz) masked, g1 = (W1^T g2) masked,
+// dL/dC_d = gz + (W0^T g1)[0..2], dL/dF = (W0^T g1)[3..6].  The weight
+// gradients are sums over the wave's rays of outer products, taken on
+// v_mfma_f32_16x16x4f32 with the rays as K, and written as one 5891-float
+// partial per wave; a second kernel adds the partials in a fixed order.
+constexpr int kVP = 65;                                  // LDS row pitch (bank spread)
+constexpr int kW0 = 0, kB0 = 64 * 23, kW1 = kB0 + 64, kB1 = kW1 + 64 * 64, kW2 = kB1 + 64,
+              kB2 = kW2 + 3 * 64;
+static_assert(kB2 + 3 == kMlpViewParams, "parameter layout");
+
+// D[ia + i][jb + j] = sum over the wave's 64 rays r of A[r][ia + i] * B[r][jb + j]
+// (i, j < 16); lane l gets D[ia + 4 (l / 16) + q][jb + l % 16], q = 0..3.
+__device__ __forceinline__ f32x4v outer16(const float* A, int pa, int ia, const float* B, int pb, int jb,
+                                          int lane) {
+  const int i = lane & 15, s = lane >> 4;
+  f32x4v acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    const int r = 4 * c + s;
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[r * pa + ia + i], B[r * pb + jb + i], acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+__global__ void __launch_bounds__(64) view_mlp_backward_kernel(int64_t n, const float* __restrict__ D,
+                                                               const float* __restrict__ c_d,
+                                                               const float* __restrict__ feat,
+                                                               const float* __restrict__ grad_rgb,
+                                                               const float* __restrict__ P,
+                                                               float* __restrict__ grad_cf,
+                                                               float* __restrict__ partial) {
+  __shared__ float sA[64 * kVP];       // a1
+  __shared__ float sB[64 * kVP];       // a2, then g1
+  __shared__ float sC[64 * kVP];       // g2
+  __shared__ float sX[64 * 32];        // x (23 used, zero padded)
+  __shared__ float sG[64 * 16];        // gz (3 used, zero padded)
+  const int lane = threadIdx.x;
+  const int64_t ray = int64_t(blockIdx.x) * 64 + lane;
+  const bool ok = ray < n;
+  float x[23];
+#pragma unroll
+  for (int j = 0; j < 23; ++j) x[j] = 0.0f;
+  float g[3] = {0.0f, 0.0f, 0.0f};
+  if (ok) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) x[j] = c_d[ray * 3 + j];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) x[3 + j] = feat[ray * 4 + j];
+    const float d0 = D[ray * 3], d1 = D[ray * 3 + 1], d2 = D[ray * 3 + 2];
+    const float nn = sqrtf((d0 * d0 + d1 * d1) + d2 * d2);
+    if (nn > 0.0f && isfinite(nn)) sh16(d0 / nn, d1 / nn, d2 / nn, x + 7);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) g[j] = grad_rgb[ray * 3 + j];
+  }
+  float* rowA = sA + lane * kVP;
+  float* rowB = sB + lane * kVP;
+  float* rowC = sC + lane * kVP;
+  float* rowX = sX + lane * 32;
+  float* rowG = sG + lane * 16;
+#pragma unroll
+  for (int j = 0; j < 32; ++j) rowX[j] = j < 23 ? x[j < 23 ? j : 0] : 0.0f;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) rowG[j] = 0.0f;
+  // forward
+  uint64_t m1 = 0, m2 = 0;
+  for (int j = 0; j < 64; ++j) {
+    float z = P[kB0 + j];
+#pragma unroll
+    for (int k = 0; k < 23; ++k) z = __builtin_fmaf(P[kW0 + j * 23 + k], x[k], z);
+    m1 |= uint64_t(z > 0.0f) << j;
+    rowA[j] = fmaxf(z, 0.0f);
+  }
+  for (int i = 0; i < 64; ++i) {
+    float z = P[kB1 + i];
+    for (int j = 0; j < 64; ++j) z = __builtin_fmaf(P[kW1 + i * 64 + j], rowA[j], z);
+    m2 |= uint64_t(z > 0.0f) << i;
+    rowB[i] = fmaxf(z, 0.0f);
+  }
+  float gz[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    float o = P[kB2 + c];
+    for (int i = 0; i < 64; ++i) o = __builtin_fmaf(P[kW2 + c * 64 + i], rowB[i], o);
+    const float C = 1.0f / (1.0f + __expf(-(x[c] + o)));
+    gz[c] = g[c] * C * (1.0f - C);
+    rowG[c] = gz[c];
+  }
+  // g2
+  for (int i = 0; i < 64; ++i) {
+    float a = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a = __builtin_fmaf(P[kW2 + c * 64 + i], gz[c], a);
+    rowC[i] = ((m2 >> i) & 1) ? a : 0.0f;
+  }
+  __syncthreads();
+  float* part = partial + int64_t(blockIdx.x) * kMlpViewParams;
+  const int qi = lane >> 4, col = lane & 15;
+  // dW2 [3][64] = sum gz (x) a2; db2
+#pragma unroll
+  for (int jb = 0; jb < 64; jb += 16) {
+    f32x4v r = outer16(sG, 16, 0, sB, kVP, jb, lane);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = 4 * qi + q;
+      if (c < 3) part[kW2 + c * 64 + jb + col] = r[q];
+    }
+  }
+  if (lane < 3) {
+    float a = 0.0f;
+    for (int r = 0; r < 64; ++r) a += sG[r * 16 + lane];
+    part[kB2 + lane] = a;
+  }
+  // dW1 [64][64] = sum g2 (x) a1; db1
+#pragma unroll
+  for (int ia = 0; ia < 64; ia += 16) {
+#pragma unroll
+    for (int jb = 0; jb < 64; jb += 16) {
+      f32x4v r = outer16(sC, kVP, ia, sA, kVP, jb, lane);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) part[kW1 + (ia + 4 * qi + q) * 64 + jb + col] = r[q];
+    }
+  }
+  {
+    float a = 0.0f;
+    for (int r = 0; r < 64; ++r) a += sC[r * kVP + lane];
+    part[kB1 + lane] = a;
+  }
+  __syncthreads();
+  // g1 (over a2's rows, no longer needed) and the input gradients
+  float gx[7] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  for (int j = 0; j < 64; ++j) {
+    float a = 0.0f;
+    for (int i = 0; i < 64; ++i) a = __builtin_fmaf(P[kW1 + i * 64 + j], rowC[i], a);
+    const float g1 = ((m1 >> j) & 1) ? a : 0.0f;
+    rowB[j] = g1;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) gx[k] = __builtin_fmaf(P[kW0 + j * 23 + k], g1, gx[k]);
+  }
+  if (ok) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) grad_cf[ray * 7 + c] = gz[c] + gx[c];
+#pragma unroll
+    for (int k = 3; k < 7; ++k) grad_cf[ray * 7 + k] = gx[k];
+  }
+  __syncthreads();
+  // dW0 [64][23] = sum g1 (x) x; db0
+#pragma unroll
+  for (int ia = 0; ia < 64; ia += 16) {
+#pragma unroll
+    for (int jb = 0; jb < 32; jb += 16) {
+      f32x4v r = outer16(sB, kVP, ia, sX, 32, jb, lane);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = jb + col;
+        if (k < 23) part[kW0 + (ia + 4 * qi + q) * 23 + k] = r[q];
+      }
+    }
+  }
+  {
+    float a = 0.0f;
+    for (int r = 0; r < 64; ++r) a += sB[r * kVP + lane];
+    part[kB0 + lane] = a;
+  }
+}
+
+__global__ void view_reduce_kernel(const float* __restrict__ partial, int64_t n_waves, float* __restrict__ out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= kMlpViewParams) return;
+  float a = 0.0f;
+  for (int64_t w = 0; w < n_waves; ++w) a += partial[w * kMlpViewParams + p];
+  out[p] += a;
+}
+
+int launch_view_mlp_backward(ngprt_ctx* ctx, int64_t n, const float* d, const float* c_d, const float* feat,
+                             const float* grad_rgb, float* grad_cf, float* gmlp, hipStream_t st) {
+  const int64_t waves = (n + 63) / 64;
+  if (waves > 0x7FFFFFFF) return fail(ctx, NGPRT_E_SHAPE, "too many rays for one launch");
+  const size_t need = size_t(waves) * kMlpViewParams * sizeof(float);
+  if (need > ctx->ws_bytes) {
+    if (ctx->ws) (void)hipFreeAsync(ctx->ws, st);
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+    if (hipMallocAsync(&ctx->ws, need, st) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(ctx, NGPRT_E_ALLOC, "view MLP backward workspace allocation failed");
+    }
+    ctx->ws_bytes = need;
+  }
+  float* partial = reinterpret_cast<float*>(ctx->ws);
+  hipLaunchKernelGGL(view_mlp_backward_kernel, dim3(unsigned(waves)), dim3(64), 0, st, n, d, c_d, feat, grad_rgb,
+                     ctx->mlp, grad_cf, partial);
+  int rc = check_launch(ctx, "view_mlp_backward_kernel");
+  if (rc) return rc;
+  hipLaunchKernelGGL(view_reduce_kernel, dim3((kMlpViewParams + 255) / 256), dim3(256), 0, st, partial, waves,
+                     gmlp);
+  return check_launch(ctx, "view_reduce_kernel");
+}
+
 int launch_view_mlp_arrange(ngprt_ctx* ctx, const float* params, hipStream_t st) {
   hipLaunchKernelGGL(view_mlp_arrange_kernel, dim3((kViewRecFloats + 255) / 256), dim3(256), 0, st, params,
                      ctx->mlp_rec);

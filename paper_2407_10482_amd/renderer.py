@@ -272,6 +272,38 @@ def _renderer_backward_baked(self: Renderer, origins, dirs, grad_rgb, grad_table
           self.ctx)
 
 
+def _renderer_view_mlp_backward(self: Renderer, dirs, c_d, feat, grad_rgb, grad_mlp) -> torch.Tensor:
+    """View-dependent MLP: dL/dC_d and dL/dF per ray [n, 7] for dL/drgb,
+    accumulating dL/dpsi [5891] into grad_mlp."""
+    n = dirs.shape[0]
+    _dev(dirs, torch.float32, (n, 3), "dirs")
+    _dev(c_d, torch.float32, (n, 3), "c_d")
+    _dev(feat, torch.float32, (n, 4), "feat")
+    _dev(grad_rgb, torch.float32, (n, 3), "grad_rgb")
+    _dev(grad_mlp, torch.float32, (self.n_mlp,), "grad_mlp")
+    grad_cf = torch.empty((n, 7), dtype=torch.float32, device=dirs.device)
+    check(self.lib.ngprt_view_mlp_backward(self.ctx, n, _ptr(dirs), _ptr(c_d), _ptr(feat), _ptr(grad_rgb),
+                                           _ptr(grad_cf), _ptr(grad_mlp), _stream()), self.ctx)
+    return grad_cf
+
+
+def _renderer_backward_features(self: Renderer, origins, dirs, grad_cf, grad_tables, grad_atlas=None,
+                                grad_dist=None):
+    """Accumulate dL/dtables (and, baked model, dL/datlas) from dL/dC_d and
+    dL/dF per ray [n, 7]."""
+    n = origins.shape[0]
+    _dev(grad_cf, torch.float32, (n, 7), "grad_cf")
+    _dev(grad_tables, torch.float32, (self.L, self.T, 9), "grad_tables")
+    if grad_dist is not None:
+        _dev(grad_dist, torch.float32, (n,), "grad_dist")
+    nblk = getattr(self, "n_blocks", 0) if self.feature_model == MODEL_BAKED else 0
+    if nblk:
+        _dev(grad_atlas, torch.float32, (nblk, 8, 8, 8, 8 + 2 * self.L), "grad_atlas")
+    check(self.lib.ngprt_render_backward_features(self.ctx, n, _ptr(origins), _ptr(dirs), _ptr(grad_cf),
+                                                  _ptr(grad_dist), _ptr(grad_tables),
+                                                  _ptr(grad_atlas) if nblk else None, _stream()), self.ctx)
+
+
 def _renderer_set_step(self: Renderer, step: float):
     check(self.lib.ngprt_set_step(self.ctx, float(step)), self.ctx)
     self.step = float(step)
@@ -279,6 +311,8 @@ def _renderer_set_step(self: Renderer, step: float):
 
 Renderer.backward = _renderer_backward
 Renderer.backward_baked = _renderer_backward_baked
+Renderer.view_mlp_backward = _renderer_view_mlp_backward
+Renderer.backward_features = _renderer_backward_features
 Renderer.set_step = _renderer_set_step
 
 
@@ -387,6 +421,62 @@ class BakedRenderFunction(torch.autograd.Function):
         gdist = grad_dist.contiguous().float() if (ctx.with_dist and grad_dist is not None) else None
         r.backward_baked(origins, dirs, grad_rgb.contiguous().float(), gt, ga, gm, gdist)
         return gt, ga, gm, None, None, None, None
+
+
+class ViewRenderFunction(torch.autograd.Function):
+    """rgb with the view-dependent MLP (either feature model) as a function
+    of the tables, the coarse atlas (baked model; None otherwise) and psi:
+    backward runs the MLP's adjoint, then the render adjoint from dL/dC_d
+    and dL/dF."""
+
+    @staticmethod
+    def forward(ctx, tables, atlas, mlp, origins, dirs, renderer, with_dist):
+        renderer.load_tables(tables.detach().contiguous())
+        if atlas is not None:
+            renderer.load_coarse(renderer._coarse_index, atlas.detach().contiguous(),
+                                 renderer._coarse_default)
+        renderer.load_mlp(mlp.detach().contiguous())
+        n = origins.shape[0]
+        dev = origins.device
+        out = {"rgb": torch.empty((n, 3), dtype=torch.float32, device=dev),
+               "c_d": torch.empty((n, 3), dtype=torch.float32, device=dev),
+               "feat": torch.empty((n, 4), dtype=torch.float32, device=dev)}
+        if with_dist:
+            out["dist_loss"] = torch.empty((n,), dtype=torch.float32, device=dev)
+        renderer.render(origins, dirs, out=out)
+        ctx.renderer = renderer
+        ctx.with_dist = with_dist
+        ctx.atlas_shape = None if atlas is None else tuple(atlas.shape)
+        ctx.save_for_backward(origins, dirs, out["c_d"], out["feat"])
+        if not with_dist:
+            dist = torch.zeros((n,), dtype=torch.float32, device=dev)
+            ctx.mark_non_differentiable(dist)
+            return out["rgb"], dist
+        return out["rgb"], out["dist_loss"]
+
+    @staticmethod
+    def backward(ctx, grad_rgb, grad_dist):
+        origins, dirs, c_d, feat = ctx.saved_tensors
+        r = ctx.renderer
+        dev = origins.device
+        if grad_rgb is None:
+            grad_rgb = torch.zeros((origins.shape[0], 3), dtype=torch.float32, device=dev)
+        gm = torch.zeros((r.n_mlp,), dtype=torch.float32, device=dev)
+        grad_cf = r.view_mlp_backward(dirs, c_d, feat, grad_rgb.contiguous().float(), gm)
+        gt = torch.zeros((r.L, r.T, 9), dtype=torch.float32, device=dev)
+        ga = None if ctx.atlas_shape is None else torch.zeros(ctx.atlas_shape, dtype=torch.float32, device=dev)
+        gdist = grad_dist.contiguous().float() if (ctx.with_dist and grad_dist is not None) else None
+        r.backward_features(origins, dirs, grad_cf, gt, ga, gdist)
+        return gt, ga, gm, None, None, None, None
+
+
+def render_differentiable_view(renderer: Renderer, tables, mlp, origins, dirs, atlas=None,
+                               with_dist: bool = False):
+    """View-dependent MLP: rgb (and, with_dist, the distortion regulariser)
+    as differentiable functions of the tables, psi and, baked model, the
+    coarse atlas."""
+    rgb, dist = ViewRenderFunction.apply(tables, atlas, mlp, origins, dirs, renderer, with_dist)
+    return (rgb, dist) if with_dist else rgb
 
 
 def render_differentiable_baked(renderer: Renderer, tables, atlas, mlp, origins, dirs, with_dist: bool = False):

@@ -40,7 +40,7 @@ def test_view_mlp_render_parity_and_ragged_batches():
             assert err < COLOUR_TOL, (n, k, err)
 
 
-def test_view_mlp_needs_cd_and_feat_outputs_and_has_no_backward():
+def test_view_mlp_needs_cd_and_feat_outputs_and_rejects_the_fused_backward():
     import ctypes
     import torch
     from paper_2407_10482_amd._lib import NgprtError, NgprtOutputs, check
