@@ -6,7 +6,8 @@
 //          lane, the deferred MLP forward and backward give dL/dC_d, dL/dF,
 //          and per-ray outer products whose sum over the wave's 64 rays is
 //          taken on v_mfma_f32_16x16x4_f32 (K = rays) and written as one
-//          451-float partial per wave;
+//          451-float partial per wave (with the view-dependent MLP, dL/dC_d
+//          and dL/dF come per ray from its own backward instead, `ups`);
 //  pass 2  re-march again with the same decisions; at each sample
 //          dL/dsigma_i = delta (T_{i+1} s_i - (S - P_i)) with
 //          s_i = dL/dC_d . c_i + dL/dF . v_i, S = dL/dC_d . C_d + dL/dF . F and
@@ -18,7 +19,8 @@
 //          samples share cells) so one lane issues each entry's atomics;
 //          measured on 2^18-ray training batches this beats plain per-lane
 //          atomics at every level (4.3x on 8 x 2^14 tables, 1.9x on
-//          16 x 2^19).
+//          16 x 2^19).  The baked model scatters into its fine levels and
+//          coarse atlas rows instead (baked_scatter).
 // A second kernel reduces the per-wave MLP partials in a fixed order.
 #include <hip/hip_runtime.h>
 
