@@ -21,7 +21,7 @@
 //          atomics at every level (4.3x on 8 x 2^14 tables, 1.9x on
 //          16 x 2^19).  The baked model scatters into its fine levels and
 //          coarse atlas rows instead (baked_scatter).
-// A second kernel reduces the per-wave MLP partials in a fixed order.
+// The per-wave MLP partials are then added in a fixed order (reduce.h).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -29,6 +29,7 @@
 #include "device.h"
 #include "internal.h"
 #include "march.h"
+#include "reduce.h"
 
 namespace ngprt {
 
@@ -504,15 +505,6 @@ __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, c
   }
 }
 
-__global__ void reduce_partials_kernel(const float* __restrict__ partial, int64_t n_waves,
-                                       float* __restrict__ out) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= kMlpParams) return;
-  float a = 0.0f;
-  for (int64_t w = 0; w < n_waves; ++w) a += partial[w * kMlpParams + p];
-  out[p] += a;
-}
-
 __global__ void adam_kernel(int64_t n, float* __restrict__ p, const float* __restrict__ g,
                             float* __restrict__ m, float* __restrict__ v, float lr, float b1, float b2,
                             float eps, float c1, float c2) {
@@ -533,7 +525,7 @@ int launch_backward(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, c
   const int64_t blocks = (n + 255) / 256;
   if (blocks > 0x7FFFFFFF) return fail(ctx, NGPRT_E_SHAPE, "too many rays for one launch");
   const int64_t n_waves = blocks * 4;
-  const size_t need = size_t(n_waves) * kMlpParams * sizeof(float);
+  const size_t need = (size_t(n_waves) + kSumGroups) * kMlpParams * sizeof(float);
   if (need > ctx->ws_bytes) {
     if (ctx->ws) (void)hipFreeAsync(ctx->ws, st);
     ctx->ws = nullptr;
@@ -571,8 +563,7 @@ int launch_backward(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, c
 #undef NGPRT_BW
   int rc = check_launch(ctx, "backward_kernel");
   if (rc || ups) return rc;
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3(2), dim3(256), 0, st, partial, n_waves, gmlp);
-  return check_launch(ctx, "reduce_partials_kernel");
+  return launch_partial_sums(ctx, partial, n_waves, kMlpParams, partial + size_t(n_waves) * kMlpParams, gmlp, st);
 }
 
 int launch_adam(int64_t n, float* p, const float* g, float* m, float* v, int32_t step, float lr, float b1,

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
+#include "reduce.h"
 
 namespace ngprt {
 
@@ -168,7 +169,7 @@ __global__ void __launch_bounds__(256) view_mlp_kernel(int64_t n, const float* _
 // dL/dC_d = gz + (W0^T g1)[0..2], dL/dF = (W0^T g1)[3..6].  The weight
 // gradients are sums over the wave's rays of outer products, taken on
 // v_mfma_f32_16x16x4f32 with the rays as K, and written as one 5891-float
-// partial per wave; a second kernel adds the partials in a fixed order.
+// partial per wave; the partials are then added in a fixed order (reduce.h).
 constexpr int kVP = 65;                                  // LDS row pitch (bank spread)
 constexpr int kW0 = 0, kB0 = 64 * 23, kW1 = kB0 + 64, kB1 = kW1 + 64 * 64, kW2 = kB1 + 64,
               kB2 = kW2 + 3 * 64;
@@ -329,19 +330,11 @@ __global__ void __launch_bounds__(64) view_mlp_backward_kernel(int64_t n, const 
   }
 }
 
-__global__ void view_reduce_kernel(const float* __restrict__ partial, int64_t n_waves, float* __restrict__ out) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= kMlpViewParams) return;
-  float a = 0.0f;
-  for (int64_t w = 0; w < n_waves; ++w) a += partial[w * kMlpViewParams + p];
-  out[p] += a;
-}
-
 int launch_view_mlp_backward(ngprt_ctx* ctx, int64_t n, const float* d, const float* c_d, const float* feat,
                              const float* grad_rgb, float* grad_cf, float* gmlp, hipStream_t st) {
   const int64_t waves = (n + 63) / 64;
   if (waves > 0x7FFFFFFF) return fail(ctx, NGPRT_E_SHAPE, "too many rays for one launch");
-  const size_t need = size_t(waves) * kMlpViewParams * sizeof(float);
+  const size_t need = (size_t(waves) + kSumGroups) * kMlpViewParams * sizeof(float);
   if (need > ctx->ws_bytes) {
     if (ctx->ws) (void)hipFreeAsync(ctx->ws, st);
     ctx->ws = nullptr;
@@ -357,9 +350,8 @@ int launch_view_mlp_backward(ngprt_ctx* ctx, int64_t n, const float* d, const fl
                      ctx->mlp, grad_cf, partial);
   int rc = check_launch(ctx, "view_mlp_backward_kernel");
   if (rc) return rc;
-  hipLaunchKernelGGL(view_reduce_kernel, dim3((kMlpViewParams + 255) / 256), dim3(256), 0, st, partial, waves,
-                     gmlp);
-  return check_launch(ctx, "view_reduce_kernel");
+  return launch_partial_sums(ctx, partial, waves, kMlpViewParams, partial + size_t(waves) * kMlpViewParams, gmlp,
+                             st);
 }
 
 int launch_view_mlp_arrange(ngprt_ctx* ctx, const float* params, hipStream_t st) {
