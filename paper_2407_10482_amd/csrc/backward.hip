@@ -543,7 +543,17 @@ int launch_backward(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, c
   hipLaunchKernelGGL((backward_kernel<DOMV, LM, PY, MD>), g, dim3(256), 0, st, S, n, o, d, grad_rgb,   \
                      grad_dist, ups, gtab, gatlas, partial, ctx->mlp)
   if (S.model == NGPRT_MODEL_BAKED) {
-    if (S.pyr_n > 0) {
+    // L <= 2 fine levels: coarse rows of at most 12 channels, so the wave
+    // sums in the coarse scatter carry 12 values instead of 16
+    if (S.L <= 2) {
+      if (S.pyr_n > 0) {
+        if (box) NGPRT_BW(DOM_BOX, 2, true, 1);
+        else NGPRT_BW(DOM_CONTRACT, 2, true, 1);
+      } else {
+        if (box) NGPRT_BW(DOM_BOX, 2, false, 1);
+        else NGPRT_BW(DOM_CONTRACT, 2, false, 1);
+      }
+    } else if (S.pyr_n > 0) {
       if (box) NGPRT_BW(DOM_BOX, 4, true, 1);
       else NGPRT_BW(DOM_CONTRACT, 4, true, 1);
     } else {
