@@ -281,6 +281,14 @@ static void dispatch_l(const SceneArgs& S, dim3 g, hipStream_t st, int64_t n, co
         hipLaunchKernelGGL((render_kernel<DOM, DT, 4, MODE, 5>), g, dim3(256), 0, st, S, n, o, d, out, rec,
                            mlp, naive, pa);
     }
+  } else if (S.model == 1 && S.L <= 2) {
+    // at most two fine levels: coarse rows of at most 12 channels
+    if (S.pyr_n > 0)
+      hipLaunchKernelGGL((render_kernel<DOM, DT, 2, MODE, 3>), g, dim3(256), 0, st, S, n, o, d, out, rec,
+                         mlp, naive, pa);
+    else
+      hipLaunchKernelGGL((render_kernel<DOM, DT, 2, MODE, 1>), g, dim3(256), 0, st, S, n, o, d, out, rec,
+                         mlp, naive, pa);
   } else if (S.model == 1 && S.pyr_n > 0)
     hipLaunchKernelGGL((render_kernel<DOM, DT, 4, MODE, 3>), g, dim3(256), 0, st, S, n, o, d, out, rec,
                        mlp, naive, pa);
