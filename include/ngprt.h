@@ -2,12 +2,15 @@
  * ngprt.h -- C ABI of the MI355X (gfx950) NGP-RT rendering library.
  *
  * The library renders rays through a baked NGP-RT-style scene (arXiv
- * 2407.10482): it marches each ray with an occupancy grid and the occupancy
- * distance grid (Sec. 4.3, Eq. 9), looks up every level of multi-level hash
- * tables of explicit deferred features at each occupied sample (Sec. 4.1,
- * Eq. 6; Sec. 3, Eq. 3), fuses the levels with attention (Sec. 4.2,
- * Eq. 7-8, softmax form), composites front to back (Sec. 3, Eq. 2 and
- * Eq. 5) and runs one deferred MLP per ray (Eq. 5).
+ * 2407.10482): it marches each ray with an occupancy grid (or pyramid) and
+ * the occupancy distance grid (Sec. 4.3, Eq. 9), looks up every level of
+ * multi-level hash tables of explicit deferred features at each occupied
+ * sample (Sec. 4.1, Eq. 6; Sec. 3, Eq. 3), fuses the levels with attention
+ * (Sec. 4.2, Eq. 7-8: a softmax over per-entry logits, or the paper's
+ * sigmoid gates from a baked coarse grid), composites front to back
+ * (Sec. 3, Eq. 2 and Eq. 5) and runs one deferred MLP per ray (Eq. 5,
+ * optionally view-dependent).  Backward entry points give the gradients of
+ * a loss through all of it, for training.
  *
  * Conventions
  *  - Every pointer named dev_* is device memory on the current HIP device.
@@ -53,7 +56,7 @@ enum ngprt_status {
   NGPRT_E_NOT_LOADED = -4,  /* render before tables / occupancy / MLP were loaded */
   NGPRT_E_ALLOC = -5,       /* device allocation failed */
   NGPRT_E_HIP = -6,         /* a HIP runtime call or kernel launch failed */
-  NGPRT_E_UNSUPPORTED = -7  /* valid request this build does not implement */
+  NGPRT_E_UNSUPPORTED = -7  /* valid request the library does not implement */
 };
 
 enum ngprt_dtype { NGPRT_F32 = 0, NGPRT_BF16 = 1, NGPRT_FP8E4M3 = 2 };
