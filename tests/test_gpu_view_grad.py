@@ -111,3 +111,35 @@ def test_training_with_the_view_mlp_reduces_loss():
         params = [p.detach() for p in params]
     print("losses", losses[0], losses[-1], flush=True)
     assert losses[-1] < 0.5 * losses[0]
+
+
+def test_render_backward_from_features_with_regulariser_matches_oracle():
+    """The distortion regulariser (supplement Eq. S2) through the
+    feature-driven render backward, baked model on the pyramid."""
+    import torch
+    print("[render backward from features + dist] paper_tiny", flush=True)
+    sc, dist = scene_and_dist("paper_tiny")
+    cfg = sc.cfg
+    inp = inputs_from_scene(sc, dist)
+    o, d, _ = synth.scene_rays(cfg)
+    o, d = o[::8], d[::8]
+    s_ray, s_pos, _, s_k = frozen_samples(inp, o, d, with_k=True)
+    rng = np.random.default_rng(9)
+    g_cd, g_f = rng.normal(size=(len(o), 3)), rng.normal(size=(len(o), 4))
+    g_dist = np.full(len(o), 0.05)
+    coarse = dict(atlas=sc.atlas.astype(np.float64), default=sc.default.astype(np.float64),
+                  block_index=sc.block_index, res=cfg.coarse_res)
+    (ga64, gf64), _, _ = backward64(sc.tables.astype(np.float64), sc.mlp, cfg.resolutions, cfg.step, len(o),
+                                    s_ray, s_pos, None, grad_dist=g_dist, s_k=s_k, coarse=coarse,
+                                    upstream=(g_cd, g_f))
+    r = gpu_renderer("paper_tiny")
+    go, gd, gcf, gdd = to_gpu(o, d, np.concatenate([g_cd, g_f], axis=1).astype(np.float32),
+                             g_dist.astype(np.float32))
+    gt = torch.zeros((r.L, r.T, 9), device="cuda")
+    ga = torch.zeros(sc.atlas.shape, device="cuda")
+    r.backward_features(go, gd, gcf, gt, ga, gdd)
+    torch.cuda.synchronize()
+    for got, ref in ((_np(gt), gf64), (_np(ga), ga64)):
+        scale = np.abs(ref).max()
+        assert scale > 0
+        assert np.all(np.abs(got - ref) <= 1e-4 * scale + 1e-3 * np.abs(ref)), np.abs(got - ref).max() / scale
