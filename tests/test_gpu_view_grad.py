@@ -143,3 +143,22 @@ def test_render_backward_from_features_with_regulariser_matches_oracle():
         scale = np.abs(ref).max()
         assert scale > 0
         assert np.all(np.abs(got - ref) <= 1e-4 * scale + 1e-3 * np.abs(ref)), np.abs(got - ref).max() / scale
+
+
+def test_feature_backward_and_view_backward_reject_unsupported_contexts():
+    import torch
+    from paper_2407_10482_amd._lib import NgprtError
+    print("[feature backward errors]", flush=True)
+    o = torch.zeros((8, 3), device="cuda")
+    gcf = torch.zeros((8, 7), device="cuda")
+    bf = gpu_renderer("tiny_view", 1)                   # bf16 tables: no backward
+    with pytest.raises(NgprtError):
+        bf.backward_features(o, o, gcf, torch.zeros((bf.L, bf.T, 9), device="cuda"))
+    sm = gpu_renderer("baked_tiny_sum")                 # SUM aggregation: no backward
+    with pytest.raises(NgprtError):
+        sm.backward_features(o, o, gcf, torch.zeros((sm.L, sm.T, 9), device="cuda"),
+                             torch.zeros((sm.n_blocks, 8, 8, 8, 12), device="cuda"))
+    pl = gpu_renderer("tiny")                           # plain MLP: no MLP_psi backward
+    with pytest.raises(NgprtError):
+        pl.view_mlp_backward(o, o, torch.zeros((8, 4), device="cuda"), o, torch.zeros((451,), device="cuda"))
+    torch.cuda.synchronize()
