@@ -105,12 +105,6 @@ class OracleInputs:
             self.val64 = self.deq32.astype(np.float64) * self.scales.astype(np.float64)[:, None, :]
         else:
             raise ValueError("unknown table dtype")
-        # softmax shift: the largest stored logit over all levels (float32,
-        # dequantised), a scene constant
-        lg = self.deq32[:, :, 8]
-        if self.scales is not None:
-            lg = lg * self.scales[:, 8][:, None]
-        self.logit_shift = F32(np.max(lg))
         self.occ_flat = np.ascontiguousarray(self.occ, dtype=np.uint8).ravel()
         self.dist_flat = np.ascontiguousarray(self.dist, dtype=np.uint8).ravel()
 
@@ -138,19 +132,28 @@ class OracleInputs:
 def fused32(inp: OracleInputs, u: np.ndarray):
     """Float32 mirror of the lookup + attention chain at grid coordinates u.
 
-    Softmax across levels with a constant shift c (the largest stored
-    logit; the softmax is unchanged by any common shift): e_l =
-    exp32(a_l - c); levels accumulated in order, S = sum e_l,
-    fused_j = (sum e_l v_l[j]) / S, attention weights e_l / S.
+    Softmax across levels (Eq. 8, softmax reading) in one pass over the
+    levels with a running maximum (the online softmax of Milakov and
+    Gimelshein, 2018), so no level's term underflows unless it is negligible
+    against the sample's own largest logit.  Per level, in order, with a_l
+    the interpolated logit and m the running maximum (m = -inf before level
+    0):
+        d = a_l - m;  x = exp32(-|d|)
+        d > 0:  the new maximum is a_l; the sums so far scale by x, e_l = 1
+        else:   the sums keep their scale, e_l = x
+        S = S * scale + e_l;   N_j = N_j * scale + e_l * v_l[j]
+    fused_j = N_j / S; attention weights w_l = exp32(a_l - m) / S with m the
+    final maximum.  S >= 1 always (the level holding the maximum adds 1).
 
     Returns fused channels [m, 8], attention weights [m, L], corner indices
     [m, L, 8].  (Baked model: see oracle.baked.fused32.)"""
     if inp.coarse_res:
         return baked.fused32(inp, u)
     m = u.shape[0]
+    run_max = np.full(m, -np.inf, dtype=F32)
     esum = np.zeros(m, dtype=F32)
     num = np.zeros((m, 8), dtype=F32)
-    es, idxs = [], []
+    logits, idxs = [], []
     for l, N in enumerate(inp.resolutions):
         idx, w = corners32(u, N, inp.T)
         idxs.append(idx)
@@ -160,14 +163,19 @@ def fused32(inp: OracleInputs, u: np.ndarray):
             acc = acc + w[:, c:c + 1] * g[:, c, :]
         if inp.scales is not None:
             acc = inp.scales[l][None, :] * acc
-        e = exp32(acc[:, 8] - inp.logit_shift)
-        esum = esum + e
-        num = num + e[:, None] * acc[:, :8]
-        es.append(e)
-    ok = esum > 0
-    safe = np.where(ok, esum, F32(1.0))
-    fused = np.where(ok[:, None], num / safe[:, None], F32(0.0)).astype(F32)
-    wl = np.where(ok[:, None], np.stack(es, axis=1) / safe[:, None], F32(0.0)).astype(F32)
+        a = acc[:, 8]
+        with np.errstate(invalid="ignore"):
+            dlt = a - run_max
+        x = exp32(-np.abs(dlt))
+        up = dlt > F32(0.0)
+        scale = np.where(up, x, F32(1.0)).astype(F32)
+        e = np.where(up, F32(1.0), x).astype(F32)
+        run_max = np.where(up, a, run_max).astype(F32)
+        esum = esum * scale + e
+        num = num * scale[:, None] + e[:, None] * acc[:, :8]
+        logits.append(a)
+    fused = (num / esum[:, None]).astype(F32)
+    wl = np.stack([exp32(a - run_max) / esum for a in logits], axis=1).astype(F32)
     return fused, wl, np.stack(idxs, axis=1)
 
 

@@ -49,7 +49,6 @@ SceneArgs scene_args(const ngprt_ctx* ctx) {
   S.step = d.step;
   S.thr = d.t_threshold;
   S.max_samples = d.max_samples;
-  S.lshift = ctx->logit_shift;
   S.pyr_n = d.occ_levels > 0 ? d.occ_levels : 0;
   S.use_dist = d.use_distance;
   for (int j = 0; j < kMaxPyr; ++j) {

@@ -156,13 +156,15 @@ __device__ __forceinline__ void level_corners(const float u[3], int N, float Nf,
 
 // Lookup + attention at grid coordinate u, in one pass over the levels.
 // Per level: 8 corners, each gathering its feature row and logit; the
-// interpolated logit a_l gives e_l = exp32(a_l - c), where c is the scene's
-// largest stored logit (a constant: softmax is unchanged by any common shift,
-// and a_l <= c up to rounding keeps exp32 from overflowing); the levels are
-// accumulated in order: S = sum e_l, N_j = sum e_l v_l[j]; fused_j = N_j / S.
-// The density channel and S are on the decision chain (plain float32 ops);
-// the colour and specular channels use fma.  Optionally the attention
-// weights e_l / S [L] and corner indices [L][8].
+// interpolated logit a_l enters a softmax across levels (Eq. 8, softmax
+// reading) taken with a running maximum m (online softmax, Milakov and
+// Gimelshein 2018): d = a_l - m, x = exp32(-|d|); when d > 0 the sums so far
+// are scaled by x and e_l = 1 (a_l is the new maximum), else e_l = x; then
+// S = S * scale + e_l and N_j = N_j * scale + e_l v_l[j].  fused_j = N_j / S,
+// and S >= 1, so no sample's softmax underflows whatever the offset of its
+// logits.  The density channel and S are on the decision chain (plain
+// float32 ops); the colour and specular channels use fma.  Optionally the
+// attention weights exp32(a_l - m) / S [L] and corner indices [L][8].
 #ifndef NGPRT_LEVEL_UNROLL
 #define NGPRT_LEVEL_UNROLL 1
 #endif
@@ -170,7 +172,7 @@ __device__ __forceinline__ void level_corners(const float u[3], int N, float Nf,
 template <int DT, int LMAX, bool DEBUG = false>
 __device__ __forceinline__ void eval_fused(const SceneArgs& S, const float u[3], float fused[8],
                                            float* wout = nullptr, int32_t* idxout = nullptr) {
-  float esum = 0.0f, num0 = 0.0f;
+  float run_max = -__int_as_float(0x7F800000), esum = 0.0f, num0 = 0.0f;
   float num[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   // a rolled level loop: per-level constants come in by scalar loads instead
   // of being held in (and spilled from) scalar registers across the march
@@ -207,31 +209,32 @@ __device__ __forceinline__ void eval_fused(const SceneArgs& S, const float u[3],
 #pragma unroll
         for (int j = 0; j < 9; ++j) acc[j] = S.scale[l][j] * acc[j];
       }
-      const float e = exp32(acc[8] - S.lshift);
-      esum = esum + e;
-      num0 = num0 + e * acc[0];
+      const float a = acc[8];
+      const float dl = a - run_max;
+      const float x = exp32(-fabsf(dl));
+      const bool up = dl > 0.0f;
+      const float sc = up ? x : 1.0f;
+      const float e = up ? 1.0f : x;
+      run_max = up ? a : run_max;
+      esum = esum * sc + e;
+      num0 = num0 * sc + e * acc[0];
 #pragma unroll
-      for (int j = 0; j < 7; ++j) num[j] = __builtin_fmaf(e, acc[1 + j], num[j]);
+      for (int j = 0; j < 7; ++j) num[j] = __builtin_fmaf(e, acc[1 + j], num[j] * sc);
       if (DEBUG) {
-        wout[l] = e;
+        wout[l] = a;
 #pragma unroll
         for (int k = 0; k < 8; ++k) idxout[l * 8 + k] = int32_t(c.idx[k]);
       }
     }
   }
-  if (esum > 0.0f) {
-    fused[0] = num0 / esum;
-    const float inv = 1.0f / esum;
+  fused[0] = num0 / esum;
+  const float inv = 1.0f / esum;
 #pragma unroll
-    for (int j = 0; j < 7; ++j) fused[1 + j] = num[j] * inv;
-  } else {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) fused[j] = 0.0f;
-  }
+  for (int j = 0; j < 7; ++j) fused[1 + j] = num[j] * inv;
   if (DEBUG) {
 #pragma unroll
     for (int l = 0; l < LMAX; ++l)
-      if (l < S.L) wout[l] = esum > 0.0f ? wout[l] / esum : 0.0f;
+      if (l < S.L) wout[l] = exp32(wout[l] - run_max) / esum;
   }
 }
 

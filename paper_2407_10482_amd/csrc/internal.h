@@ -39,7 +39,6 @@ struct SceneArgs {
   int N[kMaxLevels];
   float Nf[kMaxLevels];
   float scale[kMaxLevels][9];     // FP8 dequantisation scales (1 otherwise)
-  float lshift;                   // largest stored (dequantised) logit: the softmax shift
   const void* feat;               // [L][T][8] storage dtype
   const void* logit;              // [L][T]    storage dtype
   const uint16_t* grid;           // [R^3]: low byte G, bit 8 = occupied
@@ -98,9 +97,8 @@ struct ngprt_ctx {
   int64_t T = 0;
   void* feat = nullptr;       // [L][T][8]
   void* logit = nullptr;      // [L][T]
-  float* scales_dev = nullptr;// [16][9] scales + 1 scratch word
+  float* scales_dev = nullptr;// [16][9] scales
   float scales_host[NGPRT_MAX_LEVELS][9];
-  float logit_shift = 0.0f;   // largest stored logit (set by load_tables)
   uint16_t* grid = nullptr;   // [R^3]
   float* mlp = nullptr;       // [451] or, view-dependent MLP, [5891]
   float* mlp_rec = nullptr;   // view-dependent MLP: weights in MFMA order [8960]

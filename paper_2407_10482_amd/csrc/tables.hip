@@ -88,57 +88,6 @@ __global__ void split_fp8_kernel(const float* __restrict__ src, uint8_t* __restr
   logit[e] = fp8_encode(s[8] / sc.s[l][8]);
 }
 
-// Largest stored logit (dequantised, float32) over all levels: the
-// constant shift of the softmax across levels.  Floats are compared through
-// an order-preserving unsigned key.
-__device__ __forceinline__ uint32_t order_key(float f) {
-  const uint32_t b = __float_as_uint(f);
-  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
-}
-
-template <int DT>
-__global__ void logit_max_kernel(const void* __restrict__ logit, int64_t T, Scales9 sc,
-                                 uint32_t* __restrict__ out) {
-  __shared__ uint32_t part;
-  const int l = int(blockIdx.y);
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (threadIdx.x == 0) part = 0;
-  __syncthreads();
-  if (i < T) {
-    float v = Store<DT>::logit(reinterpret_cast<const char*>(logit) +
-                                   (size_t(l) * size_t(T) + size_t(i)) * (Store<DT>::kRow / 8),
-                               0);
-    if (DT == DT_FP8) v = sc.s[l][8] * v;
-    if (v == v) atomicMax(&part, order_key(v));
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) atomicMax(out, part);
-}
-
-static int compute_logit_shift(ngprt_ctx* ctx, const Scales9& sc, hipStream_t st) {
-  const int L = ctx->desc.n_levels;
-  const int64_t T = ctx->T;
-  uint32_t* key = reinterpret_cast<uint32_t*>(ctx->scales_dev) + kMaxLevels * 9;  // word after the scales
-  if (hipMemsetAsync(key, 0, sizeof(uint32_t), st) != hipSuccess) return check_launch(ctx, "memset");
-  dim3 g(unsigned((T + 255) / 256), unsigned(L));
-  switch (ctx->desc.table_dtype) {
-    case DT_F32: hipLaunchKernelGGL(logit_max_kernel<DT_F32>, g, dim3(256), 0, st, ctx->logit, T, sc, key); break;
-    case DT_BF16: hipLaunchKernelGGL(logit_max_kernel<DT_BF16>, g, dim3(256), 0, st, ctx->logit, T, sc, key); break;
-    default: hipLaunchKernelGGL(logit_max_kernel<DT_FP8>, g, dim3(256), 0, st, ctx->logit, T, sc, key); break;
-  }
-  int rc = check_launch(ctx, "logit_max_kernel");
-  if (rc) return rc;
-  uint32_t k = 0;
-  if (hipMemcpyAsync(&k, key, sizeof(uint32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess)
-    return check_launch(ctx, "logit shift readback");
-  const uint32_t b = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
-  float f;
-  std::memcpy(&f, &b, 4);
-  ctx->logit_shift = (k == 0) ? 0.0f : f;
-  return NGPRT_OK;
-}
-
 template <typename Tv>
 __global__ void join_kernel(const Tv* __restrict__ feat, const Tv* __restrict__ logit, Tv* __restrict__ dst,
                             int64_t n_entries) {
@@ -159,14 +108,12 @@ int launch_load_tables(ngprt_ctx* ctx, const float* src, hipStream_t st) {
     case DT_F32: {
       hipLaunchKernelGGL(split_f32_kernel, dim3(nb), dim3(256), 0, st, src, (float*)ctx->feat,
                          (float*)ctx->logit, n);
-      int rc = check_launch(ctx, "split_f32_kernel");
-      return rc ? rc : compute_logit_shift(ctx, Scales9{}, st);
+      return check_launch(ctx, "split_f32_kernel");
     }
     case DT_BF16: {
       hipLaunchKernelGGL(split_bf16_kernel, dim3(nb), dim3(256), 0, st, src, (uint16_t*)ctx->feat,
                          (uint16_t*)ctx->logit, n);
-      int rc = check_launch(ctx, "split_bf16_kernel");
-      return rc ? rc : compute_logit_shift(ctx, Scales9{}, st);
+      return check_launch(ctx, "split_bf16_kernel");
     }
     case DT_FP8: {
       uint32_t* amax = reinterpret_cast<uint32_t*>(ctx->scales_dev);
@@ -200,8 +147,9 @@ int launch_load_tables(ngprt_ctx* ctx, const float* src, hipStream_t st) {
                          (uint8_t*)ctx->logit, T, sc);
       rc = check_launch(ctx, "split_fp8_kernel");
       if (rc) return rc;
-      // synchronises: the host copy of the scales outlives the async upload
-      return compute_logit_shift(ctx, sc, st);
+      // the host copy of the scales must outlive the async upload
+      if (hipStreamSynchronize(st) != hipSuccess) return check_launch(ctx, "scale upload");
+      return NGPRT_OK;
     }
     default:
       return fail(ctx, NGPRT_E_DTYPE, "unknown table dtype");

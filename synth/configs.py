@@ -156,6 +156,19 @@ def baked_tiny(seed: int = 0, table_dtype: int = DTYPE_F32) -> SceneConfig:
     return cfg
 
 
+def baked_tiny_levels(n_fine: int, seed: int = 0, table_dtype: int = DTYPE_F32) -> SceneConfig:
+    """baked_tiny with n_fine (1..4) fine levels 128 * 2^l (the paper doubles
+    the fine resolution per level; supplement "Multi-level Hash Features")."""
+    if not 1 <= n_fine <= 4:
+        raise ValueError("n_fine must be 1..4")
+    cfg = baked_tiny(seed, table_dtype)
+    cfg.name = f"baked_tiny_l{n_fine}"
+    cfg.n_levels = n_fine
+    cfg.resolutions = [128 << l for l in range(n_fine)]
+    cfg.n_min, cfg.n_max = cfg.resolutions[0], cfg.resolutions[-1]
+    return cfg
+
+
 def baked_hd(seed: int = 0, table_dtype: int = DTYPE_F32, n_fine: int = 2) -> SceneConfig:
     """The hd geometry with the paper's feature construction (supplement,
     "Multi-level Hash Features"): L_C = 512, fine levels 1024 * 2^l for
@@ -256,4 +269,6 @@ CONFIGS = {"paper_tiny": paper_tiny, "paper_hd": paper_hd, "tiny_view": tiny_vie
            "baked_tiny_sum": lambda **k: with_aggregation(baked_tiny(**k), "sum"),
            "baked_tiny_pyramid_shared_inv":
                lambda **k: with_aggregation(baked_tiny_pyramid(**k), "shared_inv"),
+           "baked_tiny_l3": lambda **k: baked_tiny_levels(3, **k),
+           "baked_tiny_l4": lambda **k: baked_tiny_levels(4, **k),
            "baked_hd": baked_hd, "tiny_pyramid": tiny_pyramid, "hd_pyramid": hd_pyramid}

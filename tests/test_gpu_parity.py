@@ -222,3 +222,51 @@ def test_render_hd_full_frame_sampled():
     _check_render(sub, ref)
     ns = _np(out["n_samples"])
     print(f"hd: samples/ray {ns.mean():.2f} reads/ray {_np(out['n_reads']).mean():.2f}", flush=True)
+
+
+# ---------------------------------------------------------------- extreme logits
+
+@pytest.mark.parametrize("dtype", [0, 1, 2])
+@pytest.mark.parametrize("case", ["outlier_entry", "offset"])
+def test_softmax_extreme_logits_parity(case, dtype):
+    """The softmax across levels is taken with each sample's running maximum:
+    a table with one logit entry at +100 (far above every logit a typical
+    sample interpolates) and a table whose logits all sit 300 below zero
+    render like the float64 softmax, and the decision chain stays bit-exact
+    against the oracle's float32 mirror."""
+    print(f"[softmax extreme logits {case} dtype {dtype}]", flush=True)
+    sc, dist = scene_and_dist("tiny")
+    cfg = sc.cfg
+    tab = sc.tables.copy()
+    if case == "outlier_entry":
+        tab[2, 17, 8] = 100.0
+    else:
+        tab[:, :, 8] -= 300.0
+    inp = OracleInputs(tables=tab, occ=sc.occ, dist=dist, mlp=sc.mlp, resolutions=cfg.resolutions,
+                       domain=cfg.domain, roi_half=cfg.roi_half, step=cfg.step,
+                       max_samples=cfg.max_samples, t_threshold=cfg.t_threshold, dtype=dtype)
+    r = gpu_renderer("tiny", dtype)
+    (gt,) = to_gpu(tab)
+    r.load_tables(gt)
+    rng = np.random.default_rng(21)
+    pos = rng.uniform(-1.0, 1.0, size=(2000, 3)).astype(F32)
+    (p,) = to_gpu(pos)
+    idx, fused, w = (_np(x) for x in r.eval_points(p))
+    u = grid_coords32(inp, pos)
+    f32, w32, idx32 = fused32(inp, u)
+    assert np.array_equal(idx, idx32.astype(np.int32))
+    assert np.array_equal(w.view(np.uint32), w32.view(np.uint32))
+    assert np.array_equal(fused[:, 0].view(np.uint32), f32[:, 0].view(np.uint32))
+    f64, _ = fused64(inp, u.astype(np.float64))
+    # float32 rounding of logits of magnitude |a| moves the weights by ~8 ulp(|a|)
+    tol = COLOUR_TOL if case == "outlier_entry" else 300.0 * 2.0 ** -20 * 10
+    assert np.abs(fused - f64).max() < tol
+    o, d, _ = synth.scene_rays(cfg)
+    go, gd = to_gpu(o, d)
+    out = r.render(go, gd)
+    ref = render(inp, o, d)
+    assert np.array_equal(_np(out["n_samples"]), ref.n_samples)
+    assert np.array_equal(_np(out["t_final"]).view(np.uint32), ref.t_final32.view(np.uint32))
+    if case == "outlier_entry":
+        _check_render(out, ref)
+    assert ref.n_samples.sum() > 0

@@ -104,3 +104,19 @@ def test_shared_gate_on_the_wrong_channel_is_caught():
                   "from . import baked, pyramid, quant, sh", baked=bk)
     _fails(pins_baked.test_aggregation_variants_closed_forms, bk.SHARED_V, fused64=rd.fused64,
            fused32=rd.fused32, baked=bk)
+
+
+def test_scene_constant_softmax_shift_is_caught():
+    """Shifting every sample's logits by a fixed constant instead of the
+    running maximum (the softmax is unchanged by the shift in exact
+    arithmetic, but every term underflows when the sample's logits lie far
+    below the constant)."""
+    rd = _mutated("oracle.render", "run_max = np.full(m, -np.inf, dtype=F32)",
+                  "run_max = np.full(m, F32(100.0), dtype=F32)")
+    _fails(pins.test_softmax_mirror_with_extreme_logits, "outlier_entry", fused32=rd.fused32)
+
+
+def test_unrescaled_running_sums_are_caught():
+    """A new running maximum that does not rescale the sums taken so far."""
+    rd = _mutated("oracle.render", "esum = esum * scale + e", "esum = esum + e")
+    _fails(pins.test_softmax_mirror_with_extreme_logits, "ramp", fused32=rd.fused32)

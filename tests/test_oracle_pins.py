@@ -139,13 +139,58 @@ def test_softmax_attention_properties():
     idx, w = corners64(u, 16, T)
     common = np.einsum("mc,mcd->md", w, tab4[0][idx][:, :, :8].astype(np.float64))
     assert np.allclose(fz4, common, atol=1e-12)
-    # float32 mirror (constant shift) agrees with the max-subtracted float64
-    # softmax to float32 rounding
+    # float32 mirror (running-maximum softmax) agrees with the max-subtracted
+    # float64 softmax to float32 rounding
     f32, w32, _ = fused32(inp, u.astype(F32))
     _, wref = fused64(inp, u.astype(F32).astype(np.float64))
     assert np.abs(w32 - wref).max() < 1e-6
     fz64, _ = fused64(inp, u.astype(F32).astype(np.float64))
     assert np.abs(f32 - fz64).max() < 1e-5
+
+
+@pytest.mark.parametrize("case", ["outlier_entry", "all_very_negative", "all_very_positive", "ramp"])
+def test_softmax_mirror_with_extreme_logits(case):
+    """Eq. 8's softmax is invariant to a common shift of the logits, so the
+    float32 mirror must return the softmax whatever their offset and spread:
+    one table entry far above the rest (a shift by the table's largest
+    logit would underflow every other sample's terms to 0), every logit far
+    below or above 0 (exp of the raw logits would underflow or overflow),
+    and levels whose logits differ by more than the float32 exponential's
+    range (the weights of the lower levels are then exactly 0 and the fused
+    value is the top level's own interpolated value)."""
+    rng = np.random.default_rng(11)
+    L, T = 4, 1 << 10
+    res = (16, 23, 35, 52)
+    tab = rng.normal(0, 0.5, size=(L, T, 9)).astype(F32)
+    if case == "outlier_entry":
+        tab[2, 17, 8] = 100.0
+    elif case == "all_very_negative":
+        tab[:, :, 8] -= 300.0
+    elif case == "all_very_positive":
+        tab[:, :, 8] += 200.0
+    else:
+        tab[:, :, 8] = (np.arange(L, dtype=F32) * 120.0)[:, None] + tab[:, :, 8]
+    inp = _tiny_inputs(tab, res=res)
+    u = rng.uniform(0, 1, size=(1000, 3)).astype(F32)
+    f32, w32, _ = fused32(inp, u)
+    fz64, w64 = fused64(inp, u.astype(np.float64))
+    assert np.isfinite(f32).all() and np.isfinite(w32).all()
+    # float32 interpolation rounds each logit a_l to within a few ulp of
+    # its magnitude, which moves the weights by about that much: the
+    # tolerance grows with the sample's largest |a_l| (2^-20 |a| is 8 ulp)
+    amax = np.zeros(len(u))
+    for l, N in enumerate(res):
+        idx, w = corners64(u.astype(np.float64), N, T)
+        amax = np.maximum(amax, np.abs(np.einsum("mc,mc->m", w, tab[l][idx][:, :, 8].astype(np.float64))))
+    tol = 1e-6 + 2.0 ** -20 * amax
+    assert (np.abs(w32 - w64).max(axis=1) <= tol).all()
+    assert (np.abs(f32 - fz64).max(axis=1) <= 10 * tol).all()
+    if case == "ramp":
+        # the top level dominates: its interpolated channels, in closed form
+        idx, w = corners64(u.astype(np.float64), res[-1], T)
+        top = np.einsum("mc,mcd->md", w, tab[-1][idx][:, :, :8].astype(np.float64))
+        assert np.array_equal(w32[:, :-1], np.zeros_like(w32[:, :-1]))
+        assert np.abs(f32 - top).max() < 1e-5
 
 
 # ---------------------------------------------------------------- distance grid
