@@ -36,7 +36,7 @@ from __future__ import annotations
 import numpy as np
 
 from .exact32 import F32, exp32
-from .hashgrid import corners32, corners64
+from .hashgrid import cell32, corners32, corners64
 
 BLOCK = 8
 
@@ -54,8 +54,7 @@ def _vertex_values(inp, vx, vy, vz) -> np.ndarray:
 def coarse_corners32(u: np.ndarray, Lc: int):
     """Integer corner vertices [m, 8, 3] (x, y, z) and float32 weights [m, 8]."""
     u = np.asarray(u, dtype=F32)
-    p = u * F32(Lc)
-    i0 = np.clip(np.floor(p), 0, Lc - 1).astype(np.int64)
+    i0 = cell32(u, Lc)
     f = (u.astype(np.float64) * Lc - i0).astype(F32)     # rounded once
     g = F32(1.0) - f
     v = np.empty((u.shape[0], 8, 3), dtype=np.int64)
@@ -83,9 +82,8 @@ def coarse64(inp, u: np.ndarray) -> np.ndarray:
     """Float64 trilinear interpolation of the coarse channels."""
     u = np.asarray(u, dtype=np.float64)
     Lc = inp.coarse_res
-    p = u * Lc
-    i0 = np.clip(np.floor(p), 0, Lc - 1).astype(np.int64)
-    f = p - i0
+    i0 = cell32(u, Lc)               # the cell decided in float32
+    f = u * Lc - i0
     acc = np.zeros((u.shape[0], inp.coarse_channels))
     for c in range(8):
         b = ((c >> 0) & 1, (c >> 1) & 1, (c >> 2) & 1)
@@ -186,9 +184,8 @@ def forward64_parts(atlas64, default, block_index, Lc, fine64, resolutions, u):
     u = np.asarray(u, dtype=np.float64)
     m = u.shape[0]
     T = fine64.shape[1]
-    p = u * Lc
-    i0 = np.clip(np.floor(p), 0, Lc - 1).astype(np.int64)
-    f = p - i0
+    i0 = cell32(u, Lc)               # the cell decided in float32
+    f = u * Lc - i0
     C = atlas64.shape[-1]
     co = np.zeros((m, C))
     cv, cw, cb = [], [], []

@@ -5,7 +5,8 @@ Eq. 3; Sec. 4.1 "fine-grained" hash levels holding explicit 8-D deferred
 features, supplement "Multi-level Hash Features"):
 
 * grid coordinate u = (x - lo) * inv_extent in [0, 1]^3;
-* level l of resolution N_l: p = u * N_l, i0 = clamp(floor(p), 0, N_l - 1),
+* level l of resolution N_l: p = u * N_l, i0 = clamp(floor(p), 0, N_l - 1)
+  (p rounded to float32: the cell is decided in float32 arithmetic),
   f = u * N_l - i0, corners i0 + b for b in {0,1}^3 (bit 0 -> x, 1 -> y, 2 -> z);
 * spatial hash h = (cx * 1) xor (cy * 2654435761) xor (cz * 805459861),
   each product taken modulo 2^32, then h mod T (T a power of two);
@@ -39,6 +40,19 @@ def spatial_hash_py(cx: int, cy: int, cz: int, table_size: int) -> int:
     return h % table_size
 
 
+def cell32(u: np.ndarray, N: int) -> np.ndarray:
+    """Cell index per axis as the float32 decision chain takes it:
+    i0 = clamp(floor(fl32(u N)), 0, N - 1), u rounded to float32 first.
+
+    The cell is an integer decided in floating point, so the float64 values
+    use the same one.  Where u N lies within half an ulp below an integer
+    the float32 product rounds up to it: i0 is then the cell above and the
+    fraction u N - i0 is slightly negative (by at most half an ulp of u N),
+    which the trilinear formula takes as it is."""
+    p = np.asarray(u, dtype=F32) * F32(N)
+    return np.clip(np.floor(p), 0, N - 1).astype(np.int64)
+
+
 def corners32(u: np.ndarray, N: int, table_size: int):
     """Corner indices [m, 8] and float32 trilinear weights [m, 8] of one level.
 
@@ -48,8 +62,7 @@ def corners32(u: np.ndarray, N: int, table_size: int):
     the float32 op order w = (wx * wy) * wz.
     """
     u = np.asarray(u, dtype=F32)
-    p = u * F32(N)
-    i0 = np.clip(np.floor(p), 0, N - 1).astype(np.int64)
+    i0 = cell32(u, N)
     # f = u*N - i0 rounded once (a fused multiply-add): the product of a
     # float32 and an integer below 2^20 and the difference are exact in float64
     f = (u.astype(np.float64) * N - i0).astype(F32)
@@ -65,11 +78,12 @@ def corners32(u: np.ndarray, N: int, table_size: int):
 
 
 def corners64(u: np.ndarray, N: int, table_size: int):
-    """Same as corners32 in float64 (for values)."""
+    """Same as corners32 in float64 (for values): the cell decided in
+    float32 (cell32; u holds float32 values), the fraction u N - i0 and the
+    weights in float64."""
     u = np.asarray(u, dtype=np.float64)
-    p = u * N
-    i0 = np.clip(np.floor(p), 0, N - 1).astype(np.int64)
-    f = p - i0
+    i0 = cell32(u, N)
+    f = u * N - i0
     idx = np.empty((u.shape[0], 8), dtype=np.int64)
     w = np.empty((u.shape[0], 8), dtype=np.float64)
     for c in range(8):

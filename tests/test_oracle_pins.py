@@ -86,6 +86,37 @@ def test_trilinear_reproduces_affine_field_on_injective_level():
     assert np.allclose(val, 0.3 + 0.7 * p[:, 0] - 1.1 * p[:, 1] + 0.25 * p[:, 2], atol=1e-11)
 
 
+def test_cell_decided_in_float32_below_an_integer():
+    # u N within half an ulp below an integer k: the float32 product rounds
+    # up to k, so the decided cell is k (not k - 1) with a negative fraction;
+    # the float64 values use the same cell, and the trilinear formula there
+    # equals the exact cell's value (the interpolant is continuous)
+    N, T = 1351, 1 << 19
+    found = []
+    for k in range(300, 1300):
+        u = np.nextafter(F32(k / N), F32(0.0))
+        for _ in range(4):
+            if float(u) * N < k and math.floor(float(F32(u) * F32(N))) == k:
+                found.append((k, u))
+                break
+            u = np.nextafter(u, F32(0.0))
+    assert found
+    k, ux = found[0]
+    u = np.array([[ux, F32(0.37), F32(0.61)]], dtype=F32)
+    idx32, w32 = corners32(u, N, T)
+    idx64, w64 = corners64(u, N, T)
+    assert np.array_equal(idx32, idx64)
+    f_exact = float(ux) * N - k
+    assert f_exact < 0
+    # corners 1, 3, 5, 7 (x + 1) carry the negative fraction
+    assert np.all(w64[0, 1::2] < 0) and np.all(w32[0, 1::2] <= 0)
+    assert abs(w64.sum() - 1.0) < 1e-14
+    # an affine field is reproduced in the decided cell, as in the exact one
+    c = np.array([[(k + (cc & 1)), 0, 0] for cc in range(8)], dtype=np.float64)
+    val = (w64[0] * (0.5 + 2.0 * c[:, 0])).sum()
+    assert abs(val - (0.5 + 2.0 * float(ux) * N)) < 1e-9
+
+
 # ---------------------------------------------------------------- exp32 / sums
 
 def test_exp32_accuracy_and_specials():
