@@ -310,6 +310,23 @@ int ngprt_render_backward_reg(ngprt_ctx* ctx, int64_t n_rays, const float* dev_o
                               const float* dev_dirs, const float* dev_grad_rgb, const float* dev_grad_dist,
                               float* dev_grad_tables, float* dev_grad_mlp, void* stream);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight training loops, hosts that forbid allocation): the same
+ * computation as ngprt_render_backward_reg (same arguments, conditions and
+ * results; the MLP gradient bit for bit), with its workspace in a static
+ * device array of NGPRT_NOALLOC_SCRATCH_BYTES that each GPU holds from the
+ * first ngprt_create on it until the process ends.  It allocates nothing.
+ * n_rays above NGPRT_NOALLOC_MAX_RAYS -> NGPRT_E_SHAPE (nothing enqueued).
+ * Every call on one GPU shares that array and the next call overwrites it:
+ * calls that overlap on one GPU (other streams, threads or contexts) race,
+ * so the caller serialises them.  Needs nothing cleared between calls. */
+#define NGPRT_NOALLOC_MAX_RAYS 524288
+#define NGPRT_NOALLOC_SCRATCH_BYTES 14893824 /* (MAX_RAYS / 64 + 64) * 451 floats */
+int ngprt_render_backward_noalloc(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins,
+                                  const float* dev_dirs, const float* dev_grad_rgb,
+                                  const float* dev_grad_dist, float* dev_grad_tables,
+                                  float* dev_grad_mlp, void* stream);
+
 /* ngprt_render_backward_reg for the baked feature model (Sec. 4.1 Eq. 6,
  * Sec. 4.2 Eq. 7-8): f = f~ + [sum_l g(omega_l) sigma^_l, sum_l g(beta_l)
  * c^_l, sum_l g(beta_l) v^_l], g the sigmoid.  Accumulates (+=)

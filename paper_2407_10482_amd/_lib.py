@@ -9,6 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libngprt.so")
 
 MAX_LEVELS = 16
+NOALLOC_MAX_RAYS = 524288        # NGPRT_NOALLOC_MAX_RAYS
 NGPRT_OK = 0
 STATUS = {0: "NGPRT_OK", -1: "NGPRT_E_INVALID_ARG", -2: "NGPRT_E_SHAPE", -3: "NGPRT_E_DTYPE",
           -4: "NGPRT_E_NOT_LOADED", -5: "NGPRT_E_ALLOC", -6: "NGPRT_E_HIP", -7: "NGPRT_E_UNSUPPORTED"}
@@ -73,6 +74,7 @@ SIGNATURES = [
                                              ctypes.POINTER(NgprtOutputs), _P, _P]),
     ("ngprt_render_backward", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P]),
     ("ngprt_render_backward_reg", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P]),
+    ("ngprt_render_backward_noalloc", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P]),
     ("ngprt_render_backward_baked", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P]),
     ("ngprt_view_mlp_backward", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P]),
     ("ngprt_render_backward_features", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P]),

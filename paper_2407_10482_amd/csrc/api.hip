@@ -225,6 +225,10 @@ int ngprt_create(const ngprt_desc* desc, ngprt_ctx** out) {
     ngprt_destroy(ctx);
     return NGPRT_E_ALLOC;
   }
+  // this device's copy of the allocation-free backward's static scratch; a
+  // failure here only disables ngprt_render_backward_noalloc (which reports it)
+  (void)init_static_scratch(ctx);
+  ctx->last_error.clear();
   *out = ctx;
   return NGPRT_OK;
 }
@@ -349,6 +353,27 @@ static int check_ready(ngprt_ctx* ctx) {
   return NGPRT_OK;
 }
 
+}  // extern "C"
+
+namespace ngprt {
+// Host checks shared by the hash-model render backward entry points.
+int check_backward_args(ngprt_ctx* ctx, const float* o, const float* d, const float* grad_rgb,
+                        const float* grad_tables, const float* grad_mlp) {
+  if (!o || !d || !grad_rgb || !grad_tables || !grad_mlp) return fail(ctx, NGPRT_E_INVALID_ARG, "NULL pointer");
+  if (ctx->desc.table_dtype != NGPRT_F32) return fail(ctx, NGPRT_E_DTYPE, "backward needs float32 tables");
+  if (ctx->desc.feature_model != NGPRT_MODEL_HASH)
+    return fail(ctx, NGPRT_E_UNSUPPORTED, "backward supports the hash feature model only");
+  if (is_view_mlp(&ctx->desc))
+    return fail(ctx, NGPRT_E_UNSUPPORTED, "backward supports the 7-16-16-3 deferred MLP only");
+  int rc = check_ready(ctx);
+  if (rc) return rc;
+  if (!ctx->mlp_loaded) return fail(ctx, NGPRT_E_NOT_LOADED, "mlp not loaded");
+  return NGPRT_OK;
+}
+}  // namespace ngprt
+
+extern "C" {
+
 int ngprt_render(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins, const float* dev_dirs,
                  const ngprt_outputs* out, void* stream) {
   if (!ctx) return NGPRT_E_INVALID_ARG;
@@ -431,17 +456,8 @@ int ngprt_render_backward_reg(ngprt_ctx* ctx, int64_t n_rays, const float* dev_o
   if (!ctx) return NGPRT_E_INVALID_ARG;
   if (n_rays < 0) return fail(ctx, NGPRT_E_INVALID_ARG, "n_rays < 0");
   if (n_rays == 0) return NGPRT_OK;
-  if (!dev_origins || !dev_dirs || !dev_grad_rgb || !dev_grad_tables || !dev_grad_mlp)
-    return fail(ctx, NGPRT_E_INVALID_ARG, "NULL pointer");
-  if (ctx->desc.table_dtype != NGPRT_F32)
-    return fail(ctx, NGPRT_E_DTYPE, "backward needs float32 tables");
-  if (ctx->desc.feature_model != NGPRT_MODEL_HASH)
-    return fail(ctx, NGPRT_E_UNSUPPORTED, "backward supports the hash feature model only");
-  if (is_view_mlp(&ctx->desc))
-    return fail(ctx, NGPRT_E_UNSUPPORTED, "backward supports the 7-16-16-3 deferred MLP only");
-  int rc = check_ready(ctx);
+  int rc = check_backward_args(ctx, dev_origins, dev_dirs, dev_grad_rgb, dev_grad_tables, dev_grad_mlp);
   if (rc) return rc;
-  if (!ctx->mlp_loaded) return fail(ctx, NGPRT_E_NOT_LOADED, "mlp not loaded");
   return launch_backward(ctx, n_rays, dev_origins, dev_dirs, dev_grad_rgb, dev_grad_dist, nullptr,
                          dev_grad_tables, nullptr, dev_grad_mlp, (hipStream_t)stream);
 }

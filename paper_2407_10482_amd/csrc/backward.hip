@@ -518,14 +518,16 @@ __global__ void adam_kernel(int64_t n, float* __restrict__ p, const float* __res
   p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
 }
 
+size_t backward_workspace_bytes(int64_t n) {
+  const int64_t n_waves = (n + 255) / 256 * 4;
+  return (size_t(n_waves) + kSumGroups) * kMlpParams * sizeof(float);
+}
+
 int launch_backward(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const float* grad_rgb,
                     const float* grad_dist, const float* ups, float* gtab, float* gatlas, float* gmlp,
                     hipStream_t st) {
-  SceneArgs S = scene_args(ctx);
-  const int64_t blocks = (n + 255) / 256;
-  if (blocks > 0x7FFFFFFF) return fail(ctx, NGPRT_E_SHAPE, "too many rays for one launch");
-  const int64_t n_waves = blocks * 4;
-  const size_t need = (size_t(n_waves) + kSumGroups) * kMlpParams * sizeof(float);
+  if ((n + 255) / 256 > 0x7FFFFFFF) return fail(ctx, NGPRT_E_SHAPE, "too many rays for one launch");
+  const size_t need = backward_workspace_bytes(n);
   if (need > ctx->ws_bytes) {
     if (ctx->ws) (void)hipFreeAsync(ctx->ws, st);
     ctx->ws = nullptr;
@@ -536,7 +538,17 @@ int launch_backward(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, c
     }
     ctx->ws_bytes = need;
   }
-  float* partial = reinterpret_cast<float*>(ctx->ws);
+  return launch_backward_ws(ctx, n, o, d, grad_rgb, grad_dist, ups, gtab, gatlas, gmlp,
+                            reinterpret_cast<float*>(ctx->ws), st);
+}
+
+int launch_backward_ws(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const float* grad_rgb,
+                       const float* grad_dist, const float* ups, float* gtab, float* gatlas, float* gmlp,
+                       float* partial, hipStream_t st) {
+  SceneArgs S = scene_args(ctx);
+  const int64_t blocks = (n + 255) / 256;
+  if (blocks > 0x7FFFFFFF) return fail(ctx, NGPRT_E_SHAPE, "too many rays for one launch");
+  const int64_t n_waves = blocks * 4;
   dim3 g = dim3(unsigned(blocks));
   const bool box = ctx->desc.domain == DOM_BOX;
 #define NGPRT_BW(DOMV, LM, PY, MD)                                                                 \

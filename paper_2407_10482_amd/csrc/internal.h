@@ -138,6 +138,15 @@ int launch_march(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, int3
 int launch_backward(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const float* grad_rgb,
                     const float* grad_dist, const float* ups, float* gtab, float* gatlas, float* gmlp,
                     hipStream_t s);
+// workspace of launch_backward_ws: one MLP-gradient partial per wave of 64
+// rays plus kSumGroups group sums, every element written before it is read
+size_t backward_workspace_bytes(int64_t n);
+int launch_backward_ws(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const float* grad_rgb,
+                       const float* grad_dist, const float* ups, float* gtab, float* gatlas, float* gmlp,
+                       float* workspace, hipStream_t s);
+int init_static_scratch(ngprt_ctx* ctx);
+int check_backward_args(ngprt_ctx* ctx, const float* o, const float* d, const float* grad_rgb,
+                        const float* grad_tables, const float* grad_mlp);
 int launch_view_mlp_backward(ngprt_ctx* ctx, int64_t n, const float* d, const float* c_d, const float* feat,
                              const float* grad_rgb, float* grad_cf, float* gmlp, hipStream_t s);
 int launch_view_mlp_arrange(ngprt_ctx* ctx, const float* params, hipStream_t s);

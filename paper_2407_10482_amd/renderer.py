@@ -253,6 +253,20 @@ def _renderer_backward(self: Renderer, origins, dirs, grad_rgb, grad_tables, gra
           self.ctx)
 
 
+def _renderer_backward_noalloc(self: Renderer, origins, dirs, grad_rgb, grad_tables, grad_mlp, grad_dist=None):
+    """_renderer_backward through the allocation-free entry point (workspace
+    in the library's static device scratch; at most NOALLOC_MAX_RAYS rays)."""
+    n = origins.shape[0]
+    _dev(grad_rgb, torch.float32, (n, 3), "grad_rgb")
+    _dev(grad_tables, torch.float32, (self.L, self.T, 9), "grad_tables")
+    _dev(grad_mlp, torch.float32, (self.n_mlp,), "grad_mlp")
+    if grad_dist is not None:
+        _dev(grad_dist, torch.float32, (n,), "grad_dist")
+    check(self.lib.ngprt_render_backward_noalloc(self.ctx, n, _ptr(origins), _ptr(dirs), _ptr(grad_rgb),
+                                                 _ptr(grad_dist), _ptr(grad_tables), _ptr(grad_mlp),
+                                                 _stream()), self.ctx)
+
+
 def _renderer_backward_baked(self: Renderer, origins, dirs, grad_rgb, grad_tables, grad_atlas, grad_mlp,
                              grad_dist=None):
     """Baked model: accumulate dL/d(fine tables) [L, T, 9] (channel 8 not
@@ -310,6 +324,7 @@ def _renderer_set_step(self: Renderer, step: float):
 
 
 Renderer.backward = _renderer_backward
+Renderer.backward_noalloc = _renderer_backward_noalloc
 Renderer.backward_baked = _renderer_backward_baked
 Renderer.view_mlp_backward = _renderer_view_mlp_backward
 Renderer.backward_features = _renderer_backward_features
