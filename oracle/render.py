@@ -255,13 +255,15 @@ class RenderResult:
 
 
 def march(inp: OracleInputs, o: np.ndarray, d: np.ndarray, naive: bool = False,
-          terminate: bool = True, intervals=None):
+          terminate: bool = True, intervals=None, hi_guard: float = 0.0):
     """March all rays in lock-step over the lattice index k.
 
     intervals: optional float32 [n, 2] (t_lo, t_hi) restricting a ray to the
     lattice points with t in [t_lo, t_hi] (NaN rows: no restriction).  Box
     scenes start at lattice index max(0, floor((t_lo - t0) / step)); in the
     contracted domain points with t < t_lo are visited without a read.
+    hi_guard > 0: a ray that reaches t > t_hi holding samples whose float32
+    transmittance is not below hi_guard drops its t_hi and marches on.
 
     Returns per-ray sample lists and counts; transmittance decisions in the
     float32 mirror."""
@@ -311,6 +313,9 @@ def march(inp: OracleInputs, o: np.ndarray, d: np.ndarray, naive: bool = False,
         ids = np.nonzero(alive)[0]
         if inp.domain == BOX:
             tk = t0[ids] + F32(k) * step
+            if hi_guard > 0:
+                go_on = (tk > t_hi[ids]) & (nsamp[ids] > 0) & ~(T[ids] < F32(hi_guard))
+                t_hi[ids[go_on]] = np.inf
             at_hi = (tk < t1[ids]) & (tk > t_hi[ids])
             stopped_hi[ids[at_hi]] = True
             inside = (tk < t1[ids]) & ~(tk > t_hi[ids])
@@ -325,6 +330,9 @@ def march(inp: OracleInputs, o: np.ndarray, d: np.ndarray, naive: bool = False,
                 need = k >= next_read[ids]
         else:
             tk = t[ids]
+            if hi_guard > 0:
+                go_on = (tk > t_hi[ids]) & (nsamp[ids] > 0) & ~(T[ids] < F32(hi_guard))
+                t_hi[ids[go_on]] = np.inf
             at_hi = tk > t_hi[ids]               # checked before the exit test
             stopped_hi[ids[at_hi]] = True
             alive[ids[at_hi]] = False
@@ -553,24 +561,28 @@ def valid_rays(inp: OracleInputs, o, d):
     return np.isfinite(o).all(axis=1) & np.isfinite(d).all(axis=1) & (dn2 > 0)
 
 
-def render_proposal(inp: OracleInputs, o, d, proposal, conf_threshold=0.9, margin=0.0):
-    """Render with a per-ray proposal [t_near, t_far, t_term, conf]: a
-    confident ray ends its march after t_far + margin; one with no sample by
-    then carries on, which is exactly the plain march.  Returns the result
-    and the fallback mask."""
+def render_proposal(inp: OracleInputs, o, d, proposal, conf_threshold=0.9, margin=0.0, use_near=True,
+                    far_guard=0.0):
+    """Render with a per-ray proposal [t_near, t_far, t_term, conf] (an
+    extension).  A ray with conf >= conf_threshold marches only the lattice
+    points with t in [t_near - margin, t_far + margin] (use_near false: from
+    its start); with far_guard > 0 the far end stops a ray only once its
+    transmittance is below far_guard, else the ray marches on.  If the padded
+    interval holds no occupied lattice point the ray marches again from its
+    start as the plain march (its samples are then the plain march's, its
+    read count the sum of both marches).  Other rays march plainly.  Returns
+    the result and the fallback mask."""
     o = np.asarray(o, F32)
     d = np.asarray(d, F32)
     n = len(o)
     prop = np.asarray(proposal, F32)
     conf = prop[:, 3] >= F32(conf_threshold)
     iv = np.full((n, 2), np.nan, F32)
-    iv[conf, 0] = -np.inf
+    iv[conf, 0] = prop[conf, 0] - F32(margin) if use_near else -np.inf
     iv[conf, 1] = prop[conf, 1] + F32(margin)
-    m = march(inp, o, d, intervals=iv)
+    m = march(inp, o, d, intervals=iv, hi_guard=far_guard)
     plain = march(inp, o, d)
-    # a confident ray stopped at its proposed end without a sample resumes
-    # there, which makes it the plain march
-    fb = conf & (m["n_samples"] == 0) & m["stopped_hi"]
+    fb = conf & (m["n_samples"] == 0)
     if fb.any():
         idx = np.nonzero(fb)[0]
         keep = ~np.isin(m["s_ray"], idx)
@@ -580,7 +592,8 @@ def render_proposal(inp: OracleInputs, o, d, proposal, conf_threshold=0.9, margi
         order = np.lexsort((m["s_k"], m["s_ray"]))
         for key in ("s_ray", "s_k", "s_t", "s_pos", "s_T"):
             m[key] = m[key][order]
-        for key in ("n_samples", "n_reads", "t_final32"):
+        m["n_reads"][idx] = m["n_reads"][idx] + plain["n_reads"][idx]
+        for key in ("n_samples", "t_final32"):
             m[key][idx] = plain[key][idx]
     if len(m["s_ray"]):
         fz, _ = fused64(inp, grid_coords32(inp, m["s_pos"]).astype(np.float64))

@@ -111,3 +111,52 @@ def test_interval_march_with_exact_labels_equals_plain():
     assert (res3.n_samples <= ref.n_samples).all() and (res3.n_samples < ref.n_samples).any()
     assert np.abs(res3.c_d - ref.c_d).max() <= 1.05e-3 * np.abs(ref.c_d).max() + 1e-12
     assert np.all((res3.t_final <= 1e-3 + 1e-9) | (res3.n_samples == ref.n_samples))
+
+
+def test_interval_render_is_a_filter_of_the_exhaustive_march():
+    """With both ends used, a proposed ray's samples are the occupied lattice
+    points of the exhaustive (naive, no termination) march whose t lies in
+    [t_near - m, t_far + m], in order, cut where its own transmittance
+    crosses the threshold; a ray whose padded interval holds none of them
+    is the plain march, with the reads of both marches counted."""
+    import synth
+    from oracle.distgrid import distance_grid_edt
+    from oracle.render import inputs_from_scene, march, ray_box32, render, render_proposal
+    cfg = synth.tiny()
+    sc = synth.make_scene(cfg)
+    inp = inputs_from_scene(sc, distance_grid_edt(sc.occ))
+    o, d, _ = synth.scene_rays(cfg)
+    o, d = o[::11], d[::11]
+    n = len(o)
+    rng = np.random.default_rng(8)
+    lo = rng.uniform(0.0, 0.4, n).astype(np.float32)
+    hi = (lo + rng.uniform(0.0, 0.3, n)).astype(np.float32)
+    margin = np.float32(2.0 / 256.0)
+    prop = np.stack([lo, hi, lo, rng.uniform(0, 1, n)], axis=1).astype(np.float32)
+    res, fb = render_proposal(inp, o, d, prop, 0.5, float(margin))
+    plain = render(inp, o, d)
+    full = march(inp, o, d, naive=True, terminate=False)
+    t0, _, _ = ray_box32(o, d, inp.roi_half)
+    conf = prop[:, 3] >= np.float32(0.5)
+    assert fb.any() and (conf & ~fb).any() and (~conf).any()
+    for i in range(n):
+        got = res.s_k[res.s_ray == i]
+        if not conf[i] or fb[i]:
+            assert np.array_equal(got, plain.s_k[plain.s_ray == i])
+            extra = 0
+            if fb[i]:
+                iv = np.array([[prop[i, 0] - margin, prop[i, 1] + margin]], np.float32)
+                extra = march(inp, o[i:i + 1], d[i:i + 1], intervals=iv)["n_reads"][0]
+                assert march(inp, o[i:i + 1], d[i:i + 1], intervals=iv)["n_samples"][0] == 0
+            assert res.n_reads[i] == plain.n_reads[i] + extra
+            continue
+        sel = full["s_ray"] == i
+        t, k = full["s_t"][sel], full["s_k"][sel]
+        # box lattice: the march starts at the lattice point at or before t_near - m
+        kstart = np.floor((np.float32(prop[i, 0] - margin) - t0[i]) / np.float32(inp.step))
+        keep = (k >= max(kstart, 0)) & (t <= prop[i, 1] + margin)
+        want = k[keep]
+        assert len(got) >= 1
+        assert np.array_equal(got, want[:len(got)])
+        # cut short only by termination
+        assert len(got) == len(want) or res.t_final32[i] < np.float32(inp.t_threshold)
