@@ -37,8 +37,8 @@ AGG_NAME = {"separate_v": "sigmoid-gated separate attention (Separate-Att (V))",
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=10)
-    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--steps", type=int, default=100)
+    p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--dtype", choices=["f32", "bf16", "fp8"], default="f32")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="approximate CPU time for the oracle baseline (0 skips it)")
@@ -70,6 +70,8 @@ def parse():
                         "proposal: learned sample-interval proposal vs plain marching")
     p.add_argument("--train-size", choices=["tiny", "train_large"], default="tiny")
     p.add_argument("--prop-epochs", type=int, default=12)
+    p.add_argument("--prop-steps", type=int, default=20,
+                   help="timed renders per side of the plain-vs-proposal comparison (0 skips it)")
     return p.parse_args()
 
 
@@ -169,13 +171,23 @@ def bench_train(args):
     }
 
 
-CONF = 0.99      # proposal confidence needed to stop a ray at its predicted far end
+# proposal settings of the comparison: rays with confidence >= 0.99 stop at
+# t_far + 2 steps, and only once their transmittance is below 1e-3 (the near
+# end is not used: at this scale its misses cost up to 10 dB)
+CONF = 0.99
+MARGIN_STEPS = 2
+USE_NEAR = False
+FAR_GUARD = 1e-3
 
 
-def bench_proposal(args):
-    """Train the proposal network on 2^22 labelled rays (1024 cameras x 64^2
-    of the tiny scene, labels from the plain renderer), then render 8 unseen
-    1920x1080 views plainly and with the proposal."""
+def proposal_comparison(steps: int, warmup: int, epochs: int):
+    """Plain distance-grid marching against the learned sample-interval
+    proposal on the same GPU: train the proposal network on 2^22 rays of the
+    tiny scene (1024 cameras x 64^2, labels from the plain renderer), load it
+    into the library, then render 8 unseen 1920x1080 views both ways (the
+    network runs inside the render kernel).  The quality bar is the PSNR of
+    each render against a reference rendered at a quarter of the step
+    without termination (by the same GPU renderer), on every 16th ray."""
     import torch
 
     import synth
@@ -187,7 +199,6 @@ def bench_proposal(args):
     r = Renderer.from_config(cfg)
     r.load_scene(torch.from_numpy(sc.tables).cuda(), torch.from_numpy(sc.occ).cuda(),
                  torch.from_numpy(sc.mlp).cuda())
-    # labels from the plain renderer
     tcams = synth.random_sphere_cameras(1024, 1.0, seed=1000)
     to, td, _ = synth.scene_rays(cfg, cams=tcams, width=64, height=64)
     to, td = torch.from_numpy(to).cuda(), torch.from_numpy(td).cuda()
@@ -198,77 +209,128 @@ def bench_proposal(args):
     n = len(to)
     bs = 1 << 14
     g = torch.Generator(device="cuda").manual_seed(0)
-    t0 = time.time()
-    margin = 4.0 * cfg.step
+    margin = MARGIN_STEPS * cfg.step
     loss = torch.zeros((1,), dtype=torch.float32, device="cuda")
     history = []
-    for ep in range(args.prop_epochs):
-        phase = 1 if ep < args.prop_epochs // 2 else 2
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for ep in range(epochs):
+        phase = 1 if ep < epochs // 2 else 2
         lr = 3e-3 if phase == 1 else 1e-3
         perm = torch.randperm(n, generator=g, device="cuda")
         loss.zero_()
         for b in range(0, n, bs):
             idx = perm[b:b + bs]
             net.train_step(to[idx].contiguous(), td[idx].contiguous(), labels[idx].contiguous(), lr,
-                           phase=phase, margin=margin, loss=loss)
+                           phase=phase, margin=4.0 * cfg.step, loss=loss)
         history.append(round(loss.item() / (n // bs), 6))
     torch.cuda.synchronize()
     train_s = time.time() - t0
-    # unseen views
+    r.load_proposal(net.params)
     ecams = synth.random_sphere_cameras(8, 1.0, seed=2000)
     eo, ed, _ = synth.scene_rays(cfg, cams=ecams, width=1920, height=1080)
     eo, ed = torch.from_numpy(eo).cuda(), torch.from_numpy(ed).cuda()
     ne = len(eo)
     plain = r.render(eo, ed)
-    prop = net.infer(eo, ed)
-    withp = r.render_proposal(eo, ed, prop, CONF, margin)
+    withp = r.render_proposal(eo, ed, CONF, margin, use_near=USE_NEAR, far_guard=FAR_GUARD)
     torch.cuda.synchronize()
-    mse = torch.mean((withp["rgb"] - plain["rgb"]) ** 2).item()
-    psnr = float("inf") if mse == 0 else 10 * np.log10(1.0 / mse)
 
     def timed(fn):
         outp = {"rgb": torch.empty((ne, 3), dtype=torch.float32, device="cuda")}
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             fn(outp)
         torch.cuda.synchronize()
-        s0, s1 = _events()
-        s0.record()
-        for _ in range(args.steps):
+        a, b = _events()
+        a.record()
+        for _ in range(steps):
             fn(outp)
-        s1.record()
+        b.record()
         torch.cuda.synchronize()
-        return s0.elapsed_time(s1) / args.steps
+        return a.elapsed_time(b) / steps
 
+    # the bound on any proposal: a perfect one, the plain render's own labels
+    # of these rays (first sample .. the sample after which T < 1e-3), margin 0
+    lab = r.render(eo, ed, out=r.alloc_outputs(ne, labels=True))
+    perfect = torch.stack([lab["t_first"], lab["t_far"], lab["t_half"],
+                           (lab["n_samples"] > 0).float()], dim=1).contiguous()
+    del lab
+    best = r.render_intervals(eo, ed, perfect, 0.5, 0.0)
     ms_plain = timed(lambda outp: r.render(eo, ed, out=outp))
-    ms_prop = timed(lambda outp: r.render_proposal(eo, ed, net.infer(eo, ed), CONF, margin, out=outp))
-    pbuf = torch.empty((ne, 4), dtype=torch.float32, device="cuda")
-    ms_infer = timed(lambda outp: net.infer(eo, ed, out=pbuf))
-    ms_render_only = timed(lambda outp: r.render_proposal(eo, ed, prop, CONF, margin, out=outp))
+    ms_prop = timed(lambda outp: r.render_proposal(eo, ed, CONF, margin, out=outp, use_near=USE_NEAR,
+                                                   far_guard=FAR_GUARD))
+    # the perfect proposal is the plain render terminated at T < 1e-3
+    r3 = Renderer(resolutions=cfg.resolutions, log2_table_size=cfg.log2_table, table_dtype=0, domain=cfg.domain,
+                  roi_half=cfg.roi_half, occ_res=cfg.occ_res, step=cfg.step, max_samples=cfg.max_samples,
+                  t_threshold=1e-3)
+    r3.load_scene(torch.from_numpy(sc.tables).cuda(), torch.from_numpy(sc.occ).cuda(),
+                  torch.from_numpy(sc.mlp).cuda())
+    term3 = r3.render(eo, ed)
+    ms_term3 = timed(lambda outp: r3.render(eo, ed, out=outp))
+    ms_best = timed(lambda outp: r.render_intervals(eo, ed, perfect, 0.5, 0.0, out=outp))
+    # quality: both renders against a quarter-step reference without termination
+    sub = slice(0, ne, 16)
+    fine = Renderer(resolutions=cfg.resolutions, log2_table_size=cfg.log2_table, table_dtype=0,
+                    domain=cfg.domain, roi_half=cfg.roi_half, occ_res=cfg.occ_res, step=cfg.step / 4,
+                    max_samples=1 << 15, t_threshold=0.0)
+    fine.load_scene(torch.from_numpy(sc.tables).cuda(), torch.from_numpy(sc.occ).cuda(),
+                    torch.from_numpy(sc.mlp).cuda())
+    ref = fine.render(eo[sub].contiguous(), ed[sub].contiguous(), aux=False)["rgb"].double()
+    torch.cuda.synchronize()
+
+    def psnr(x, y):
+        mse = torch.mean((x.double() - y) ** 2).item()
+        return float("inf") if mse == 0 else 10 * np.log10(1.0 / mse)
+
+    p_plain, p_prop = psnr(plain["rgb"][sub], ref), psnr(withp["rgb"][sub], ref)
+    p_best = psnr(best["rgb"][sub], ref)
+    p_term3 = psnr(term3["rgb"][sub], ref)
     views = 8
+
+    def side(ms, out):
+        ns = int(out["n_samples"].sum().item())
+        nr = int(out["n_reads"].sum().item())
+        return {"fps": round(views / (ms / 1e3), 3), "ms": round(ms, 4),
+                "msamples_per_s": round(ns / (ms / 1e3) / 1e6, 1),
+                "samples_per_ray": round(ns / ne, 3), "reads_per_ray": round(nr / ne, 3)}
+
     return {
-        "metric": "1080p frames/s, learned proposal vs plain distance-grid marching",
-        "value": round(views / (ms_prop / 1e3), 3),
-        "unit": "frames/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_prop, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16",
-        "data": "synthetic",
-        "config": {"workload": "tiny scene, proposal trained on 2^22 rays (1024 cameras x 64^2), "
-                               "evaluated on 8 unseen 1920x1080 views; conf >= 0.99, margin 4 steps",
-                   "rays_per_step": ne},
-        "plain_fps": round(views / (ms_plain / 1e3), 3),
-        "plain_ms": round(ms_plain, 4),
+        "workload": "tiny scene (8 levels 16..256, 2^14 entries, box ROI, 64^3 grid); proposal "
+                    "48-64-64-4 trained on 2^22 rays (1024 cameras x 64^2, labels from the plain "
+                    f"renderer, {epochs} epochs); 8 unseen 1920x1080 views; conf >= {CONF}, margin "
+                    f"{MARGIN_STEPS} steps, near end {'used' if USE_NEAR else 'not used'}, far end cut only "
+                    f"below T = {FAR_GUARD}; network run inside the render kernel",
+        "plain": side(ms_plain, plain),
+        "proposal": side(ms_prop, withp),
         "speedup": round(ms_plain / ms_prop, 4),
-        "ms_infer": round(ms_infer, 4),
-        "ms_render_with_proposal": round(ms_render_only, 4),
-        "samples_per_ray": {"plain": round(plain["n_samples"].float().mean().item(), 3),
-                            "proposal": round(withp["n_samples"].float().mean().item(), 3)},
-        "reads_per_ray": {"plain": round(plain["n_reads"].float().mean().item(), 3),
-                          "proposal": round(withp["n_reads"].float().mean().item(), 3)},
+        "perfect_proposal_bound": dict(side(ms_best, best), speedup=round(ms_plain / ms_best, 4),
+                                       psnr_loss_db=round(p_plain - p_best, 4)),
+        "plain_terminated_at_1e-3": dict(side(ms_term3, term3), speedup=round(ms_plain / ms_term3, 4),
+                                         psnr_loss_db=round(p_plain - p_term3, 4),
+                                         same_samples_as_perfect=bool(torch.equal(term3["n_samples"],
+                                                                                  best["n_samples"]))),
+        "psnr_vs_reference_db": {"plain": round(p_plain, 3), "proposal": round(p_prop, 3)},
+        "psnr_loss_db": round(p_plain - p_prop, 4),
+        "psnr_proposal_vs_plain_db": round(psnr(withp["rgb"], plain["rgb"].double()), 3),
+        "confident_fraction": round((withp["proposal"][:, 3] >= CONF).float().mean().item(), 4),
         "fallback_fraction": round(withp["fallback"].float().mean().item(), 4),
-        "confident_fraction": round((prop[:, 3] >= CONF).float().mean().item(), 4),
-        "psnr_proposal_vs_plain_db": round(psnr, 3),
         "train_seconds": round(train_s, 1),
         "train_loss_per_epoch": history,
+    }
+
+
+def bench_proposal(args):
+    """The plain-vs-proposal comparison as its own line (metric: frames/s of
+    the proposal render)."""
+    c = proposal_comparison(args.steps, args.warmup, args.prop_epochs)
+    return {
+        "metric": "1080p frames/s, learned proposal vs plain distance-grid marching",
+        "value": c["proposal"]["fps"],
+        "unit": "frames/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": c["proposal"]["ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16",
+        "data": "synthetic",
+        "config": {"workload": c["workload"], "rays_per_step": 8 * 1920 * 1080},
+        "proposal_comparison": c,
     }
 
 
@@ -338,9 +400,13 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def committed_traffic(dtype_name: str):
-    """HBM bytes per render launch from the committed counter summary, or None
-    when it is missing or was taken on other kernel sources."""
+VALU_PEAK_G = 256 * 4 * 2.4 / 4     # wave64 VALU instructions per ns: 256 CUs x 4 SIMDs x 2.4 GHz,
+                                   # one wave64 instruction per 4 cycles on a 16-lane SIMD
+
+
+def committed_counters(dtype_name: str):
+    """Per-launch hardware counters of the render kernel from the committed
+    summary, or None when it is missing or was taken on other kernel sources."""
     path = os.path.join(ROOT, "profiles", f"render_kernel_hd_{dtype_name}_counters.md")
     if not os.path.exists(path):
         return None
@@ -352,10 +418,15 @@ def committed_traffic(dtype_name: str):
                 vals[k.strip()] = v.strip().strip("`")
     if vals.get("kernel sources sha256/16") != kernel_source_hash():
         return None
-    try:
-        return int(vals["HBM bytes per launch"])
-    except (KeyError, ValueError):
-        return None
+    out = {}
+    for key, name in (("HBM bytes per launch", "hbm_bytes"), ("VALU instructions per launch", "valu"),
+                      ("L2 requests per launch", "l2_req"), ("L2 hits per launch", "l2_hit"),
+                      ("vector memory reads per launch", "vmem_rd")):
+        try:
+            out[name] = int(vals[key].replace(",", ""))
+        except (KeyError, ValueError):
+            out[name] = None
+    return out
 
 
 def gather_probe(r, n_points: int, reps: int, pairs: bool) -> float:
@@ -473,8 +544,49 @@ def main():
         per_sample = L * 8 * BYTES_PER_ENTRY[dtype]
     gather = n_samples * per_sample
     alg_bytes = gather + 2 * n_reads + n * (24 + 12)
-    achieved = alg_bytes / (ms / 1e3) / 1e9
-    traffic = None if (baked or pyr or args.mlp == "view") else committed_traffic(DTYPE_NAME[dtype])
+    sec = ms / 1e3
+    ctr = None if (baked or pyr or args.mlp == "view") else committed_counters(DTYPE_NAME[dtype])
+    levels = {
+        # what the method asks for: every corner row of every level of every
+        # sample; most of it is served by the L1 and L2 caches, so this is no
+        # fraction of any one peak
+        "requested_gather": {"achieved_gbs": round(alg_bytes / sec / 1e9, 1), "bytes": alg_bytes},
+    }
+    if ctr:
+        if ctr["valu"]:
+            v = ctr["valu"] / sec / 1e9
+            levels["valu_issue"] = {"achieved": round(v, 1), "peak": VALU_PEAK_G,
+                                    "unit": "G wave64 VALU instructions/s", "frac": round(v / VALU_PEAK_G, 4),
+                                    "instructions_per_launch": ctr["valu"]}
+        if ctr["hbm_bytes"]:
+            h = ctr["hbm_bytes"] / sec / 1e9
+            levels["hbm_fabric"] = {"achieved_gbs": round(h, 1), "peak_gbs": HBM_PEAK_GBS,
+                                    "frac": round(h / HBM_PEAK_GBS, 4), "bytes_per_launch": ctr["hbm_bytes"],
+                                    "requested_over_fabric": round(alg_bytes / ctr["hbm_bytes"], 2)}
+        if ctr["l2_req"] and ctr["l2_hit"] is not None:
+            levels["l2"] = {"requests_per_launch": ctr["l2_req"],
+                            "hit_rate": round(ctr["l2_hit"] / ctr["l2_req"], 4)}
+    # the binding level is the one closest to its peak
+    cands = [(lv["frac"], name) for name, lv in levels.items() if "frac" in lv]
+    if cands:
+        frac, bname = max(cands)
+        lv = levels[bname]
+        roof = {"bound": "alu" if bname == "valu_issue" else "hbm", "level": bname,
+                "achieved": lv.get("achieved", lv.get("achieved_gbs")),
+                "peak": lv.get("peak", lv.get("peak_gbs")),
+                "unit": lv.get("unit", "GB/s"), "frac": frac}
+    else:
+        roof = {"bound": None, "level": None, "achieved": None, "peak": None, "unit": None, "frac": None,
+                "note": "no counter summary of these kernel sources: re-profile (profiles/)"}
+    roof.update({
+        "kernel": "render_kernel",
+        "traffic": ctr["hbm_bytes"] if ctr else None,
+        "levels": levels,
+        "algorithmic_bytes_per_launch": alg_bytes,
+        "algorithmic_bytes_per_sample": per_sample,
+        "uniform_random_gather_probe_gbs": probe or None,
+        "kernel_sources": kernel_source_hash(),
+    })
     if baked:
         workload = (f"baked_hd: 8 views x 1920x1080 rays, coarse grid L_C=512 block-sparse "
                     f"({sc.n_blocks} of {sc.block_index.size} blocks of 8^3 vertices), {L} fine hash levels "
@@ -517,27 +629,15 @@ def main():
         "mreads_per_s": round(n_reads / (ms / 1e3) / 1e6, 1),
         "samples_per_ray": round(n_samples / n, 3),
         "reads_per_ray": round(n_reads / n, 3),
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "render_kernel",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
-            "algorithmic_bytes_per_launch": alg_bytes,
-            "algorithmic_bytes_per_sample": per_sample,
-            "requested_gather_gbs_per_level": round(gather / L / (ms / 1e3) / 1e9, 1),
-            "hbm_gbs_measured": None if traffic is None else round(traffic / (ms / 1e3) / 1e9, 1),
-            "hbm_frac_measured": None if traffic is None else round(traffic / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-            "gather_probe_gbs": probe or None,
-            "frac_of_gather_probe": (round(gather / (ms / 1e3) / 1e9 / probe["pairs"], 4)
-                                     if probe else None),
-            "kernel_sources": kernel_source_hash(),
-        },
+        "roofline": roof,
     }
     if cpu is not None:
         res["cpu_baseline"] = cpu
+    if args.prop_steps > 0 and not (baked or pyr or args.mlp == "view" or args.dtype != "f32"):
+        # the metric's second half: the learned proposal against plain marching
+        del r, go, gd, aux, out
+        torch.cuda.empty_cache()
+        res["proposal_comparison"] = proposal_comparison(args.prop_steps, 3, args.prop_epochs)
     print(json.dumps(res), flush=True)
 
 

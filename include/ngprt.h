@@ -153,6 +153,8 @@ typedef struct ngprt_outputs {
                       *        rendering weights w_i on the lattice intervals
                       *        [k_i step, (k_i + 1) step] (k_i the sample's lattice index):
                       *        sum_ij w_i w_j |m_i - m_j| + step/3 sum_i w_i^2, m_i = (k_i + 1/2) step */
+  float* proposal;   /* [n][4] ngprt_render_proposal only: the loaded network's t_near, t_far,
+                      *        t_term and sigmoid(confidence logit) for the ray */
 } ngprt_outputs;
 
 /* Create a context on the current HIP device.  Validates the descriptor
@@ -247,16 +249,51 @@ int ngprt_load_mlp(ngprt_ctx* ctx, const float* dev_params, void* stream);
 int ngprt_render(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins,
                  const float* dev_dirs, const ngprt_outputs* out, void* stream);
 
-/* Render with a per-ray sample-interval proposal (an extension; see
- * ngprt_proposal_infer).  dev_proposal: float32 [n][4] = t_near, t_far,
- * t_term, confidence.  A ray whose confidence reaches conf_threshold stops
- * marching after t_far + margin (same lattice, so its samples are the plain
- * march's first ones); if it has no sample by then it carries on as the
- * plain march (dev_fallback, int32 [n] NULL-able, marks those rays: their
- * result is the plain render's bit for bit).  Other rays march plainly. */
+/* How a per-ray sample-interval proposal [t_near, t_far, t_term, conf]
+ * restricts the march (an extension; see ngprt_render_proposal). */
+typedef struct ngprt_proposal_cfg {
+  float conf_threshold; /* rays with conf >= conf_threshold use their proposal */
+  float margin;         /* padding of the interval, in t units, finite and >= 0 */
+  int32_t use_near;     /* 1: skip the lattice points before t_near - margin; 0: march from the start */
+  float far_guard;      /* <= 0: a lattice point beyond t_far + margin ends the ray; > 0: it ends the
+                         * ray only when the ray's transmittance is below far_guard (so the colour
+                         * weight dropped is below far_guard), otherwise the ray marches on */
+} ngprt_proposal_cfg;
+
+/* Render with the learned per-ray sample-interval proposal (an extension;
+ * the network is described at ngprt_proposal_infer and loaded by
+ * ngprt_proposal_load, NGPRT_E_NOT_LOADED otherwise).  The render kernel
+ * runs the network for its rays before marching (no separate pass; the
+ * outputs go to out->proposal when given).  A ray whose confidence reaches
+ * cfg->conf_threshold marches only the lattice points with t in
+ * [t_near - margin, t_far + margin] of the plain render's lattice (the far
+ * end subject to cfg->far_guard): with cfg->use_near, in the box domain from
+ * lattice index max(0, floor((t_near - margin - t0) / step)), t0 the ROI
+ * entry, and in the contracted domain lattice points before t_near - margin
+ * are visited without a grid read.  A proposed ray that takes no sample in
+ * its interval marches again from its start as the plain march, so its
+ * result is the plain render's bit for bit (dev_fallback, int32 [n]
+ * NULL-able, marks those rays; out->n_reads counts the reads of both
+ * marches).  Other rays march plainly.  A NULL or invalid cfg ->
+ * NGPRT_E_INVALID_ARG. */
 int ngprt_render_proposal(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins,
-                          const float* dev_dirs, const float* dev_proposal, float conf_threshold,
-                          float margin, const ngprt_outputs* out, int32_t* dev_fallback, void* stream);
+                          const float* dev_dirs, const ngprt_proposal_cfg* cfg,
+                          const ngprt_outputs* out, int32_t* dev_fallback, void* stream);
+
+/* ngprt_render_proposal with the proposals given per ray instead of the
+ * loaded network: dev_proposal, float32 [n][4] = t_near, t_far, t_term,
+ * confidence (out->proposal is ignored). */
+int ngprt_render_intervals(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins,
+                           const float* dev_dirs, const float* dev_proposal,
+                           const ngprt_proposal_cfg* cfg, const ngprt_outputs* out,
+                           int32_t* dev_fallback, void* stream);
+
+/* Load the proposal network's float32 master weights [7556] (the layout of
+ * ngprt_proposal_infer) for ngprt_render_proposal: copied into library
+ * memory as bfloat16 (round to nearest even) product operands and float32
+ * biases; the caller may free or update its buffer once the stream has
+ * passed the call (load again after training steps). */
+int ngprt_proposal_load(ngprt_ctx* ctx, const float* dev_params, void* stream);
 
 /* Parity helpers.  Evaluate the lookup + attention chain at n positions in
  * the grid's domain (box: world coordinates; contract: contracted

@@ -48,7 +48,12 @@ class NgprtDesc(ctypes.Structure):
 class NgprtOutputs(ctypes.Structure):
     _fields_ = [(name, ctypes.c_void_p) for name in
                 ("rgb", "c_d", "feat", "t_final", "depth", "n_samples", "n_reads", "t_first",
-                 "t_far", "t_half", "dist_loss")]
+                 "t_far", "t_half", "dist_loss", "proposal")]
+
+
+class NgprtProposalCfg(ctypes.Structure):
+    _fields_ = [("conf_threshold", ctypes.c_float), ("margin", ctypes.c_float), ("use_near", ctypes.c_int32),
+                ("far_guard", ctypes.c_float)]
 
 
 # (name, restype, argtypes)
@@ -70,8 +75,11 @@ SIGNATURES = [
     ("ngprt_debug_eval_points", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P]),
     ("ngprt_gather_probe", ctypes.c_int, [_P, _I64, ctypes.c_uint32, _I32, _P, _P]),
     ("ngprt_debug_march", ctypes.c_int, [_P, _I64, _P, _P, _I32, _P, _P, _P, _I32, _P]),
-    ("ngprt_render_proposal", ctypes.c_int, [_P, _I64, _P, _P, _P, ctypes.c_float, ctypes.c_float,
+    ("ngprt_render_intervals", ctypes.c_int, [_P, _I64, _P, _P, _P, ctypes.POINTER(NgprtProposalCfg),
+                                              ctypes.POINTER(NgprtOutputs), _P, _P]),
+    ("ngprt_render_proposal", ctypes.c_int, [_P, _I64, _P, _P, ctypes.POINTER(NgprtProposalCfg),
                                              ctypes.POINTER(NgprtOutputs), _P, _P]),
+    ("ngprt_proposal_load", ctypes.c_int, [_P, _P, _P]),
     ("ngprt_render_backward", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P]),
     ("ngprt_render_backward_reg", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P]),
     ("ngprt_render_backward_noalloc", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P]),

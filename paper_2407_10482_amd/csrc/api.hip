@@ -183,6 +183,8 @@ void ngprt_destroy(ngprt_ctx* ctx) {
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->prop_wb) (void)hipFree(ctx->prop_wb);
   if (ctx->prop_grad) (void)hipFree(ctx->prop_grad);
+  if (ctx->prop_net) (void)hipFree(ctx->prop_net);
+  if (ctx->prop_tmp) (void)hipFree(ctx->prop_tmp);
   if (ctx->mlp_rec) (void)hipFree(ctx->mlp_rec);
   if (ctx->cidx) (void)hipFree(ctx->cidx);
   if (ctx->catlas) (void)hipFree(ctx->catlas);
@@ -387,30 +389,63 @@ int ngprt_render(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins, const
   if (is_view_mlp(&ctx->desc) && (!out->c_d || !out->feat))
     return fail(ctx, NGPRT_E_INVALID_ARG, "the view-dependent MLP needs the c_d and feat outputs");
   RayOut o{out->rgb,       out->c_d,     out->feat,   out->t_final, out->depth,
-           out->n_samples, out->n_reads, out->t_first, out->t_far,   out->t_half, out->dist_loss};
-  return launch_render(ctx, n_rays, dev_origins, dev_dirs, o, nullptr, 0.0f, 0.0f, nullptr,
+           out->n_samples, out->n_reads, out->t_first, out->t_far,   out->t_half, out->dist_loss,
+           nullptr};
+  const ngprt_proposal_cfg none{0.0f, 0.0f, 0, 0.0f};
+  return launch_render(ctx, n_rays, dev_origins, dev_dirs, o, nullptr, false, nullptr, none, nullptr,
                        (hipStream_t)stream);
 }
 
-int ngprt_render_proposal(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins, const float* dev_dirs,
-                          const float* dev_proposal, float conf_threshold, float margin,
-                          const ngprt_outputs* out, int32_t* dev_fallback, void* stream) {
+}  // extern "C"
+
+// Shared checks and launch of the two proposal renders.
+static int render_with_proposal(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins, const float* dev_dirs,
+                                const float* dev_proposal, bool use_net, const ngprt_proposal_cfg* cfg,
+                                const ngprt_outputs* out, int32_t* dev_fallback, void* stream) {
   if (!ctx) return NGPRT_E_INVALID_ARG;
   if (n_rays < 0) return fail(ctx, NGPRT_E_INVALID_ARG, "n_rays < 0");
+  if (!cfg) return fail(ctx, NGPRT_E_INVALID_ARG, "NULL proposal configuration");
+  if (!std::isfinite(cfg->margin) || cfg->margin < 0.0f) return fail(ctx, NGPRT_E_INVALID_ARG, "bad margin");
+  if (cfg->conf_threshold != cfg->conf_threshold || cfg->far_guard != cfg->far_guard)
+    return fail(ctx, NGPRT_E_INVALID_ARG, "NaN confidence threshold or far guard");
+  if (cfg->use_near != 0 && cfg->use_near != 1) return fail(ctx, NGPRT_E_INVALID_ARG, "use_near must be 0 or 1");
   if (n_rays == 0) return NGPRT_OK;
   if (!out || !out->rgb) return fail(ctx, NGPRT_E_INVALID_ARG, "out->rgb is required");
-  if (!dev_origins || !dev_dirs || !dev_proposal)
+  if (!dev_origins || !dev_dirs || (!use_net && !dev_proposal))
     return fail(ctx, NGPRT_E_INVALID_ARG, "ray or proposal pointers are NULL");
-  if (!std::isfinite(margin) || margin < 0.0f) return fail(ctx, NGPRT_E_INVALID_ARG, "bad margin");
   int rc = check_ready(ctx);
   if (rc) return rc;
   if (!ctx->mlp_loaded) return fail(ctx, NGPRT_E_NOT_LOADED, "mlp not loaded");
+  if (use_net && !ctx->prop_loaded) return fail(ctx, NGPRT_E_NOT_LOADED, "proposal network not loaded");
   if (is_view_mlp(&ctx->desc) && (!out->c_d || !out->feat))
     return fail(ctx, NGPRT_E_INVALID_ARG, "the view-dependent MLP needs the c_d and feat outputs");
   RayOut o{out->rgb,       out->c_d,     out->feat,   out->t_final, out->depth,
-           out->n_samples, out->n_reads, out->t_first, out->t_far,   out->t_half, out->dist_loss};
-  return launch_render(ctx, n_rays, dev_origins, dev_dirs, o, dev_proposal, conf_threshold, margin,
-                       dev_fallback, (hipStream_t)stream);
+           out->n_samples, out->n_reads, out->t_first, out->t_far,   out->t_half, out->dist_loss,
+           use_net ? out->proposal : nullptr};
+  return launch_render(ctx, n_rays, dev_origins, dev_dirs, o, use_net ? nullptr : dev_proposal, use_net,
+                       o.proposal, *cfg, dev_fallback, (hipStream_t)stream);
+}
+
+extern "C" {
+
+int ngprt_render_intervals(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins, const float* dev_dirs,
+                           const float* dev_proposal, const ngprt_proposal_cfg* cfg, const ngprt_outputs* out,
+                           int32_t* dev_fallback, void* stream) {
+  return render_with_proposal(ctx, n_rays, dev_origins, dev_dirs, dev_proposal, false, cfg, out, dev_fallback,
+                              stream);
+}
+
+int ngprt_render_proposal(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins, const float* dev_dirs,
+                          const ngprt_proposal_cfg* cfg, const ngprt_outputs* out, int32_t* dev_fallback,
+                          void* stream) {
+  return render_with_proposal(ctx, n_rays, dev_origins, dev_dirs, nullptr, true, cfg, out, dev_fallback,
+                              stream);
+}
+
+int ngprt_proposal_load(ngprt_ctx* ctx, const float* dev_params, void* stream) {
+  if (!ctx) return NGPRT_E_INVALID_ARG;
+  if (!dev_params) return fail(ctx, NGPRT_E_INVALID_ARG, "NULL pointer");
+  return load_proposal(ctx, dev_params, (hipStream_t)stream);
 }
 
 int ngprt_debug_eval_points(ngprt_ctx* ctx, int64_t n, const float* dev_pos, int32_t* dev_idx,

@@ -87,6 +87,7 @@ struct RayOut {
   float* t_far;
   float* t_half;
   float* dist_loss;
+  float* proposal;
 };
 
 }  // namespace ngprt
@@ -105,6 +106,9 @@ struct ngprt_ctx {
   void* ws = nullptr;         // workspace (per-wave gradient partials of backward / proposal)
   size_t ws_bytes = 0;
   void* prop_wb = nullptr;    // proposal weights in bfloat16 [7556]
+  void* prop_net = nullptr;   // loaded proposal network: A-operand tiles [32][64] uint2 + biases [132]
+  void* prop_tmp = nullptr;   // the same layout for ngprt_proposal_infer's caller-owned weights
+  bool prop_loaded = false;
   void* prop_grad = nullptr;  // proposal gradient [7556] when the caller wants none
   int32_t* cidx = nullptr;    // baked model: block index grid [nb^3]
   float* catlas = nullptr;    // baked model: atlas [n_blocks][512][Cpad]
@@ -129,8 +133,11 @@ int launch_build_distance(ngprt_ctx* ctx, const uint8_t* occ, const uint8_t* dis
 int launch_export_distance(ngprt_ctx* ctx, uint8_t* out, hipStream_t s);
 int launch_load_tables(ngprt_ctx* ctx, const float* tables, hipStream_t s);
 int launch_export_tables(ngprt_ctx* ctx, void* codes, float* scales, hipStream_t s);
+// prop: per-ray proposals [n][4] given by the caller, or use_net: the network
+// loaded by ngprt_proposal_load runs in the kernel (its outputs to prop_out)
 int launch_render(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const RayOut& out,
-                  const float* prop, float conf_thr, float margin, int32_t* fallback, hipStream_t s);
+                  const float* prop, bool use_net, float* prop_out, const ngprt_proposal_cfg& pc,
+                  int32_t* fallback, hipStream_t s);
 int launch_eval_points(ngprt_ctx* ctx, int64_t n, const float* pos, int32_t* idx, float* fused,
                        float* weights, hipStream_t s);
 int launch_march(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, int32_t cap,
@@ -157,6 +164,8 @@ int launch_pack_atlas(ngprt_ctx* ctx, const float* atlas, int64_t n_blocks, hipS
 int launch_gather_probe(ngprt_ctx* ctx, int64_t n, uint32_t seed, int pairs, float* out, hipStream_t s);
 int launch_adam(int64_t n, float* p, const float* g, float* m, float* v, int32_t step, float lr,
                 float b1, float b2, float eps, hipStream_t s);
+int launch_prop_arrange(ngprt_ctx* ctx, const float* P, void* dst, hipStream_t s);
+int load_proposal(ngprt_ctx* ctx, const float* P, hipStream_t s);
 int launch_prop_infer(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const float* P,
                       float* out, hipStream_t s);
 int launch_prop_train(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const float* labels,

@@ -27,6 +27,8 @@ struct MarchState {
   int next_read;      // box: first lattice index not known to be empty
   bool has_ball;      // contract: known-empty ball
   float bc[3], br2;
+  float t_lo;         // optional start: contract: lattice points with t < t_lo are not read
+                      // (box: the caller sets k to the first lattice point at or after it)
   float t_hi;         // optional end: a lattice point with t > t_hi stops the march
   bool stopped_at_hi; // the march ended at t_hi (and can be resumed)
   bool done;
@@ -48,6 +50,7 @@ __device__ __forceinline__ void march_init(const SceneArgs& S, const float* o, c
   m.next_read = 0;
   m.has_ball = false;
   m.t = 0.0f;
+  m.t_lo = -__int_as_float(0x7F800000);
   m.t_hi = __int_as_float(0x7F800000);
   m.stopped_at_hi = false;
   if (DOM == DOM_BOX) {
@@ -91,7 +94,9 @@ __device__ __forceinline__ uint32_t voxel_of(const SceneArgs& S, const float p[3
 // ray leaves the domain.
 // PYR: the scene marches an occupancy pyramid (S.pyr_n > 0) instead of one
 // occupancy grid; a template flag so the single-grid march carries none of it.
-template <int DOM, bool PYR>
+// LO: honour m.t_lo in the contracted domain (points before it are visited
+// without a read).
+template <int DOM, bool PYR, bool LO = false>
 __device__ __forceinline__ bool march_next(const SceneArgs& S, MarchState& m, bool naive,
                                            int& reads, float u[3], float& ts, int& ks) {
   while (!m.done) {
@@ -140,6 +145,7 @@ __device__ __forceinline__ bool march_next(const SceneArgs& S, MarchState& m, bo
     }
     m.k = kcur + 1;
     if (!need) continue;
+    if (LO && DOM == DOM_CONTRACT && tcur < m.t_lo) continue;
     const uint32_t v = voxel_of(S, p, u);
     if (PYR) {
       // multi-level occupancy (Eq. 9's s_O branch): levels coarse to fine;

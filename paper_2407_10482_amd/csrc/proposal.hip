@@ -17,6 +17,7 @@
 
 #include "device.h"
 #include "internal.h"
+#include "proposal_net.h"
 
 namespace ngprt {
 
@@ -130,21 +131,49 @@ __device__ __forceinline__ void prop_forward(PropLds& L, const float* __restrict
   __syncthreads();
 }
 
-__global__ void __launch_bounds__(64) prop_infer_kernel(int64_t n, const float* __restrict__ O,
-                                                        const float* __restrict__ D,
-                                                        const float* __restrict__ P,
-                                                        const uint16_t* __restrict__ Wb,
-                                                        float* __restrict__ out) {
-  __shared__ PropLds L;
-  const int lane = threadIdx.x;
-  const int64_t ray = int64_t(blockIdx.x) * 64 + lane;
-  const bool in_range = ray < n;
-  prop_forward(L, P, Wb, O + 3 * (in_range ? ray : 0), D + 3 * (in_range ? ray : 0), in_range, lane);
-  if (in_range) {
-    out[ray * 4 + 0] = L.out[0 * 64 + lane];
-    out[ray * 4 + 1] = L.out[1 * 64 + lane];
-    out[ray * 4 + 2] = L.out[2 * 64 + lane];
-    out[ray * 4 + 3] = 1.0f / (1.0f + __expf(-L.out[3 * 64 + lane]));
+// Float32 master weights -> the A-operand tiles and biases of
+// prop_infer_wave (proposal_net.h): 32 tiles x 64 lanes of four bfloat16,
+// then b1, b2, b3 as float32.
+__global__ void prop_arrange_kernel(const float* __restrict__ P, uint2* __restrict__ tiles,
+                                    float* __restrict__ bias) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < kPropTiles * 64) {
+    const int tile = t >> 6, lane = t & 63;
+    const int i = lane & 15, k0 = 4 * (lane >> 4);
+    int base, row, col, ld;
+    bool zero = false;
+    if (tile < 12) {             // layer 1: W1[64][48]
+      base = kPW1; ld = kPIn; row = 16 * (tile / 3) + i; col = 16 * (tile % 3) + k0;
+    } else if (tile < 28) {      // layer 2: W2[64][64]
+      const int q = tile - 12;
+      base = kPW2; ld = kPH; row = 16 * (q / 4) + i; col = 16 * (q % 4) + k0;
+    } else {                     // layer 3: W3[4][64], rows 4..15 zero
+      base = kPW3; ld = kPH; row = i; col = 16 * (tile - 28) + k0;
+      zero = i >= kPOut;
+    }
+    uint16_t h[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) h[e] = zero ? (uint16_t)0 : bf16_rne(P[base + (zero ? 0 : row) * ld + col + e]);
+    tiles[t] = make_uint2(uint32_t(h[0]) | (uint32_t(h[1]) << 16), uint32_t(h[2]) | (uint32_t(h[3]) << 16));
+  }
+  if (t < kPropBias) bias[t] = t < 64 ? P[kPB1 + t] : (t < 128 ? P[kPB2 + t - 64] : P[kPB3 + t - 128]);
+}
+
+// Stand-alone inference: four waves per workgroup, one wave per 64 rays.
+__global__ void __launch_bounds__(256) prop_infer_kernel(int64_t n, const float* __restrict__ O,
+                                                         const float* __restrict__ D,
+                                                         const uint2* __restrict__ tiles,
+                                                         const float* __restrict__ bias,
+                                                         float* __restrict__ out) {
+  __shared__ float out4_all[4][256];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t ray_base = (int64_t(blockIdx.x) * 4 + wave) * 64;
+  prop_infer_wave(tiles, bias, O, D, ray_base, n, lane, out4_all[wave]);
+  __syncthreads();
+  const int64_t ray = ray_base + lane;
+  if (ray < n) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) out[ray * 4 + c] = out4_all[wave][4 * lane + c];
   }
 }
 
@@ -316,18 +345,44 @@ static int ensure_prop_buffers(ngprt_ctx* ctx, int64_t n_waves, hipStream_t st) 
   return NGPRT_OK;
 }
 
+constexpr size_t kPropNetBytes = size_t(kPropTiles) * 64 * sizeof(uint2) + kPropBias * sizeof(float);
+
+// dst: kPropNetBytes of device memory (tiles, then biases)
+int launch_prop_arrange(ngprt_ctx* ctx, const float* P, void* dst, hipStream_t st) {
+  uint2* tiles = reinterpret_cast<uint2*>(dst);
+  float* bias = reinterpret_cast<float*>(reinterpret_cast<char*>(dst) + size_t(kPropTiles) * 64 * sizeof(uint2));
+  hipLaunchKernelGGL(prop_arrange_kernel, dim3((kPropTiles * 64 + 255) / 256), dim3(256), 0, st, P, tiles, bias);
+  return check_launch(ctx, "prop_arrange_kernel");
+}
+
 int launch_prop_infer(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const float* P, float* out,
                       hipStream_t st) {
-  int rc = ensure_prop_buffers(ctx, 0, st);
+  if (!ctx->prop_tmp && hipMalloc(&ctx->prop_tmp, kPropNetBytes) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->prop_tmp = nullptr;
+    return fail(ctx, NGPRT_E_ALLOC, "proposal inference weights");
+  }
+  int rc = launch_prop_arrange(ctx, P, ctx->prop_tmp, st);
   if (rc) return rc;
-  hipLaunchKernelGGL(prop_cast_kernel, dim3((kPParams + 255) / 256), dim3(256), 0, st, P,
-                     (uint16_t*)ctx->prop_wb);
-  if ((rc = check_launch(ctx, "prop_cast_kernel"))) return rc;
-  const int64_t blocks = (n + 63) / 64;
+  const int64_t blocks = (n + 255) / 256;
   if (blocks > 0x7FFFFFFF) return fail(ctx, NGPRT_E_SHAPE, "too many rays");
-  hipLaunchKernelGGL(prop_infer_kernel, dim3(unsigned(blocks)), dim3(64), 0, st, n, o, d, P,
-                     (const uint16_t*)ctx->prop_wb, out);
+  const uint2* tiles = reinterpret_cast<const uint2*>(ctx->prop_tmp);
+  const float* bias = reinterpret_cast<const float*>(reinterpret_cast<const char*>(ctx->prop_tmp) +
+                                                     size_t(kPropTiles) * 64 * sizeof(uint2));
+  hipLaunchKernelGGL(prop_infer_kernel, dim3(unsigned(blocks)), dim3(256), 0, st, n, o, d, tiles, bias, out);
   return check_launch(ctx, "prop_infer_kernel");
+}
+
+int load_proposal(ngprt_ctx* ctx, const float* P, hipStream_t st) {
+  if (!ctx->prop_net && hipMalloc(&ctx->prop_net, kPropNetBytes) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->prop_net = nullptr;
+    return fail(ctx, NGPRT_E_ALLOC, "proposal network");
+  }
+  int rc = launch_prop_arrange(ctx, P, ctx->prop_net, st);
+  if (rc) return rc;
+  ctx->prop_loaded = true;
+  return NGPRT_OK;
 }
 
 int launch_prop_train(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const float* labels,

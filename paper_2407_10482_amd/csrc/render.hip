@@ -15,6 +15,7 @@
 #include "device.h"
 #include "internal.h"
 #include "march.h"
+#include "proposal_net.h"
 
 namespace ngprt {
 
@@ -25,13 +26,26 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // MODE_MARCH: sample lists for parity checks (no MLP).
 enum { MODE_RENDER = 0, MODE_MARCH = 1, MODE_RENDER_EXT = 2 };
 
-// Optional per-ray sample-interval proposal: rays whose confidence reaches
-// conf_thr end their march after t_far + margin (same lattice); a ray with
-// no sample by then carries on as the plain march.
+// Optional per-ray sample-interval proposal [t_near, t_far, t_term,
+// confidence], given per ray (prop) or computed by the loaded network in the
+// kernel's prologue (net_w): a ray whose confidence reaches conf_thr marches
+// only the lattice points with t in [t_near - margin, t_far + margin] (box:
+// from lattice index max(0, floor((t_near - margin - t0) / step)); contracted
+// domain: points before t_near - margin are visited without a read; without
+// use_near from its start).  With far_guard > 0 the far end ends a ray only
+// once its transmittance is below far_guard; otherwise it marches on.  A
+// proposed ray that takes no sample in its interval marches again from its
+// start as the plain march (its samples are then the plain render's; its
+// read count includes both marches).
 struct ProposalArgs {
-  const float* prop;     // [n][4]: t_near, t_far, t_term, confidence (NULL: plain march)
+  const float* prop;     // [n][4] (NULL: no per-ray proposal given)
+  const uint2* net_w;    // loaded network: A-operand tiles (NULL: none)
+  const float* net_b;    // its biases
+  float* prop_out;       // [n][4] the network's outputs (NULL-able)
   float conf_thr;
   float margin;
+  int use_near;
+  float far_guard;
   int32_t* fallback;     // [n] 1 where the plain march ran after a proposal (NULL-able)
 };
 
@@ -146,10 +160,36 @@ render_kernel(SceneArgs S, int64_t n, const float* __restrict__ O,
   march_init<DOM>(S, oray, dray, in_range, m);
   constexpr bool EXT = MODE == MODE_RENDER_EXT;
   bool proposed = false, fell_back = false;
-  if (EXT && pa.prop && in_range && !m.done) {
-    const float* q = pa.prop + 4 * ray;
-    if (q[3] >= pa.conf_thr) {
+  if (EXT && (pa.prop || pa.net_w)) {
+    float q[4];
+    if (pa.net_w) {
+      // the loaded network, run by the wave for its 64 rays (uniform branch:
+      // every wave of the grid takes it)
+      float* out4 = xin_all[wave];
+      prop_infer_wave(pa.net_w, pa.net_b, O, D, ray_base, n, lane, out4);
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < 4; ++c) q[c] = out4[4 * lane + c];
+      __syncthreads();
+      if (pa.prop_out && in_range) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) pa.prop_out[4 * ray + c] = q[c];
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) q[c] = in_range ? pa.prop[4 * ray + c] : 0.0f;
+    }
+    if (in_range && !m.done && q[3] >= pa.conf_thr) {
       m.t_hi = q[1] + pa.margin;
+      if (pa.use_near) {
+        const float lo = q[0] - pa.margin;
+        if (DOM == DOM_BOX) {
+          const float kf = floorf((lo - m.t0) / S.step);
+          m.k = kf > 0.0f ? (kf < (float)kMaxLattice ? (int)kf : kMaxLattice) : 0;
+        } else {
+          m.t_lo = lo;
+        }
+      }
       proposed = true;
     }
   }
@@ -165,14 +205,21 @@ render_kernel(SceneArgs S, int64_t n, const float* __restrict__ O,
   for (;;) {
     float u[3], ts;
     int ks;
-    bool have = march_next<DOM, (MODEL & 2) != 0>(S, m, naive != 0, reads, u, ts, ks);
-    if (EXT && !have && proposed && !fell_back && ns == 0 && m.stopped_at_hi) {
-      // nothing sampled before the proposed end: carry on as the plain march
-      m.t_hi = __int_as_float(0x7F800000);
-      m.done = false;
-      m.stopped_at_hi = false;
-      fell_back = true;
-      have = march_next<DOM, (MODEL & 2) != 0>(S, m, naive != 0, reads, u, ts, ks);
+    bool have = march_next<DOM, (MODEL & 2) != 0, EXT>(S, m, naive != 0, reads, u, ts, ks);
+    if (EXT && !have && proposed && !fell_back) {
+      if (ns == 0) {
+        // the proposed interval holds no occupied lattice point: march again
+        // from the start as the plain march
+        march_init<DOM>(S, oray, dray, in_range, m);
+        fell_back = true;
+        have = march_next<DOM, (MODEL & 2) != 0, EXT>(S, m, naive != 0, reads, u, ts, ks);
+      } else if (m.stopped_at_hi && pa.far_guard > 0.0f && !(T < pa.far_guard)) {
+        // at the proposed far end with too much transmittance left: march on
+        m.t_hi = __int_as_float(0x7F800000);
+        m.done = false;
+        m.stopped_at_hi = false;
+        have = march_next<DOM, (MODEL & 2) != 0, EXT>(S, m, naive != 0, reads, u, ts, ks);
+      }
     }
     if (__ballot(have) == 0) break;
     if (have) {
@@ -325,13 +372,19 @@ static void dispatch(const SceneArgs& S, int dom, int dt, dim3 g, hipStream_t st
 }
 
 int launch_render(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const RayOut& out,
-                  const float* prop, float conf_thr, float margin, int32_t* fallback, hipStream_t st) {
+                  const float* prop, bool use_net, float* prop_out, const ngprt_proposal_cfg& pc,
+                  int32_t* fallback, hipStream_t st) {
   SceneArgs S = scene_args(ctx);
   const int64_t blocks = (n + 255) / 256;
   if (blocks > 0x7FFFFFFF) return fail(ctx, NGPRT_E_SHAPE, "too many rays for one launch");
   MarchRecord rec{nullptr, nullptr, nullptr, 0};
-  ProposalArgs pa{prop, conf_thr, margin, fallback};
-  const bool ext = prop || out.t_first || out.t_far || out.t_half || out.dist_loss;
+  const uint2* net_w = use_net ? reinterpret_cast<const uint2*>(ctx->prop_net) : nullptr;
+  const float* net_b = use_net ? reinterpret_cast<const float*>(
+                                     reinterpret_cast<const char*>(ctx->prop_net) + kPropTiles * 64 * 8)
+                               : nullptr;
+  ProposalArgs pa{prop,         net_w,           net_b,        use_net ? prop_out : nullptr,
+                  pc.conf_threshold, pc.margin, pc.use_near, pc.far_guard, fallback};
+  const bool ext = prop || use_net || out.t_first || out.t_far || out.t_half || out.dist_loss;
   if (ext)
     dispatch<MODE_RENDER_EXT>(S, ctx->desc.domain, ctx->desc.table_dtype, dim3(unsigned(blocks)), st, n,
                               o, d, out, rec, ctx->mlp, 0, pa);
@@ -350,7 +403,7 @@ int launch_march(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, int3
   if (blocks > 0x7FFFFFFF) return fail(ctx, NGPRT_E_SHAPE, "too many rays for one launch");
   MarchRecord rec{sk, ns, nr, cap};
   RayOut out{};
-  ProposalArgs pa{nullptr, 0.0f, 0.0f, nullptr};
+  ProposalArgs pa{nullptr, nullptr, nullptr, nullptr, 0.0f, 0.0f, 0, 0.0f, nullptr};
   dispatch<MODE_MARCH>(S, ctx->desc.domain, ctx->desc.table_dtype, dim3(unsigned(blocks)), st, n, o,
                        d, out, rec, ctx->mlp, naive, pa);
   return check_launch(ctx, "march_kernel");

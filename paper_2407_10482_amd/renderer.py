@@ -166,7 +166,7 @@ class Renderer:
                 out["feat"] = torch.empty((n, 4), dtype=torch.float32, device="cuda")
 
     OUTPUT_FIELDS = ("rgb", "c_d", "feat", "t_final", "depth", "n_samples", "n_reads", "t_first",
-                     "t_far", "t_half", "dist_loss")
+                     "t_far", "t_half", "dist_loss", "proposal")
 
     @staticmethod
     def _outputs(out: Dict[str, torch.Tensor]) -> NgprtOutputs:
@@ -187,24 +187,54 @@ class Renderer:
                        t_half=torch.empty((n,), **f))
         return out
 
-    def render_proposal(self, origins: torch.Tensor, dirs: torch.Tensor, proposal: torch.Tensor,
-                        conf_threshold: float = 0.9, margin: float = 0.0, aux: bool = True,
-                        out: Optional[Dict[str, torch.Tensor]] = None):
+    def _proposal_outputs(self, origins, dirs, aux, out, with_net):
         n = origins.shape[0]
         _dev(origins, torch.float32, (n, 3), "origins")
         _dev(dirs, torch.float32, (n, 3), "dirs")
-        _dev(proposal, torch.float32, (n, 4), "proposal")
         if out is None:
             out = self.alloc_outputs(n) if aux else {"rgb": torch.empty((n, 3), dtype=torch.float32,
                                                                         device="cuda")}
+            if aux and with_net:
+                out["proposal"] = torch.empty((n, 4), dtype=torch.float32, device="cuda")
         self._view_buffers(out, n)
         fb = out.get("fallback")
         if fb is None and aux:
             fb = out["fallback"] = torch.empty((n,), dtype=torch.int32, device="cuda")
+        return n, out, fb
+
+    @staticmethod
+    def _proposal_cfg(conf_threshold, margin, use_near, far_guard):
+        return _lib.NgprtProposalCfg(float(conf_threshold), float(margin), int(bool(use_near)),
+                                     float(far_guard))
+
+    def render_intervals(self, origins: torch.Tensor, dirs: torch.Tensor, proposal: torch.Tensor,
+                         conf_threshold: float = 0.9, margin: float = 0.0, aux: bool = True,
+                         out: Optional[Dict[str, torch.Tensor]] = None, use_near: bool = True,
+                         far_guard: float = 0.0):
+        """Render with per-ray proposals [n, 4] (t_near, t_far, t_term, confidence) given by the caller."""
+        n, out, fb = self._proposal_outputs(origins, dirs, aux, out, False)
+        _dev(proposal, torch.float32, (n, 4), "proposal")
         o = self._outputs(out)
-        check(self.lib.ngprt_render_proposal(self.ctx, n, _ptr(origins), _ptr(dirs), _ptr(proposal),
-                                             float(conf_threshold), float(margin), ctypes.byref(o),
-                                             _ptr(fb), _stream()), self.ctx)
+        cfg = self._proposal_cfg(conf_threshold, margin, use_near, far_guard)
+        check(self.lib.ngprt_render_intervals(self.ctx, n, _ptr(origins), _ptr(dirs), _ptr(proposal),
+                                              ctypes.byref(cfg), ctypes.byref(o), _ptr(fb), _stream()), self.ctx)
+        return out
+
+    def load_proposal(self, params: torch.Tensor):
+        """Load the proposal network's float32 master weights [7556] into the library."""
+        _dev(params, torch.float32, (7556,), "proposal params")
+        check(self.lib.ngprt_proposal_load(self.ctx, _ptr(params), _stream()), self.ctx)
+
+    def render_proposal(self, origins: torch.Tensor, dirs: torch.Tensor, conf_threshold: float = 0.9,
+                        margin: float = 0.0, aux: bool = True, out: Optional[Dict[str, torch.Tensor]] = None,
+                        use_near: bool = True, far_guard: float = 0.0):
+        """Render with the loaded proposal network run inside the render kernel
+        (its per-ray outputs in out["proposal"] when aux)."""
+        n, out, fb = self._proposal_outputs(origins, dirs, aux, out, True)
+        o = self._outputs(out)
+        cfg = self._proposal_cfg(conf_threshold, margin, use_near, far_guard)
+        check(self.lib.ngprt_render_proposal(self.ctx, n, _ptr(origins), _ptr(dirs), ctypes.byref(cfg),
+                                             ctypes.byref(o), _ptr(fb), _stream()), self.ctx)
         return out
 
     # ---------------------------------------------------------------- debug
