@@ -16,11 +16,18 @@
 //          every level's 9-channel gradient into its 8 corner entries with
 //          hardware float atomics (order-nondeterministic sums).  The wave
 //          first sums the contributions to equal entries (neighbouring rays'
-//          samples share cells) so one lane issues each entry's atomics;
-//          measured on 2^18-ray training batches this beats plain per-lane
-//          atomics at every level (4.3x on 8 x 2^14 tables, 1.9x on
-//          16 x 2^19).  The baked model scatters into its fine levels and
-//          coarse atlas rows instead (baked_scatter).
+//          samples share cells) so one lane issues each entry's atomics:
+//          per corner slot the 64 (entry, lane) words are sorted across the
+//          wave (a bitonic network on DPP and swizzle lane moves), runs of
+//          equal entries are summed by a segmented scan, and the last lane
+//          of each run issues the atomics.  Measured on 2^18-ray training
+//          batches (backward kernel): 16 x 2^19 tables 174 -> 92 ms, 8 x 2^14
+//          35 -> 14 ms against one pass per distinct entry with a butterfly
+//          sum each; with the sort in place the float atomics themselves
+//          (about 2.9 G per 16 x 2^19 step, nearly all at the finest levels,
+//          where a wave's entries are all distinct) take ~78 ms of the 92.
+//          The baked model scatters into its fine levels and coarse atlas
+//          rows instead (baked_scatter).
 // The per-wave MLP partials are then added in a fixed order (reduce.h).
 #include <hip/hip_runtime.h>
 
@@ -36,8 +43,91 @@ namespace ngprt {
 typedef float bf32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kPad = 17;   // LDS row pitch of the per-wave staging (bank spread)
-// levels up to this resolution merge equal entries across the wave before
-// their atomics (their cells are shared by neighbouring rays' samples)
+
+// Levels of at least this resolution merge equal table entries across the
+// wave by sorting (wave_sort_merge); coarser levels, where a wave's samples
+// share a handful of cells, by the leader loop (one pass per distinct entry).
+#ifndef NGPRT_BW_SORT_MIN_RES
+#define NGPRT_BW_SORT_MIN_RES 16
+#endif
+
+// value of lane (lane ^ J) for every lane of a full wave; J = 1, 2, 4, 8 by
+// DPP lane moves (quad_perm, row_half_mirror, row_mirror), 16 by ds_swizzle,
+// 32 by ds_bpermute
+template <int J>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v, int lane) {
+  const int x = int(v);
+  if constexpr (J == 1) return uint32_t(__builtin_amdgcn_update_dpp(x, x, 0xB1, 0xF, 0xF, false));
+  if constexpr (J == 2) return uint32_t(__builtin_amdgcn_update_dpp(x, x, 0x4E, 0xF, 0xF, false));
+  if constexpr (J == 4) {
+    const int h = __builtin_amdgcn_update_dpp(x, x, 0x141, 0xF, 0xF, false);   // i ^ 7 within 8
+    return uint32_t(__builtin_amdgcn_update_dpp(h, h, 0x1B, 0xF, 0xF, false)); // then ^ 3
+  }
+  if constexpr (J == 8) {
+    const int m = __builtin_amdgcn_update_dpp(x, x, 0x140, 0xF, 0xF, false);   // i ^ 15 within 16
+    return uint32_t(__builtin_amdgcn_update_dpp(m, m, 0x141, 0xF, 0xF, false)); // then ^ 7
+  }
+  if constexpr (J == 16) return uint32_t(__builtin_amdgcn_ds_swizzle(x, 0x401F));
+  return uint32_t(__builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, x));
+}
+
+// one compare-exchange stage of a bitonic sort over the wave's 64 lanes
+template <int K, int J>
+__device__ __forceinline__ uint32_t bitonic_stage(uint32_t v, int lane) {
+  const uint32_t o = lane_xor<J>(v, lane);
+  const bool keep_min = ((lane & J) == 0) == ((lane & K) == 0);
+  const uint32_t lo = v < o ? v : o, hi = v < o ? o : v;
+  return keep_min ? lo : hi;
+}
+
+// Sums the NV values of the wave's lanes that hold the same key (an entry
+// index below 2^26; lanes with active = false take no part).  Sorting the
+// words (key << 6 | lane) puts equal keys on neighbouring lanes; each lane
+// fetches the values of the lane whose word it holds, runs of equal keys are
+// summed by a scan (skipped when no key repeats) and the last lane of each
+// run returns true with the run's key and sum in key, v.  Every lane of the
+// wave must call this with all 64 lanes active.
+template <int NV>
+__device__ __forceinline__ bool wave_sort_merge(uint32_t& key, bool active, float v[NV], int lane) {
+  uint32_t w = active ? ((key << 6) | uint32_t(lane)) : 0xFFFFFFFFu;
+  w = bitonic_stage<2, 1>(w, lane);
+  w = bitonic_stage<4, 2>(w, lane);   w = bitonic_stage<4, 1>(w, lane);
+  w = bitonic_stage<8, 4>(w, lane);   w = bitonic_stage<8, 2>(w, lane);   w = bitonic_stage<8, 1>(w, lane);
+  w = bitonic_stage<16, 8>(w, lane);  w = bitonic_stage<16, 4>(w, lane);  w = bitonic_stage<16, 2>(w, lane);
+  w = bitonic_stage<16, 1>(w, lane);
+  w = bitonic_stage<32, 16>(w, lane); w = bitonic_stage<32, 8>(w, lane);  w = bitonic_stage<32, 4>(w, lane);
+  w = bitonic_stage<32, 2>(w, lane);  w = bitonic_stage<32, 1>(w, lane);
+  w = bitonic_stage<64, 32>(w, lane); w = bitonic_stage<64, 16>(w, lane); w = bitonic_stage<64, 8>(w, lane);
+  w = bitonic_stage<64, 4>(w, lane);  w = bitonic_stage<64, 2>(w, lane);  w = bitonic_stage<64, 1>(w, lane);
+  const bool valid = w != 0xFFFFFFFFu;
+  const int src = int(w & 63u);
+  const uint32_t k = w >> 6;
+  float x[NV];
+#pragma unroll
+  for (int j = 0; j < NV; ++j)
+    x[j] = __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v[j])));
+  // neighbours' keys (sentinels sort last, so a valid lane's successor is
+  // either valid or the sentinel)
+  const uint32_t next = uint32_t(__builtin_amdgcn_ds_bpermute(((lane + 1) & 63) << 2, int(k)));
+  const bool tail = valid && (lane == 63 || next != k);
+  // segmented inclusive scan over runs of equal keys (Hillis-Steele), only
+  // as far as the longest run needs
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t pk = uint32_t(__builtin_amdgcn_ds_bpermute(((lane - d) & 63) << 2, int(k)));
+    const bool same = valid && lane >= d && pk == k;
+    if (__ballot(same) == 0) break;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      const float o = __int_as_float(__builtin_amdgcn_ds_bpermute(((lane - d) & 63) << 2, __float_as_int(x[j])));
+      x[j] = same ? x[j] + o : x[j];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NV; ++j) v[j] = x[j];
+  key = k;
+  return tail;
+}
 
 // D[i][j] = sum over the wave's 64 rays r of A_r[i] * B_r[j] (i, j < 16).
 // sA, sB: [64][kPad].  Lane l returns D[4*(l/16) + q][l%16], q = 0..3.
@@ -147,6 +237,22 @@ __device__ __forceinline__ void baked_scatter(const SceneArgs& S, const float u[
       for (int j = 1; j < 8; ++j) gv[j] = gf[j] * gb;
     }
     float* gbase = gtab + (size_t(l) * T_entries) * 9;
+    const int lane = threadIdx.x & 63;
+    if (S.N[l] >= NGPRT_BW_SORT_MIN_RES) {
+#pragma unroll 1
+      for (int k = 0; k < 8; ++k) {
+        uint32_t key = c.idx[k];
+        float x[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) x[j] = c.w[k] * gv[j];
+        if (wave_sort_merge<8>(key, have, x, lane)) {
+          float* dst = gbase + size_t(key) * 9;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) unsafeAtomicAdd(dst + j, x[j]);
+        }
+      }
+      continue;
+    }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       bool pending = have;
@@ -163,7 +269,7 @@ __device__ __forceinline__ void baked_scatter(const SceneArgs& S, const float u[
 #pragma unroll
           for (int j = 0; j < 8; ++j) x[j] += __shfl_xor(x[j], off, 64);
         }
-        if ((threadIdx.x & 63) == leader) {
+        if (lane == leader) {
           float* dst = gbase + size_t(key) * 9;
 #pragma unroll
           for (int j = 0; j < 8; ++j) unsafeAtomicAdd(dst + j, x[j]);
@@ -473,7 +579,22 @@ __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, c
         gv[8] = wl[l] * (gw - gff);
       }
       float* gbase = gtab + (size_t(l) * T_entries) * 9;
-      {
+      if (S.N[l] >= NGPRT_BW_SORT_MIN_RES) {
+        // equal entries summed after a sort across the wave; the last lane
+        // of each run issues the atomics
+#pragma unroll 1
+        for (int k = 0; k < 8; ++k) {
+          uint32_t key = c.idx[k];
+          float x[9];
+#pragma unroll
+          for (int j = 0; j < 9; ++j) x[j] = c.w[k] * gv[j];
+          if (wave_sort_merge<9>(key, have, x, lane)) {
+            float* dst = gbase + size_t(key) * 9;
+#pragma unroll
+            for (int j = 0; j < 9; ++j) unsafeAtomicAdd(dst + j, x[j]);
+          }
+        }
+      } else {
         // sum equal entries over the wave; one lane issues the atomics
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
