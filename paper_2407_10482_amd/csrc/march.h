@@ -23,6 +23,7 @@ struct MarchState {
   float t;            // contract: current lattice t
   float rho;          // box: (vox/step)/|d|
   float dn, dn2;      // |d|, |d|^2
+  float dt_in;        // contract: step / |d|, the lattice spacing inside the unit ball
   int k;              // lattice index of the next point to visit
   int next_read;      // box: first lattice index not known to be empty
   bool has_ball;      // contract: known-empty ball
@@ -73,6 +74,7 @@ __device__ __forceinline__ void march_init(const SceneArgs& S, const float* o, c
     m.rho = S.v_over_step / m.dn;
   } else {
     valid = valid && (m.dn2 > 0.0f);
+    m.dt_in = S.step / m.dn;
   }
   m.done = !valid;
 }
@@ -117,7 +119,6 @@ __device__ __forceinline__ bool march_next(const SceneArgs& S, MarchState& m, bo
       for (int a = 0; a < 3; ++a) x[a] = m.o[a] + tcur * m.d[a];
       float r2 = (x[0] * x[0] + x[1] * x[1]) + x[2] * x[2];
       if (!isfinite(r2)) { m.done = true; break; }
-      float jn;
       if (r2 > 1.0f) {
         float r = sqrtf(r2);
         float inv_r = 1.0f / r;
@@ -126,15 +127,16 @@ __device__ __forceinline__ bool march_next(const SceneArgs& S, MarchState& m, bo
         if (inv_r < S.step && xd >= 0.0f) { m.done = true; break; }
         float perp2 = fmaxf(m.dn2 - xd * xd, 0.0f);
         float rad = xd * (inv_r * inv_r);
-        jn = sqrtf((s * s) * perp2 + rad * rad);
+        const float jn = sqrtf((s * s) * perp2 + rad * rad);
 #pragma unroll
         for (int a = 0; a < 3; ++a) p[a] = s * x[a];
+        m.t = tcur + S.step / jn;
       } else {
-        jn = m.dn;
+        // inside the unit ball |J d| = |d|: the same quotient, taken once per ray
 #pragma unroll
         for (int a = 0; a < 3; ++a) p[a] = x[a];
+        m.t = tcur + m.dt_in;
       }
-      m.t = tcur + S.step / jn;
     }
     const int kcur = m.k;
     bool need = true;
