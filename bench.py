@@ -355,13 +355,13 @@ def cpu_baseline(sc, o, d, dtype, seconds):
     run before this process touches the GPU (the workers are forks)."""
     import multiprocessing as mp
     from oracle.distgrid import distance_grid_edt
-    from oracle.render import inputs_from_scene, render
+    from oracle.render import inputs_from_scene, render, scene_occupancy
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count() or 1
     cores = max(1, min(16, cores))
-    inp = inputs_from_scene(sc, distance_grid_edt(sc.occ), dtype)
+    inp = inputs_from_scene(sc, distance_grid_edt(scene_occupancy(sc)), dtype)
     n_total = len(o)
     # per-ray cost on one core, then a sample that keeps every core busy for
     # about `seconds`

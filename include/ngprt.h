@@ -410,6 +410,28 @@ int ngprt_render_backward_features(ngprt_ctx* ctx, int64_t n_rays, const float* 
  * desc.step (NGPRT_E_INVALID_ARG).  Later calls use the new step. */
 int ngprt_set_step(ngprt_ctx* ctx, float step);
 
+/* Marching-step auto-tuning of the paper's training (supplement, "Auto-tuning
+ * of Marching Step Size", Eq. S3), applied between training batches. */
+typedef struct ngprt_step_tuner {
+  float s0;           /* base step (the desc.step the scene was created with), > 0 */
+  float n_min;        /* N_min: the mean sample count below which the step shrinks (paper: 3) */
+  float kappa;        /* progressive multiplier, in [0, 1) (paper: 0.001) */
+  float gamma_min;    /* lower bound of the scaler, in (0, 1] (paper: 0.2217) */
+  float gamma;        /* the scaler, in (0, 1]; start at 1; updated by each call */
+  float mean_samples; /* output: the batch's mean evaluated samples per ray */
+} ngprt_step_tuner;
+
+/* One auto-tuning update after a training batch: N = the mean of
+ * dev_n_samples (int32 [n_rays], e.g. out->n_samples of the batch's render,
+ * summed on the GPU in a fixed order); gamma <- min(1, (1 + kappa) gamma) if
+ * N >= n_min, else max(gamma_min, (1 - kappa) gamma) (in double precision,
+ * then rounded to float32); then the context's step becomes gamma * s0
+ * rounded once to float32 (as ngprt_set_step; later calls use it).
+ * Synchronises the stream (the host needs N).  Invalid parameters, an empty
+ * batch or NULL pointers -> NGPRT_E_INVALID_ARG (nothing changed). */
+int ngprt_step_autotune(ngprt_ctx* ctx, int64_t n_rays, const int32_t* dev_n_samples,
+                        ngprt_step_tuner* tuner, void* stream);
+
 /* One Adam update (Kingma & Ba; the paper's training uses beta1 = 0.9,
  * beta2 = 0.99, eps = 1e-8, supplement "Optimization") over n float32
  * parameters in place: m, v are the moment buffers (caller-owned, zero

@@ -536,6 +536,18 @@ def render(inp: OracleInputs, o: np.ndarray, d: np.ndarray, naive: bool = False,
                         s_t=m["s_t"], s_pos=m["s_pos"], extra={"s_T": m["s_T"], "n_mem": m["n_mem"]})
 
 
+def scene_occupancy(scene) -> np.ndarray:
+    """The occupancy grid behind the distance grid (Sec. 4.3): the scene's
+    single grid, or, for an occupancy pyramid, its level of resolution
+    occ_res, OR-pooled here from the finest level."""
+    if getattr(scene, "occ_fine", None) is not None:
+        for level in pyramid.build_pyramid(scene.occ_fine, scene.cfg.occ_levels):
+            if level.shape[0] == scene.cfg.occ_res:
+                return level
+        raise ValueError("occ_res is not a resolution of the occupancy pyramid")
+    return scene.occ
+
+
 def inputs_from_scene(scene, dist: np.ndarray, dtype: int = DT_F32) -> OracleInputs:
     cfg = scene.cfg
     extra = {}
@@ -545,7 +557,7 @@ def inputs_from_scene(scene, dist: np.ndarray, dtype: int = DT_F32) -> OracleInp
         extra.update(coarse_res=cfg.coarse_res, block_index=scene.block_index, atlas=scene.atlas,
                      coarse_default=scene.default, aggregation=getattr(cfg, "aggregation", 0),
                      gate_params=tuple(np.asarray(getattr(cfg, "gate_params", ()), F32)))
-    return OracleInputs(tables=scene.tables, occ=scene.occ, dist=dist, mlp=scene.mlp,
+    return OracleInputs(tables=scene.tables, occ=scene_occupancy(scene), dist=dist, mlp=scene.mlp,
                         resolutions=list(cfg.resolutions), domain=cfg.domain,
                         roi_half=cfg.roi_half, step=cfg.step, max_samples=cfg.max_samples,
                         t_threshold=cfg.t_threshold, dtype=dtype, mlp_dims=cfg.mlp_dims, **extra)

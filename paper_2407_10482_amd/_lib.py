@@ -56,6 +56,10 @@ class NgprtProposalCfg(ctypes.Structure):
                 ("far_guard", ctypes.c_float)]
 
 
+class NgprtStepTuner(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_float) for k in ("s0", "n_min", "kappa", "gamma_min", "gamma", "mean_samples")]
+
+
 # (name, restype, argtypes)
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -87,6 +91,7 @@ SIGNATURES = [
     ("ngprt_view_mlp_backward", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P]),
     ("ngprt_render_backward_features", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P]),
     ("ngprt_set_step", ctypes.c_int, [_P, ctypes.c_float]),
+    ("ngprt_step_autotune", ctypes.c_int, [_P, _I64, _P, ctypes.POINTER(NgprtStepTuner), _P]),
     ("ngprt_adam_step", ctypes.c_int, [_I64, _P, _P, _P, _P, _I32, ctypes.c_float, ctypes.c_float,
                                        ctypes.c_float, ctypes.c_float, _P]),
     ("ngprt_proposal_infer", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P]),

@@ -2,6 +2,7 @@
 // Validation is pure host code so it runs (and is tested) without a GPU.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -185,6 +186,7 @@ void ngprt_destroy(ngprt_ctx* ctx) {
   if (ctx->prop_grad) (void)hipFree(ctx->prop_grad);
   if (ctx->prop_net) (void)hipFree(ctx->prop_net);
   if (ctx->prop_tmp) (void)hipFree(ctx->prop_tmp);
+  if (ctx->count_ws) (void)hipFree(ctx->count_ws);
   if (ctx->mlp_rec) (void)hipFree(ctx->mlp_rec);
   if (ctx->cidx) (void)hipFree(ctx->cidx);
   if (ctx->catlas) (void)hipFree(ctx->catlas);
@@ -561,6 +563,35 @@ int ngprt_render_backward(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origi
                           void* stream) {
   return ngprt_render_backward_reg(ctx, n_rays, dev_origins, dev_dirs, dev_grad_rgb, nullptr, dev_grad_tables,
                                    dev_grad_mlp, stream);
+}
+
+int ngprt_step_autotune(ngprt_ctx* ctx, int64_t n_rays, const int32_t* dev_n_samples, ngprt_step_tuner* tuner,
+                        void* stream) {
+  if (!ctx) return NGPRT_E_INVALID_ARG;
+  if (!tuner || !dev_n_samples) return fail(ctx, NGPRT_E_INVALID_ARG, "NULL pointer");
+  if (n_rays < 1) return fail(ctx, NGPRT_E_INVALID_ARG, "empty batch");
+  const ngprt_step_tuner& t = *tuner;
+  if (!(t.s0 > 0.0f) || !std::isfinite(t.s0) || !std::isfinite(t.n_min) || !(t.kappa >= 0.0f) ||
+      !(t.kappa < 1.0f) || !(t.gamma_min > 0.0f) || !(t.gamma_min <= 1.0f) || !(t.gamma > 0.0f) ||
+      !(t.gamma <= 1.0f))
+    return fail(ctx, NGPRT_E_INVALID_ARG, "bad auto-tuning parameters");
+  long long total = 0;
+  int rc = sum_counts(ctx, n_rays, dev_n_samples, &total, (hipStream_t)stream);
+  if (rc) return rc;
+  // Eq. S3, in double precision on the host
+  const double mean = double(total) / double(n_rays);
+  double g = t.gamma;
+  g = mean >= double(t.n_min) ? std::min(1.0, (1.0 + double(t.kappa)) * g)
+                              : std::max(double(t.gamma_min), (1.0 - double(t.kappa)) * g);
+  const float gf = float(g);
+  const float step = float(double(gf) * double(t.s0));
+  ngprt_desc d = ctx->desc;
+  d.step = step;
+  if (ngprt_validate_desc(&d) != NGPRT_OK) return fail(ctx, NGPRT_E_INVALID_ARG, "auto-tuned step is invalid");
+  ctx->desc.step = step;
+  tuner->gamma = gf;
+  tuner->mean_samples = float(mean);
+  return NGPRT_OK;
 }
 
 int ngprt_set_step(ngprt_ctx* ctx, float step) {

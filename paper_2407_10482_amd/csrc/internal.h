@@ -109,6 +109,7 @@ struct ngprt_ctx {
   void* prop_net = nullptr;   // loaded proposal network: A-operand tiles [32][64] uint2 + biases [132]
   void* prop_tmp = nullptr;   // the same layout for ngprt_proposal_infer's caller-owned weights
   bool prop_loaded = false;
+  void* count_ws = nullptr;   // step auto-tuning: per-block partial sums of sample counts + total
   void* prop_grad = nullptr;  // proposal gradient [7556] when the caller wants none
   int32_t* cidx = nullptr;    // baked model: block index grid [nb^3]
   float* catlas = nullptr;    // baked model: atlas [n_blocks][512][Cpad]
@@ -152,6 +153,8 @@ int launch_backward_ws(ngprt_ctx* ctx, int64_t n, const float* o, const float* d
                        const float* grad_dist, const float* ups, float* gtab, float* gatlas, float* gmlp,
                        float* workspace, hipStream_t s);
 int init_static_scratch(ngprt_ctx* ctx);
+// sum of n int32 counts on the GPU in a fixed order; synchronises the stream
+int sum_counts(ngprt_ctx* ctx, int64_t n, const int32_t* counts, long long* host_total, hipStream_t s);
 int check_backward_args(ngprt_ctx* ctx, const float* o, const float* d, const float* grad_rgb,
                         const float* grad_tables, const float* grad_mlp);
 int launch_view_mlp_backward(ngprt_ctx* ctx, int64_t n, const float* d, const float* c_d, const float* feat,

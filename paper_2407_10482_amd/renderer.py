@@ -5,6 +5,7 @@ from __future__ import annotations
 import ctypes
 from typing import Dict, Optional, Sequence
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -65,6 +66,10 @@ class Renderer:
         ctx = ctypes.c_void_p()
         check(self.lib.ngprt_create(ctypes.byref(self.desc), ctypes.byref(ctx)))
         self.ctx = ctx
+        # bumped by every call that changes what a render of this context
+        # computes (loads, step changes): the autograd backward checks that
+        # the scene its forward rendered is still the loaded one
+        self.load_gen = 0
 
     @classmethod
     def from_config(cls, cfg, table_dtype: Optional[int] = None, use_distance: bool = True) -> "Renderer":
@@ -88,21 +93,25 @@ class Renderer:
 
     # ---------------------------------------------------------------- loading
     def load_tables(self, tables: torch.Tensor):
+        self.load_gen += 1
         _dev(tables, torch.float32, (self.L, self.T, 9), "tables")
         check(self.lib.ngprt_load_tables(self.ctx, _ptr(tables), _stream()), self.ctx)
 
     def load_occupancy(self, occ: torch.Tensor, dist: Optional[torch.Tensor] = None):
+        self.load_gen += 1
         _dev(occ, torch.uint8, (self.R, self.R, self.R), "occ")
         if dist is not None:
             _dev(dist, torch.uint8, (self.R, self.R, self.R), "dist")
         check(self.lib.ngprt_load_occupancy(self.ctx, _ptr(occ), _ptr(dist), _stream()), self.ctx)
 
     def load_occupancy_pyramid(self, occ_fine: torch.Tensor):
+        self.load_gen += 1
         F = self.occ_fine_res
         _dev(occ_fine, torch.uint8, (F, F, F), "occ_fine")
         check(self.lib.ngprt_load_occupancy_pyramid(self.ctx, _ptr(occ_fine), _stream()), self.ctx)
 
     def load_mlp(self, params: torch.Tensor):
+        self.load_gen += 1
         _dev(params, torch.float32, (self.n_mlp,), "mlp params")
         check(self.lib.ngprt_load_mlp(self.ctx, _ptr(params), _stream()), self.ctx)
 
@@ -110,6 +119,7 @@ class Renderer:
         """Baked model: block index grid int32 [nb]^3, atlas float32
         [n_blocks, 8, 8, 8, C], default vector (C floats, host); C = 8 + 2L
         (8 + L for Shared-Att (V), 8 for constant gates and SUM)."""
+        self.load_gen += 1
         nb = (self.coarse_res + 1 + 7) // 8
         C = _lib.coarse_channels(self.L, self.aggregation)
         _dev(block_index, torch.int32, (nb, nb, nb), "block_index")
@@ -349,6 +359,7 @@ def _renderer_backward_features(self: Renderer, origins, dirs, grad_cf, grad_tab
 
 
 def _renderer_set_step(self: Renderer, step: float):
+    self.load_gen += 1
     check(self.lib.ngprt_set_step(self.ctx, float(step)), self.ctx)
     self.step = float(step)
 
@@ -362,23 +373,29 @@ Renderer.set_step = _renderer_set_step
 
 
 class StepAutoTuner:
-    """Marching-step auto-tuning of the paper's training (supplement Eq. S3):
-    after each batch, gamma <- min(1, (1 + kappa) gamma) when the batch's
-    mean evaluated-sample count reaches n_min, else
-    max(gamma_min, (1 - kappa) gamma); the renderer's step is gamma * s0."""
+    """Marching-step auto-tuning of the paper's training (supplement Eq. S3),
+    run by the library: update(n_samples) takes a batch's per-ray sample
+    counts (int32 [n] on the GPU), updates gamma and sets the renderer's step
+    to gamma * s0."""
 
     def __init__(self, renderer: Renderer, s0: float, n_min: float = 3.0, kappa: float = 0.001,
                  gamma_min: float = 0.2217, gamma: float = 1.0):
-        self.r, self.s0 = renderer, float(s0)
-        self.n_min, self.kappa, self.gamma_min, self.gamma = n_min, kappa, gamma_min, gamma
+        self.r = renderer
+        self.state = _lib.NgprtStepTuner(float(s0), float(n_min), float(kappa), float(gamma_min), float(gamma),
+                                         0.0)
 
-    def update(self, mean_samples: float) -> float:
-        if mean_samples >= self.n_min:
-            self.gamma = min(1.0, (1.0 + self.kappa) * self.gamma)
-        else:
-            self.gamma = max(self.gamma_min, (1.0 - self.kappa) * self.gamma)
-        self.r.set_step(self.gamma * self.s0)
-        return self.gamma
+    @property
+    def gamma(self) -> float:
+        return self.state.gamma
+
+    def update(self, n_samples: torch.Tensor) -> float:
+        n = n_samples.shape[0]
+        _dev(n_samples, torch.int32, (n,), "n_samples")
+        self.r.load_gen += 1
+        check(self.r.lib.ngprt_step_autotune(self.r.ctx, n, _ptr(n_samples), ctypes.byref(self.state), _stream()),
+              self.r.ctx)
+        self.r.step = float(np.float32(float(self.state.gamma) * float(self.state.s0)))
+        return self.state.gamma
 
 
 def adam_step(param: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int,
@@ -388,6 +405,14 @@ def adam_step(param: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch
         _dev(t, torch.float32, param.shape, name)
     check(load_library().ngprt_adam_step(param.numel(), _ptr(param), _ptr(grad), _ptr(m), _ptr(v), int(step),
                                          float(lr), float(beta1), float(beta2), float(eps), _stream()))
+
+
+def _same_scene(renderer: Renderer, gen: int):
+    """The library's backward recomputes the forward from the scene loaded in
+    the renderer: refuse when it changed since the forward."""
+    if renderer.load_gen != gen:
+        raise RuntimeError("the renderer's tables, MLP, grids or step changed between this render's forward "
+                           "and its backward; render again (or use one renderer per differentiable model)")
 
 
 class RenderFunction(torch.autograd.Function):
@@ -407,6 +432,7 @@ class RenderFunction(torch.autograd.Function):
             out["dist_loss"] = torch.empty((n,), dtype=torch.float32, device=origins.device)
         renderer.render(origins, dirs, out=out)
         ctx.renderer = renderer
+        ctx.load_gen = renderer.load_gen
         ctx.with_dist = with_dist
         ctx.save_for_backward(origins, dirs)
         if not with_dist:
@@ -419,6 +445,7 @@ class RenderFunction(torch.autograd.Function):
     def backward(ctx, grad_rgb, grad_dist):
         origins, dirs = ctx.saved_tensors
         r = ctx.renderer
+        _same_scene(r, ctx.load_gen)
         gt = torch.zeros((r.L, r.T, 9), dtype=torch.float32, device=origins.device)
         gm = torch.zeros((r.n_mlp,), dtype=torch.float32, device=origins.device)
         if grad_rgb is None:
@@ -445,6 +472,7 @@ class BakedRenderFunction(torch.autograd.Function):
             out["dist_loss"] = torch.empty((n,), dtype=torch.float32, device=origins.device)
         renderer.render(origins, dirs, out=out)
         ctx.renderer = renderer
+        ctx.load_gen = renderer.load_gen
         ctx.with_dist = with_dist
         ctx.atlas_shape = tuple(atlas.shape)
         ctx.save_for_backward(origins, dirs)
@@ -458,6 +486,7 @@ class BakedRenderFunction(torch.autograd.Function):
     def backward(ctx, grad_rgb, grad_dist):
         origins, dirs = ctx.saved_tensors
         r = ctx.renderer
+        _same_scene(r, ctx.load_gen)
         gt = torch.zeros((r.L, r.T, 9), dtype=torch.float32, device=origins.device)
         ga = torch.zeros(ctx.atlas_shape, dtype=torch.float32, device=origins.device)
         gm = torch.zeros((r.n_mlp,), dtype=torch.float32, device=origins.device)
@@ -490,6 +519,7 @@ class ViewRenderFunction(torch.autograd.Function):
             out["dist_loss"] = torch.empty((n,), dtype=torch.float32, device=dev)
         renderer.render(origins, dirs, out=out)
         ctx.renderer = renderer
+        ctx.load_gen = renderer.load_gen
         ctx.with_dist = with_dist
         ctx.atlas_shape = None if atlas is None else tuple(atlas.shape)
         ctx.save_for_backward(origins, dirs, out["c_d"], out["feat"])
@@ -503,6 +533,7 @@ class ViewRenderFunction(torch.autograd.Function):
     def backward(ctx, grad_rgb, grad_dist):
         origins, dirs, c_d, feat = ctx.saved_tensors
         r = ctx.renderer
+        _same_scene(r, ctx.load_gen)
         dev = origins.device
         if grad_rgb is None:
             grad_rgb = torch.zeros((origins.shape[0], 3), dtype=torch.float32, device=dev)

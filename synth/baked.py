@@ -91,10 +91,7 @@ def make_baked_scene(cfg: SceneConfig, seed=None) -> BakedScene:
     occ_fine = None
     if cfg.occ_levels > 0:
         occ_fine = occupancy_from_blobs(dataclasses.replace(cfg, occ_res=cfg.occ_fine_res), mu, sig)
-        occ = occ_fine
-        while occ.shape[0] > cfg.occ_res:
-            R = occ.shape[0] // 2
-            occ = occ.reshape(R, 2, R, 2, R, 2).max(axis=(1, 3, 5)).astype(np.uint8)
+        occ = None           # the coarser levels are the method's (OR pooling)
     else:
         occ = occupancy_from_blobs(cfg, mu, sig)
     nb = n_blocks_per_axis(cfg.coarse_res)

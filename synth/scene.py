@@ -135,14 +135,11 @@ def make_scene(cfg: SceneConfig, seed: Optional[int] = None) -> Scene:
     mu, sig = _blobs(cfg, rng_geo)
     occ_fine = None
     if cfg.occ_levels > 0:
-        # the finest pyramid level from the blobs; the grid at occ_res (the
-        # distance grid's) is its OR-pooled level
+        # only the finest pyramid level, from the blobs: the coarser levels and
+        # the grid behind the distance grid are the method's (OR pooling)
         fine_cfg = dataclasses.replace(cfg, occ_res=cfg.occ_fine_res)
         occ_fine = occupancy_from_blobs(fine_cfg, mu, sig)
-        occ = occ_fine
-        while occ.shape[0] > cfg.occ_res:
-            R = occ.shape[0] // 2
-            occ = occ.reshape(R, 2, R, 2, R, 2).max(axis=(1, 3, 5)).astype(np.uint8)
+        occ = None
     else:
         occ = occupancy_from_blobs(cfg, mu, sig)
     rng_val = np.random.default_rng(1_000_003 + (cfg.seed if seed is None else seed))

@@ -5,7 +5,7 @@ import numpy as np
 
 import synth
 from oracle.distgrid import distance_grid_edt
-from oracle.render import inputs_from_scene
+from oracle.render import inputs_from_scene, scene_occupancy
 
 
 @functools.lru_cache(maxsize=4)
@@ -16,7 +16,7 @@ def scene_and_dist(name: str, dtype: int = 0):
         sc = make_baked_scene(cfg)
     else:
         sc = synth.make_scene(cfg)
-    dist = distance_grid_edt(sc.occ)
+    dist = distance_grid_edt(scene_occupancy(sc))
     return sc, dist
 
 

@@ -7,7 +7,7 @@ import pytest
 
 import synth
 from oracle.exact32 import F32
-from oracle.render import fused32, fused64, grid_coords32, render
+from oracle.render import fused32, fused64, grid_coords32, render, scene_occupancy
 
 from helpers import gpu_renderer, oracle_inputs, scene_and_dist, to_gpu
 
@@ -131,7 +131,7 @@ def test_baked_hd_full_frame_sampled():
     from paper_2407_10482_amd.renderer import Renderer
     cfg = synth.baked_hd(n_fine=2)
     sc = make_baked_scene(cfg)
-    dist = distance_grid_edt(sc.occ)
+    dist = distance_grid_edt(scene_occupancy(sc))
     o, d, _ = synth.scene_rays(cfg)
     r = Renderer.from_config(cfg)
     r.load_scene(torch.from_numpy(sc.tables).cuda(), torch.from_numpy(sc.occ).cuda(),

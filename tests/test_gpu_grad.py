@@ -134,3 +134,27 @@ def test_autograd_function_and_training_reduces_loss():
         tabs, mlps = tabs.detach(), mlps.detach()
     print("losses", losses[0], losses[-1], flush=True)
     assert losses[-1] < 0.5 * losses[0]
+
+
+def test_autograd_refuses_a_scene_changed_after_the_forward():
+    """The backward recomputes the forward from the renderer's loaded scene:
+    a load (here another model's tables) between forward and backward is
+    refused instead of giving the other model's gradients."""
+    import torch
+    from paper_2407_10482_amd.renderer import render_differentiable
+    print("[autograd: scene changed]", flush=True)
+    cfg, sc, o, d, target, s_ray, s_pos, tab, g_rgb = _problem(16)
+    r = gpu_renderer("tiny")
+    go, gd = to_gpu(o, d)
+    tables = torch.from_numpy(sc.tables).cuda().requires_grad_(True)
+    mlp = torch.from_numpy(sc.mlp).cuda().requires_grad_(True)
+    rgb = render_differentiable(r, tables, mlp, go, gd)
+    other = synth.make_scene(cfg, seed=1)
+    r.load_tables(torch.from_numpy(other.tables).cuda())
+    with pytest.raises(RuntimeError, match="changed between"):
+        rgb.sum().backward()
+    # a fresh forward on the current scene differentiates as usual
+    rgb2 = render_differentiable(r, tables, mlp, go, gd)
+    rgb2.sum().backward()
+    torch.cuda.synchronize()
+    assert tables.grad is not None and torch.isfinite(tables.grad).all()

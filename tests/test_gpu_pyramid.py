@@ -9,7 +9,7 @@ import synth
 from oracle import pyramid
 from oracle.distgrid import distance_grid_edt
 from oracle.exact32 import F32
-from oracle.render import CONTRACT, OracleInputs, inputs_from_scene, render
+from oracle.render import CONTRACT, OracleInputs, inputs_from_scene, render, scene_occupancy
 
 from helpers import gpu_renderer, oracle_inputs, scene_and_dist, to_gpu
 
@@ -110,7 +110,7 @@ def test_pyramid_api_errors():
     sc, _ = scene_and_dist("tiny_pyramid")
     r = gpu_renderer("tiny_pyramid")
     with pytest.raises(NgprtError):                       # single-grid load on a pyramid context
-        r.load_occupancy(torch.from_numpy(sc.occ).cuda())
+        r.load_occupancy(torch.zeros((sc.cfg.occ_res,) * 3, dtype=torch.uint8, device="cuda"))
     h = gpu_renderer("tiny")
     h.occ_fine_res = 128
     with pytest.raises(NgprtError):                       # pyramid load on a single-grid context
@@ -132,7 +132,7 @@ def test_hd_pyramid_full_frame_sampled():
     go, gd = to_gpu(o, d)
     rng = np.random.default_rng(0)
     sel = np.sort(rng.choice(len(o), size=1500, replace=False))
-    inp = inputs_from_scene(sc, distance_grid_edt(sc.occ))
+    inp = inputs_from_scene(sc, distance_grid_edt(scene_occupancy(sc)))
     reads = {}
     for use_dist in (True, False):
         r2 = Renderer.from_config(cfg, use_distance=use_dist)

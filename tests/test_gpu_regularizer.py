@@ -112,9 +112,26 @@ def test_set_step_and_autotuner():
     assert np.abs(_np(out["rgb"]).astype(np.float64) - ref.rgb).max() < 1e-5
     with pytest.raises(NgprtError):
         r.set_step(0.0)
-    tuner = StepAutoTuner(r, cfg.step)
+    kappa = 0.1                                # large, to reach the floor within the test
+    tuner = StepAutoTuner(r, cfg.step, kappa=kappa)
     g = 1.0
-    for mean in [5.0, 2.0, 2.0, 1.0, 3.0, 4.0] + [0.5] * 50:
-        g = distortion.autotune_gamma(g, mean)
-        assert abs(tuner.update(mean) - g) < 1e-15
+    rng = np.random.default_rng(3)
+    # per-ray sample counts whose means straddle N_min = 3 (ragged batch sizes)
+    for i, target in enumerate([5.0, 2.0, 2.0, 1.0, 3.0, 4.0] + [0.5] * 40):
+        n = 1000 + 37 * i
+        counts = rng.poisson(target, size=n).astype(np.int32)
+        mean = counts.astype(np.float64).sum() / n
+        g = distortion.autotune_gamma(g, mean, kappa=kappa)
+        got = tuner.update(torch.from_numpy(counts).cuda())
+        assert abs(got - g) <= 2e-7 * g, (i, got, g)
+        assert abs(tuner.state.mean_samples - mean) <= 1e-6 * mean
+        g = got                                # the library keeps gamma in float32
+    assert abs(tuner.gamma - 0.2217) < 1e-6    # reached the floor
+    # the renderer marches with the tuned step: same samples as a context created with it
+    out2 = r.render(go, gd)
+    r2 = gpu_renderer("tiny", step=float(np.float32(np.float64(np.float32(tuner.gamma)) * np.float64(cfg.step))))
+    ref2 = r2.render(go, gd)
+    assert np.array_equal(_np(out2["n_samples"]), _np(ref2["n_samples"]))
+    with pytest.raises(NgprtError):
+        tuner.update(torch.zeros((0,), dtype=torch.int32, device="cuda"))
     torch.cuda.synchronize()

@@ -6,7 +6,7 @@ import pytest
 
 import synth
 from oracle.exact32 import F32
-from oracle.render import render
+from oracle.render import render, scene_occupancy
 
 from helpers import gpu_renderer, oracle_inputs, scene_and_dist, to_gpu
 
@@ -80,5 +80,5 @@ def test_view_mlp_hd_full_frame_sampled():
     r.render(go, gd, out=out)
     torch.cuda.synchronize()
     sel = np.sort(np.random.default_rng(0).choice(len(o), size=1000, replace=False))
-    ref = render(inputs_from_scene(sc, distance_grid_edt(sc.occ)), o[sel], d[sel])
+    ref = render(inputs_from_scene(sc, distance_grid_edt(scene_occupancy(sc))), o[sel], d[sel])
     assert np.abs(_np(out["rgb"])[sel].astype(np.float64) - ref.rgb).max() < COLOUR_TOL

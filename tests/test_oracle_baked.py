@@ -12,7 +12,7 @@ from scipy.ndimage import map_coordinates
 from oracle import baked
 from oracle.distgrid import distance_grid_edt
 from oracle.exact32 import F32
-from oracle.render import BOX, OracleInputs, fused32, fused64, render
+from oracle.render import BOX, OracleInputs, fused32, fused64, render, scene_occupancy
 
 LC = 20            # 21 vertices per axis -> 3 blocks of 8 (the last one partial)
 
@@ -255,7 +255,7 @@ def test_baked_scene_march_skip_equals_naive():
     from oracle.render import inputs_from_scene
     cfg = synth.CONFIGS["baked_tiny"]()
     sc = make_baked_scene(cfg)
-    inp = inputs_from_scene(sc, distance_grid_edt(sc.occ))
+    inp = inputs_from_scene(sc, distance_grid_edt(scene_occupancy(sc)))
     o, d, _ = synth.scene_rays(cfg)
     sel = slice(0, 4096, 13)
     a = render(inp, o[sel], d[sel])
@@ -274,7 +274,7 @@ def test_baked_gradient_matches_finite_differences():
     from oracle.render import inputs_from_scene
     cfg = synth.baked_tiny()
     sc = make_baked_scene(cfg)
-    inp = inputs_from_scene(sc, distance_grid_edt(sc.occ))
+    inp = inputs_from_scene(sc, distance_grid_edt(scene_occupancy(sc)))
     o, d, _ = synth.scene_rays(cfg)
     o, d = o[::16], d[::16]
     s_ray, s_pos, _ = frozen_samples(inp, o, d)

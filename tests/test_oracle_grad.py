@@ -8,14 +8,14 @@ import synth
 from oracle.distgrid import distance_grid_edt
 from oracle.grad import (adam_step, backward64, fd_mlp_grad, fd_table_grad, forward64,
                          frozen_samples, loss64, mse_grad, pick_entries)
-from oracle.render import inputs_from_scene, render
+from oracle.render import inputs_from_scene, render, scene_occupancy
 
 
 def _setup(n_rays_stride=8):
     cfg = synth.tiny()
     sc = synth.make_scene(cfg)
     teacher = synth.make_scene(cfg, seed=1)
-    inp = inputs_from_scene(sc, distance_grid_edt(sc.occ))
+    inp = inputs_from_scene(sc, distance_grid_edt(scene_occupancy(sc)))
     o, d, _ = synth.scene_rays(cfg)
     o, d = o[::n_rays_stride], d[::n_rays_stride]
     s_ray, s_pos, _ = frozen_samples(inp, o, d)

@@ -11,7 +11,8 @@ from oracle.distgrid import (dilate26, distance_grid_bruteforce, distance_grid_e
                              distance_grid_full_bruteforce)
 from oracle.exact32 import F32, exp32
 from oracle.hashgrid import corners32, corners64, spatial_hash, spatial_hash_py
-from oracle.render import (BOX, CONTRACT, OracleInputs, fused32, fused64, mlp64, render)
+from oracle.render import (BOX, CONTRACT, OracleInputs, fused32, fused64, mlp64, render,
+                           scene_occupancy)
 
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
@@ -248,7 +249,7 @@ def test_distance_grid_single_voxel_closed_form():
 def test_distance_grid_conservative_and_tight_on_tiny_scene():
     from synth import make_scene, tiny
     sc = make_scene(tiny())
-    G = distance_grid_edt(sc.occ)
+    G = distance_grid_edt(scene_occupancy(sc))
     rng = np.random.default_rng(11)
     vox = rng.integers(0, 64, size=(400, 3))
     bf = distance_grid_bruteforce(sc.occ, vox)
@@ -308,7 +309,7 @@ def test_weights_telescope_to_one_minus_transmittance():
     sc = make_scene(tiny())
     tab = sc.tables.copy()
     tab[:, :, 1:4] = 1.0                          # unit colour everywhere
-    inp = OracleInputs(tables=tab, occ=sc.occ, dist=distance_grid_edt(sc.occ), mlp=sc.mlp,
+    inp = OracleInputs(tables=tab, occ=sc.occ, dist=distance_grid_edt(scene_occupancy(sc)), mlp=sc.mlp,
                        resolutions=sc.cfg.resolutions, domain=BOX, roi_half=1.0,
                        step=sc.cfg.step, max_samples=1024, t_threshold=1e-4)
     o, d, _ = scene_rays(sc.cfg)

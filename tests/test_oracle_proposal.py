@@ -79,10 +79,10 @@ def test_labels_from_decided_samples():
 def test_interval_march_with_exact_labels_equals_plain():
     import synth
     from oracle.distgrid import distance_grid_edt
-    from oracle.render import inputs_from_scene, render, render_proposal
+    from oracle.render import inputs_from_scene, render, render_proposal, scene_occupancy
     cfg = synth.tiny()
     sc = synth.make_scene(cfg)
-    inp = inputs_from_scene(sc, distance_grid_edt(sc.occ))
+    inp = inputs_from_scene(sc, distance_grid_edt(scene_occupancy(sc)))
     o, d, _ = synth.scene_rays(cfg)
     o, d = o[::9], d[::9]
     ref = render(inp, o, d)
@@ -121,10 +121,10 @@ def test_interval_render_is_a_filter_of_the_exhaustive_march():
     is the plain march, with the reads of both marches counted."""
     import synth
     from oracle.distgrid import distance_grid_edt
-    from oracle.render import inputs_from_scene, march, ray_box32, render, render_proposal
+    from oracle.render import inputs_from_scene, march, ray_box32, render, render_proposal, scene_occupancy
     cfg = synth.tiny()
     sc = synth.make_scene(cfg)
-    inp = inputs_from_scene(sc, distance_grid_edt(sc.occ))
+    inp = inputs_from_scene(sc, distance_grid_edt(scene_occupancy(sc)))
     o, d, _ = synth.scene_rays(cfg)
     o, d = o[::11], d[::11]
     n = len(o)

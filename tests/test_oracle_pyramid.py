@@ -11,7 +11,7 @@ import synth
 from oracle import pyramid
 from oracle.distgrid import distance_grid_edt
 from oracle.exact32 import F32
-from oracle.render import BOX, CONTRACT, OracleInputs, inputs_from_scene, render
+from oracle.render import BOX, CONTRACT, OracleInputs, inputs_from_scene, render, scene_occupancy
 
 
 def test_pyramid_is_or_of_children():
@@ -77,7 +77,7 @@ def test_skip_march_equals_exhaustive_finest_level(domain, use_dist):
 def test_distance_grid_reduces_marching_points_on_tiny_scene():
     cfg = synth.tiny_pyramid()
     sc = synth.make_scene(cfg)
-    inp = inputs_from_scene(sc, distance_grid_edt(sc.occ))
+    inp = inputs_from_scene(sc, distance_grid_edt(scene_occupancy(sc)))
     o, d, _ = synth.scene_rays(cfg)
     sel = slice(0, 4096, 5)
     with_g = render(inp, o[sel], d[sel])
