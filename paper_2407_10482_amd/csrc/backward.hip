@@ -23,9 +23,9 @@
 //          of each run issues the atomics.  Measured on 2^18-ray training
 //          batches (backward kernel): 16 x 2^19 tables 174 -> 92 ms, 8 x 2^14
 //          35 -> 14 ms against one pass per distinct entry with a butterfly
-//          sum each; with the sort in place the float atomics themselves
-//          (about 2.9 G per 16 x 2^19 step, nearly all at the finest levels,
-//          where a wave's entries are all distinct) take ~78 ms of the 92.
+//          sum each; spreading each run's 9 channel atomics over neighbouring
+//          lanes of one instruction (scatter_runs) then 92 -> 20 ms and
+//          14 -> 7 ms.
 //          The baked model scatters into its fine levels and coarse atlas
 //          rows instead (baked_scatter).
 // The per-wave MLP partials are then added in a fixed order (reduce.h).
@@ -69,6 +69,40 @@ __device__ __forceinline__ uint32_t lane_xor(uint32_t v, int lane) {
   }
   if constexpr (J == 16) return uint32_t(__builtin_amdgcn_ds_swizzle(x, 0x401F));
   return uint32_t(__builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, x));
+}
+
+// The atomics of a merged level.  The 9 (NV) channels of each run's row go to
+// neighbouring lanes of one atomic instruction, so an instruction carries the
+// rows of about 7 runs, 9 consecutive floats each: the tail lanes (one per
+// run) stage key and values in this wave's LDS slab `stage` (64 x 10 words),
+// then lane q of each pass adds value q % NV of run q / NV.  Measured on
+// 2^18-ray training batches (backward kernel, 16 x 2^19 / 8 x 2^14 tables):
+// 91.6 / 14.5 ms with 9 one-lane-per-run instructions, 19.8 / 7.0 ms spread
+// (the same-line atomics of one instruction are combined on their way to
+// memory).
+template <int NV>
+__device__ __forceinline__ void scatter_runs(float* __restrict__ gbase, bool tail, uint32_t key, const float x[NV],
+                                             int lane, float* stage) {
+  const uint64_t tm = __ballot(tail);
+  const int m = __popcll(tm);
+  if (tail) {
+    const int rank = __builtin_amdgcn_mbcnt_hi(uint32_t(tm >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(tm), 0));
+    float* row = stage + rank * 10;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) row[j] = x[j];
+    row[9] = __uint_as_float(key);
+  }
+  // the other lanes' staged rows are read below: a wave-scope fence orders
+  // the LDS stores before the loads (and the next call's stores after them)
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  for (int q = lane; q < NV * m; q += 64) {
+    const int t = q / NV, c = q - t * NV;
+    const float* row = stage + t * 10;
+    unsafeAtomicAdd(gbase + size_t(__float_as_uint(row[9])) * 9 + c, row[c]);
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 }
 
 // one compare-exchange stage of a bitonic sort over the wave's 64 lanes
@@ -157,7 +191,8 @@ __device__ __forceinline__ bf32x4 wave_outer_sum(const float* sA, const float* s
 // [n_blocks][8][8][8][C], C = 8 + 2 L.
 template <int LMAX>
 __device__ __forceinline__ void baked_scatter(const SceneArgs& S, const float u[3], bool have, const float gf[8],
-                                              float* __restrict__ gtab, float* __restrict__ gatlas) {
+                                              float* __restrict__ gtab, float* __restrict__ gatlas,
+                                              float* stage) {
   static_assert(LMAX <= 4, "the coarse row holds at most 16 channels");
   constexpr int CMAX = 8 + 2 * LMAX;
   const int C = 8 + 2 * S.L;
@@ -245,11 +280,8 @@ __device__ __forceinline__ void baked_scatter(const SceneArgs& S, const float u[
         float x[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) x[j] = c.w[k] * gv[j];
-        if (wave_sort_merge<8>(key, have, x, lane)) {
-          float* dst = gbase + size_t(key) * 9;
-#pragma unroll
-          for (int j = 0; j < 8; ++j) unsafeAtomicAdd(dst + j, x[j]);
-        }
+        const bool tail = wave_sort_merge<8>(key, have, x, lane);
+        scatter_runs<8>(gbase, tail, key, x, lane, stage);
       }
       continue;
     }
@@ -324,6 +356,7 @@ __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, c
                                                        const float* __restrict__ P) {
   __shared__ float sA_all[4][64 * kPad];
   __shared__ float sB_all[4][64 * kPad];
+  __shared__ float stage_all[4][64 * 10];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t ray = (int64_t(blockIdx.x) * 4 + wave) * 64 + lane;
@@ -550,7 +583,7 @@ __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, c
       for (int l = 0; l < LMAX; ++l) wl[l] = 0.0f;
     }
     if constexpr (MODEL == 1) {
-      baked_scatter<LMAX>(S, u, have, gf, gtab, gatlas);
+      baked_scatter<LMAX>(S, u, have, gf, gtab, gatlas, stage_all[wave]);
       continue;
     }
 #pragma unroll
@@ -588,11 +621,8 @@ __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, c
           float x[9];
 #pragma unroll
           for (int j = 0; j < 9; ++j) x[j] = c.w[k] * gv[j];
-          if (wave_sort_merge<9>(key, have, x, lane)) {
-            float* dst = gbase + size_t(key) * 9;
-#pragma unroll
-            for (int j = 0; j < 9; ++j) unsafeAtomicAdd(dst + j, x[j]);
-          }
+          const bool tail = wave_sort_merge<9>(key, have, x, lane);
+          scatter_runs<9>(gbase, tail, key, x, lane, stage_all[wave]);
         }
       } else {
         // sum equal entries over the wave; one lane issues the atomics
