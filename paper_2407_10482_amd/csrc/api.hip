@@ -65,6 +65,7 @@ SceneArgs scene_args(const ngprt_ctx* ctx) {
     S.Cpad = coarse_row_floats(coarse_channels(d));
     S.cidx = ctx->cidx;
     S.catlas = ctx->catlas;
+    S.n_blocks = ctx->n_blocks;
     for (int j = 0; j < 16; ++j) S.cdef[j] = ctx->cdef[j];
     S.gen = d.aggregation != NGPRT_AGG_SEPARATE_V ? 1 : 0;
     for (int l = 0; l < 4; ++l) {

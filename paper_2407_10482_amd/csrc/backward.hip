@@ -71,35 +71,40 @@ __device__ __forceinline__ uint32_t lane_xor(uint32_t v, int lane) {
   return uint32_t(__builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, x));
 }
 
+constexpr int kStageRow = 17;   // staged run: up to 16 values and the key
+
 // The atomics of a merged level.  The 9 (NV) channels of each run's row go to
 // neighbouring lanes of one atomic instruction, so an instruction carries the
 // rows of about 7 runs, 9 consecutive floats each: the tail lanes (one per
-// run) stage key and values in this wave's LDS slab `stage` (64 x 10 words),
+// run) stage key and values in this wave's LDS slab `stage` (64 x 17 words),
 // then lane q of each pass adds value q % NV of run q / NV.  Measured on
 // 2^18-ray training batches (backward kernel, 16 x 2^19 / 8 x 2^14 tables):
 // 91.6 / 14.5 ms with 9 one-lane-per-run instructions, 19.8 / 7.0 ms spread
 // (the same-line atomics of one instruction are combined on their way to
 // memory).
+// Rows are `stride` floats apart (9 for the tables, C for the coarse atlas);
+// only the first nv <= NV channels are added.
 template <int NV>
 __device__ __forceinline__ void scatter_runs(float* __restrict__ gbase, bool tail, uint32_t key, const float x[NV],
-                                             int lane, float* stage) {
+                                             int lane, float* stage, int stride = 9, int nv = NV) {
+  static_assert(NV < kStageRow, "a staged row holds the values and the key");
   const uint64_t tm = __ballot(tail);
   const int m = __popcll(tm);
   if (tail) {
     const int rank = __builtin_amdgcn_mbcnt_hi(uint32_t(tm >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(tm), 0));
-    float* row = stage + rank * 10;
+    float* row = stage + rank * kStageRow;
 #pragma unroll
     for (int j = 0; j < NV; ++j) row[j] = x[j];
-    row[9] = __uint_as_float(key);
+    row[kStageRow - 1] = __uint_as_float(key);
   }
   // the other lanes' staged rows are read below: a wave-scope fence orders
   // the LDS stores before the loads (and the next call's stores after them)
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-  for (int q = lane; q < NV * m; q += 64) {
-    const int t = q / NV, c = q - t * NV;
-    const float* row = stage + t * 10;
-    unsafeAtomicAdd(gbase + size_t(__float_as_uint(row[9])) * 9 + c, row[c]);
+  for (int q = lane; q < nv * m; q += 64) {
+    const int t = q / nv, c = q - t * nv;
+    const float* row = stage + t * kStageRow;
+    unsafeAtomicAdd(gbase + size_t(__float_as_uint(row[kStageRow - 1])) * size_t(stride) + c, row[c]);
   }
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -312,6 +317,7 @@ __device__ __forceinline__ void baked_scatter(const SceneArgs& S, const float u[
     }
   }
   // coarse rows: one vertex = (atlas row, local offset)
+  const int lane = threadIdx.x & 63;
 #pragma unroll 1
   for (int k = 0; k < 8; ++k) {
     const int bx = k & 1, by = (k >> 1) & 1, bz = (k >> 2) & 1;
@@ -319,6 +325,16 @@ __device__ __forceinline__ void baked_scatter(const SceneArgs& S, const float u[
     const int bid = have ? S.cidx[((vz >> 3) * S.nb + (vy >> 3)) * S.nb + (vx >> 3)] : -1;
     const int loc = ((vz & 7) * 8 + (vy & 7)) * 8 + (vx & 7);
     const float wk = ((bx ? fr[0] : gr[0]) * (by ? fr[1] : gr[1])) * (bz ? fr[2] : gr[2]);
+    if (S.n_blocks <= (1 << 17)) {
+      // vertex key bid * 512 + loc < 2^26: sorted merge and spread atomics
+      uint32_t key = bid >= 0 ? uint32_t(bid) * 512u + uint32_t(loc) : 0u;
+      float x[CMAX];
+#pragma unroll
+      for (int j = 0; j < CMAX; ++j) x[j] = wk * gco[j];
+      const bool tail = wave_sort_merge<CMAX>(key, bid >= 0, x, lane);
+      scatter_runs<CMAX>(gatlas, tail, key, x, lane, stage, C, C);
+      continue;
+    }
     bool pending = bid >= 0;
     uint64_t pm = __ballot(pending);
     while (pm) {
@@ -356,7 +372,7 @@ __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, c
                                                        const float* __restrict__ P) {
   __shared__ float sA_all[4][64 * kPad];
   __shared__ float sB_all[4][64 * kPad];
-  __shared__ float stage_all[4][64 * 10];
+  __shared__ float stage_all[4][64 * kStageRow];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t ray = (int64_t(blockIdx.x) * 4 + wave) * 64 + lane;

@@ -59,6 +59,7 @@ struct SceneArgs {
   int Cpad;                       // floats per atlas row (12 or 16)
   const int32_t* cidx;            // [nb^3] atlas row of each block or -1
   const float* catlas;            // [n_blocks][512][Cpad]
+  int64_t n_blocks;               // atlas rows
   float cdef[16];                 // value of every vertex of an empty block
   // aggregation other than Separate-Att (V) (gen = 1): fine level l's gate
   // parameters are coarse channel gidx[l][0 / 1] (density / colour), or
