@@ -35,7 +35,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .exact32 import F32, exp32
+from .exact32 import F32, exp32, fma32
 from .hashgrid import cell32, corners32, corners64
 
 BLOCK = 8
@@ -74,7 +74,7 @@ def coarse32(inp, u: np.ndarray) -> np.ndarray:
     acc = np.zeros((u.shape[0], inp.coarse_channels), dtype=F32)
     for c in range(8):
         vals = _vertex_values(inp, v[:, c, 0], v[:, c, 1], v[:, c, 2])
-        acc = acc + w[:, c:c + 1] * vals
+        acc = fma32(w[:, c:c + 1], vals, acc)
     return acc
 
 
@@ -136,7 +136,7 @@ def fused32(inp, u: np.ndarray):
         g = inp.deq32[l][idx]                            # [m, 8 corners, 9]
         acc = np.zeros((m, 8), dtype=F32)
         for c in range(8):
-            acc = acc + w[:, c:c + 1] * g[:, c, :8]
+            acc = fma32(w[:, c:c + 1], g[:, c, :8], acc)
         if inp.scales is not None:
             acc = inp.scales[l][None, :8] * acc
         a = gate_params(inp, co, l)
@@ -144,8 +144,8 @@ def fused32(inp, u: np.ndarray):
             gw = gb = np.ones(m, dtype=F32)
         else:
             gw, gb = sigmoid32(a[0]), sigmoid32(a[1])
-        fused[:, 0] = fused[:, 0] + gw * acc[:, 0]
-        fused[:, 1:] = fused[:, 1:] + gb[:, None] * acc[:, 1:]
+        fused[:, 0] = fma32(gw, acc[:, 0], fused[:, 0])
+        fused[:, 1:] = fma32(gb[:, None], acc[:, 1:], fused[:, 1:])
         gws.append(gw)
     return fused.astype(F32), np.stack(gws, axis=1).astype(F32), np.stack(idxs, axis=1)
 

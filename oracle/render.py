@@ -45,7 +45,7 @@ from typing import List, Optional
 
 import numpy as np
 
-from .exact32 import F32, exp32, sqrt32
+from .exact32 import F32, exp32, fma32, sqrt32
 from .hashgrid import corners32, corners64
 from . import baked, pyramid, quant, sh
 
@@ -141,7 +141,7 @@ def fused32(inp: OracleInputs, u: np.ndarray):
         d = a_l - m;  x = exp32(-|d|)
         d > 0:  the new maximum is a_l; the sums so far scale by x, e_l = 1
         else:   the sums keep their scale, e_l = x
-        S = S * scale + e_l;   N_j = N_j * scale + e_l * v_l[j]
+        S = fma(S, scale, e_l);   N_j = fma(e_l, v_l[j], N_j * scale)
     fused_j = N_j / S; attention weights w_l = exp32(a_l - m) / S with m the
     final maximum.  S >= 1 always (the level holding the maximum adds 1).
 
@@ -159,8 +159,8 @@ def fused32(inp: OracleInputs, u: np.ndarray):
         idxs.append(idx)
         g = inp.deq32[l][idx]                        # [m, 8 corners, 9 channels]
         acc = np.zeros((m, 9), dtype=F32)
-        for c in range(8):                           # acc = acc + w_c * v_c, c = 0..7
-            acc = acc + w[:, c:c + 1] * g[:, c, :]
+        for c in range(8):                           # acc = fma(w_c, v_c, acc), c = 0..7
+            acc = fma32(w[:, c:c + 1], g[:, c, :], acc)
         if inp.scales is not None:
             acc = inp.scales[l][None, :] * acc
         a = acc[:, 8]
@@ -171,8 +171,8 @@ def fused32(inp: OracleInputs, u: np.ndarray):
         scale = np.where(up, x, F32(1.0)).astype(F32)
         e = np.where(up, F32(1.0), x).astype(F32)
         run_max = np.where(up, a, run_max).astype(F32)
-        esum = esum * scale + e
-        num = num * scale[:, None] + e[:, None] * acc[:, :8]
+        esum = fma32(esum, scale, e)
+        num = fma32(e[:, None], acc[:, :8], num * scale[:, None])
         logits.append(a)
     fused = (num / esum[:, None]).astype(F32)
     wl = np.stack([exp32(a - run_max) / esum for a in logits], axis=1).astype(F32)

@@ -2,10 +2,11 @@
 //
 // Everything on the decision chain (positions, voxel/corner indices,
 // trilinear weights, interpolated density and logit, softmax, density
-// activation, transmittance) is written with plain float32 operators; the
-// library is compiled with -ffp-contract=off and correctly rounded
-// division/sqrt, so each operator is one IEEE binary32 operation.  Colour
-// and specular channels, which decide nothing, use explicit fmaf.
+// activation, transmittance) is written with plain float32 operators and
+// explicit fused multiply-adds where the chain specifies one (exp32, the
+// corner sums, the softmax sums); the library is compiled with
+// -ffp-contract=off and correctly rounded division/sqrt, so each operator is
+// one IEEE binary32 operation.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,7 +19,7 @@ namespace ngprt {
 // ---------------------------------------------------------------------------
 // exponential of the decision chain: Cody-Waite reduction by ln 2 (split in a
 // 9-bit head and a float32 tail), degree-7 Taylor polynomial of e^r by
-// Horner without fused multiply-add, and exact scaling by 2^k.
+// Horner with fused multiply-adds, and exact scaling by 2^k.
 // (The special cases branch: a wave almost never diverges on them, and
 // taking them by selects after the polynomial measured slower, 154.2 ->
 // 149.2 frames/s on the 8-view 1080p workload, for the extra VALU work.)
@@ -29,16 +30,16 @@ __device__ __forceinline__ float exp32(float x) {
   const float log2e = __int_as_float(0x3FB8AA3B);
   const float ln2_hi = __int_as_float(0x3F318000);
   const float ln2_lo = __int_as_float(0xB95E8083);
-  float k = floorf(x * log2e + 0.5f);
-  float r = (x - k * ln2_hi) - k * ln2_lo;
-  float p = __int_as_float(0x39500D01);          // 1/7!
-  p = p * r + __int_as_float(0x3AB60B61);        // 1/6!
-  p = p * r + __int_as_float(0x3C088889);        // 1/5!
-  p = p * r + __int_as_float(0x3D2AAAAB);        // 1/4!
-  p = p * r + __int_as_float(0x3E2AAAAB);        // 1/3!
-  p = p * r + 0.5f;
-  p = p * r + 1.0f;
-  p = p * r + 1.0f;
+  float k = floorf(__builtin_fmaf(x, log2e, 0.5f));
+  float r = __builtin_fmaf(-k, ln2_lo, __builtin_fmaf(-k, ln2_hi, x));
+  float p = __int_as_float(0x39500D01);                    // 1/7!
+  p = __builtin_fmaf(p, r, __int_as_float(0x3AB60B61));    // 1/6!
+  p = __builtin_fmaf(p, r, __int_as_float(0x3C088889));    // 1/5!
+  p = __builtin_fmaf(p, r, __int_as_float(0x3D2AAAAB));    // 1/4!
+  p = __builtin_fmaf(p, r, __int_as_float(0x3E2AAAAB));    // 1/3!
+  p = __builtin_fmaf(p, r, 0.5f);
+  p = __builtin_fmaf(p, r, 1.0f);
+  p = __builtin_fmaf(p, r, 1.0f);
   int n = (int)k;
   return p * __int_as_float((n + 127) << 23);
 }
@@ -163,10 +164,10 @@ __device__ __forceinline__ void level_corners(const float u[3], int N, float Nf,
 // reading) taken with a running maximum m (online softmax, Milakov and
 // Gimelshein 2018): d = a_l - m, x = exp32(-|d|); when d > 0 the sums so far
 // are scaled by x and e_l = 1 (a_l is the new maximum), else e_l = x; then
-// S = S * scale + e_l and N_j = N_j * scale + e_l v_l[j].  fused_j = N_j / S,
-// and S >= 1, so no sample's softmax underflows whatever the offset of its
-// logits.  The density channel and S are on the decision chain (plain
-// float32 ops); the colour and specular channels use fma.  Optionally the
+// S = fma(S, scale, e_l) and N_j = fma(e_l, v_l[j], N_j * scale).
+// fused_j = N_j / S, and S >= 1, so no sample's softmax underflows whatever
+// the offset of its logits.  Each corner sum is acc = fma(w_k, v_k, acc)
+// from acc = 0, corners in order.  Optionally the
 // attention weights exp32(a_l - m) / S [L] and corner indices [L][8].
 #ifndef NGPRT_LEVEL_UNROLL
 #define NGPRT_LEVEL_UNROLL 1
@@ -202,10 +203,9 @@ __device__ __forceinline__ void eval_fused(const SceneArgs& S, const float u[3],
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const float wk = c.w[4 * g + k];
-          acc[8] = acc[8] + wk * lg[k];
-          acc[0] = acc[0] + wk * v[k][0];
+          acc[8] = __builtin_fmaf(wk, lg[k], acc[8]);
 #pragma unroll
-          for (int j = 1; j < 8; ++j) acc[j] = __builtin_fmaf(wk, v[k][j], acc[j]);
+          for (int j = 0; j < 8; ++j) acc[j] = __builtin_fmaf(wk, v[k][j], acc[j]);
         }
       }
       if (DT == DT_FP8) {
@@ -219,8 +219,8 @@ __device__ __forceinline__ void eval_fused(const SceneArgs& S, const float u[3],
       const float sc = up ? x : 1.0f;
       const float e = up ? 1.0f : x;
       run_max = up ? a : run_max;
-      esum = esum * sc + e;
-      num0 = num0 * sc + e * acc[0];
+      esum = __builtin_fmaf(esum, sc, e);
+      num0 = __builtin_fmaf(e, acc[0], num0 * sc);
 #pragma unroll
       for (int j = 0; j < 7; ++j) num[j] = __builtin_fmaf(e, acc[1 + j], num[j] * sc);
       if (DEBUG) {
@@ -251,9 +251,9 @@ __device__ __forceinline__ void eval_fused(const SceneArgs& S, const float u[3],
 // Coarse vertex v lives in block (v >> 3) (per axis) at local offset v & 7;
 // the block's atlas row comes from the index grid (-1: empty block, whose
 // vertices take the default vector).  Atlas rows hold Cpad >= 8 + 2L floats.
-// Decision chain: every coarse channel acc = acc + w_k v_k (k = 0..7, plain
-// float32); fine density as the hash levels; g = 1 / (1 + exp32(-a));
-// f_0 = f~_0, then f_0 = f_0 + g_omega_l * sigma^_l in level order.
+// Decision chain: every coarse channel acc = fma(w_k, v_k, acc) (k = 0..7,
+// from 0); fine density as the hash levels; g = 1 / (1 + exp32(-a));
+// f_0 = f~_0, then f_0 = fma(g_omega_l, sigma^_l, f_0) in level order.
 __device__ __forceinline__ float sigmoid32(float a) { return 1.0f / (1.0f + exp32(-a)); }
 
 //
@@ -308,7 +308,7 @@ __device__ __forceinline__ void eval_baked(const SceneArgs& S, const float u[3],
       for (int j = 0; j < 16; ++j) v[j] = S.cdef[j];
     }
 #pragma unroll
-    for (int j = 0; j < CMAX; ++j) co[j] = co[j] + wk * v[j];
+    for (int j = 0; j < CMAX; ++j) co[j] = __builtin_fmaf(wk, v[j], co[j]);
   }
   float f0 = co[0];
   float fc[7];
@@ -333,9 +333,8 @@ __device__ __forceinline__ void eval_baked(const SceneArgs& S, const float u[3],
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const float wk = c.w[4 * gq + k];
-          acc[0] = acc[0] + wk * v[k][0];
 #pragma unroll
-          for (int j = 1; j < 8; ++j) acc[j] = __builtin_fmaf(wk, v[k][j], acc[j]);
+          for (int j = 0; j < 8; ++j) acc[j] = __builtin_fmaf(wk, v[k][j], acc[j]);
         }
       }
       if (DT == DT_FP8) {
@@ -363,7 +362,7 @@ __device__ __forceinline__ void eval_baked(const SceneArgs& S, const float u[3],
       }
       const float gw = sigmoid32(aw);
       const float gb = sigmoid32(ab);
-      f0 = f0 + gw * acc[0];
+      f0 = __builtin_fmaf(gw, acc[0], f0);
 #pragma unroll
       for (int j = 0; j < 7; ++j) fc[j] = __builtin_fmaf(gb, acc[1 + j], fc[j]);
       if (DEBUG) {

@@ -118,5 +118,5 @@ def test_scene_constant_softmax_shift_is_caught():
 
 def test_unrescaled_running_sums_are_caught():
     """A new running maximum that does not rescale the sums taken so far."""
-    rd = _mutated("oracle.render", "esum = esum * scale + e", "esum = esum + e")
+    rd = _mutated("oracle.render", "esum = fma32(esum, scale, e)", "esum = esum + e")
     _fails(pins.test_softmax_mirror_with_extreme_logits, "ramp", fused32=rd.fused32)

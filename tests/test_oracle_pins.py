@@ -475,3 +475,50 @@ def test_fp8_scales_per_level_channel():
     floor = np.maximum(s[:, None, :].astype(np.float64) * 2.0 ** -6, 1e-30)
     rel = np.abs(deq - tab) / np.maximum(np.abs(tab), floor)
     assert rel.max() <= 2.0 ** -4 + 1e-6
+
+
+def _round_to_f32_exact(q):
+    """The float32 nearest to the rational q (ties to even), by exact
+    comparison with its float32 neighbours."""
+    from fractions import Fraction
+    f = np.float32(float(q))                      # within an ulp of the answer
+    best = None
+    for cand in (np.nextafter(f, np.float32(-np.inf)), f, np.nextafter(f, np.float32(np.inf))):
+        d = abs(Fraction(float(cand)) - q)
+        if best is None or d < best[0] or (d == best[0] and (int(np.array(cand).view(np.uint32)) & 1) == 0):
+            best = (d, cand)
+    return best[1]
+
+
+def test_fma32_is_the_single_rounding_of_the_exact_value():
+    """fma32 against exact rational arithmetic: random triples, cancellation
+    (c close to -a b), and sums placed within float64 rounding of a float32
+    halfway point, where a float64 sum rounded to float32 would round twice."""
+    from fractions import Fraction
+    from oracle.exact32 import fma32
+    rng = np.random.default_rng(17)
+    n = 4000
+    a = (rng.normal(size=n) * np.exp2(rng.integers(-20, 20, n))).astype(np.float32)
+    b = (rng.normal(size=n) * np.exp2(rng.integers(-20, 20, n))).astype(np.float32)
+    c = (rng.normal(size=n) * np.exp2(rng.integers(-20, 20, n))).astype(np.float32)
+    c[: n // 4] = (-(a[: n // 4].astype(np.float64) * b[: n // 4]) *
+                   (1 + rng.normal(size=n // 4) * 1e-6)).astype(np.float32)
+    # double-rounding traps: a = 1 + 2^-12 and b = (1 - 4095 2^-24) 2^-24 give
+    # a b = 2^-24 + 2^-60 exactly; with c = t an even float32 in [1, 2), the
+    # exact value lies 2^-60 above the halfway point t + 2^-24, the float64 sum
+    # rounds onto that halfway point and a second rounding to float32 would
+    # fall to t, while the single rounding goes up (signs flipped for half)
+    m = n // 4
+    t = (np.float32(1.0) + np.float32(2.0 ** -22) * rng.integers(0, 1 << 22, m).astype(np.float32))
+    sign = np.where(np.arange(m) % 2 == 0, np.float32(1.0), np.float32(-1.0))
+    a[-m:] = sign * np.float32(1.0 + 2.0 ** -12)
+    b[-m:] = np.float32((1.0 - 4095 * 2.0 ** -24) * 2.0 ** -24)
+    c[-m:] = sign * t
+    got = fma32(a, b, c)
+    for i in range(n):
+        exact = Fraction(float(a[i])) * Fraction(float(b[i])) + Fraction(float(c[i]))
+        want = _round_to_f32_exact(exact)
+        assert np.array(got[i]).view(np.uint32) == np.array(want).view(np.uint32), (i, a[i], b[i], c[i])
+    # the trap cases really are ones where rounding the float64 sum differs
+    naive = (a.astype(np.float64) * b + c).astype(np.float32)
+    assert np.all(naive[-m:] != got[-m:])
