@@ -423,7 +423,13 @@ def committed_counters(dtype_name: str):
                       ("L2 requests per launch", "l2_req"), ("L2 hits per launch", "l2_hit"),
                       ("vector memory reads per launch", "vmem_rd")):
         try:
-            out[name] = int(vals[key].replace(",", ""))
+            # the figure leads the value; a parenthesised note may follow
+            out[name] = int(vals[key].split()[0].replace(",", ""))
+        except (KeyError, ValueError, IndexError):
+            out[name] = None
+    for key, name in (("TA busy fraction per CU", "ta_busy"), ("TD busy fraction per CU", "td_busy")):
+        try:
+            out[name] = float(vals[key])
         except (KeyError, ValueError):
             out[name] = None
     return out
@@ -566,6 +572,13 @@ def main():
         if ctr["l2_req"] and ctr["l2_hit"] is not None:
             levels["l2"] = {"requests_per_launch": ctr["l2_req"],
                             "hit_rate": round(ctr["l2_hit"] / ctr["l2_req"], 4)}
+        if ctr["ta_busy"] is not None:
+            # busy cycles of the texture address / data units per CU; they
+            # include cycles stalled on the caches, and taking half of the
+            # load instructions off the TA (coarse levels by scalar loads)
+            # gained 2 %, so this is occupancy of the path, not its limit
+            levels["vmem_pipeline"] = {"ta_busy": ctr["ta_busy"], "td_busy": ctr["td_busy"],
+                                       "load_instructions_per_launch": ctr["vmem_rd"]}
     # the binding level is the one closest to its peak
     cands = [(lv["frac"], name) for name, lv in levels.items() if "frac" in lv]
     if cands:
