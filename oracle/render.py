@@ -213,6 +213,23 @@ def grid_coords64(inp: OracleInputs, pos: np.ndarray) -> np.ndarray:
     return (np.asarray(pos, dtype=np.float64) - lo) / (2.0 * inp.roi_half)
 
 
+def sample_coords64(inp: OracleInputs, o: np.ndarray, d: np.ndarray, s_ray: np.ndarray,
+                    s_t: np.ndarray) -> np.ndarray:
+    """Grid coordinates of decided samples recomputed in float64 from the ray
+    and the sample's lattice parameter t [Sec. 3: x = o + t d; contracted
+    scenes map |x| > 1 to (2 - 1/|x|) x / |x|].  The float32 path takes u
+    from the float32 position instead; the two differ by the rounding of the
+    position (about 1e-7 in u), which this lets one measure."""
+    o64 = np.asarray(o, dtype=np.float64)[s_ray]
+    d64 = np.asarray(d, dtype=np.float64)[s_ray]
+    x = o64 + np.asarray(s_t, dtype=np.float64)[:, None] * d64
+    if inp.domain == CONTRACT:
+        r = np.sqrt(np.sum(x * x, axis=1))
+        outer = r > 1.0
+        x[outer] = ((2.0 - 1.0 / r[outer]) / r[outer])[:, None] * x[outer]
+    return grid_coords64(inp, x)
+
+
 # --------------------------------------------------------------------------
 # ray setup
 
@@ -520,12 +537,19 @@ def composite64(inp: OracleInputs, n: int, s_ray, s_t, fused):
 
 
 def render(inp: OracleInputs, o: np.ndarray, d: np.ndarray, naive: bool = False,
-           terminate: bool = True) -> RenderResult:
+           terminate: bool = True, coords: str = "f32") -> RenderResult:
+    """coords: "f32" evaluates the decided samples at their float32 grid
+    coordinates (the lattice's own positions); "f64" recomputes each
+    position in float64 from (o, d, t) (sample_coords64)."""
     o = np.asarray(o, dtype=F32)
     n = o.shape[0]
     m = march(inp, o, d, naive=naive, terminate=terminate)
     if len(m["s_ray"]):
-        fz, _ = fused64(inp, grid_coords32(inp, m["s_pos"]).astype(np.float64))
+        if coords == "f64":
+            u = sample_coords64(inp, o, np.asarray(d, dtype=F32), m["s_ray"], m["s_t"])
+        else:
+            u = grid_coords32(inp, m["s_pos"]).astype(np.float64)
+        fz, _ = fused64(inp, u)
     else:
         fz = np.zeros((0, 8))
     c_d, feat, depth, T = composite64(inp, n, m["s_ray"], m["s_t"], fz)

@@ -3,7 +3,9 @@
 Integer outputs bit-exact; the float32 decision chain (fused density,
 attention weights, transmittance) bit-exact against the oracle's float32
 mirror; colours within 1e-5 of the float64 oracle."""
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -222,6 +224,21 @@ def test_render_hd_full_frame_sampled():
     _check_render(sub, ref)
     ns = _np(out["n_samples"])
     print(f"hd: samples/ray {ns.mean():.2f} reads/ray {_np(out['n_reads']).mean():.2f}", flush=True)
+    # the same samples evaluated at float64 positions (o + t d, contracted in
+    # float64): the colour error then includes the float32 rounding of each
+    # sample's position, about 1e-7 in u (5e-4 of a cell at N = 4096)
+    ref_c = render(inp, o[sel], d[sel], coords="f64")
+    gpu = _np(sub["rgb"]).astype(np.float64)
+    rep = {"rays": int(len(sel)),
+           "f32_positions": {"max_abs": float(np.abs(gpu - ref.rgb).max()),
+                             "mean_abs": float(np.abs(gpu - ref.rgb).mean())},
+           "f64_positions": {"max_abs": float(np.abs(gpu - ref_c.rgb).max()),
+                             "mean_abs": float(np.abs(gpu - ref_c.rgb).mean())}}
+    print("hd colour error vs float64 oracle:", json.dumps(rep), flush=True)
+    os.makedirs("gpurun_out", exist_ok=True)
+    with open("gpurun_out/hd_colour_error.json", "w") as f:
+        json.dump(rep, f, indent=1)
+    assert rep["f64_positions"]["max_abs"] < COLOUR_TOL
 
 
 # ---------------------------------------------------------------- extreme logits

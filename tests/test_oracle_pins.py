@@ -399,6 +399,41 @@ def test_contracted_lattice_has_equal_contracted_steps():
     assert 2.0 - np.linalg.norm(p0[-1]) < 2 * step
 
 
+def test_sample_coords64_closed_forms():
+    """Float64 sample coordinates: a radial ray from the origin lands at
+    contracted radius 2 - 1/t beyond the unit ball and at t inside it; every
+    coordinate agrees with the float32 lattice position to float32 rounding;
+    in the box domain the position is o + t d itself."""
+    from oracle.render import march, sample_coords64
+    step = 2 * math.sqrt(3) / 512
+    tab = np.zeros((1, 16, 9), F32)
+    occ = np.ones((8, 8, 8), np.uint8)
+    for dom in (CONTRACT, BOX):
+        half = 2.0 if dom == CONTRACT else 1.0
+        inp = OracleInputs(tables=tab, occ=occ, dist=np.zeros_like(occ), mlp=np.zeros(451, F32),
+                           resolutions=[4], domain=dom, roi_half=half, step=step,
+                           max_samples=4096, t_threshold=0.0)
+        o = np.array([[0.0, 0.0, 0.0], [0.3, -0.2, 0.1], [0.2, -0.9, 0.5]], F32)
+        d = np.array([[1.0, 0.0, 0.0], [-0.6, 0.8, 0.0], [0.0, 1.0, 0.0]], F32)
+        m = march(inp, o, d)
+        u = sample_coords64(inp, o, d, m["s_ray"], m["s_t"])
+        x = (u * 2.0 * half) - half                          # back to positions
+        t = m["s_t"].astype(np.float64)
+        r0 = m["s_ray"] == 0
+        if dom == CONTRACT:
+            want = np.where(t[r0] > 1.0, 2.0 - 1.0 / np.maximum(t[r0], 1e-300), t[r0])
+        else:
+            want = t[r0]
+        assert np.allclose(x[r0, 0], want, rtol=0, atol=1e-12)
+        assert np.allclose(x[r0, 1:], 0.0, atol=1e-12)
+        if dom == BOX:
+            exact = o.astype(np.float64)[m["s_ray"]] + t[:, None] * d.astype(np.float64)[m["s_ray"]]
+            assert np.allclose(x, exact, rtol=0, atol=1e-12)
+        u32 = ((m["s_pos"].astype(np.float64)) + half) / (2.0 * half)
+        assert np.abs(u - u32).max() < 1e-6
+        assert len(t) > 100
+
+
 def test_empty_rays_get_sigmoid_of_mlp_of_zero():
     rng = np.random.default_rng(2)
     tab = rng.normal(size=(3, 1 << 10, 9)).astype(F32)
