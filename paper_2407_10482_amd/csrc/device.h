@@ -65,8 +65,21 @@ __device__ __forceinline__ uint32_t hash3(uint32_t x, uint32_t y, uint32_t z, ui
 
 template <int DT> struct Store;
 
+// Read-only views in the constant address space: a load through one with a
+// wave-uniform address is a scalar load (scalar cache; no vector-memory
+// instruction).  The render kernels never write the tables.
+typedef float ev_f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t ev_u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t ev_u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(4))) const float c_f32;
+typedef __attribute__((address_space(4))) const ev_f32x4 c_f32x4;
+typedef __attribute__((address_space(4))) const uint32_t c_u32;
+typedef __attribute__((address_space(4))) const ev_u32x2 c_u32x2;
+typedef __attribute__((address_space(4))) const ev_u32x4 c_u32x4;
+
 // Accessors take the level's uniform base pointer and a 32-bit entry index,
 // so a gather is one global load with a scalar base and a 32-bit offset.
+// The _s forms take a wave-uniform index and read by scalar loads.
 template <> struct Store<DT_F32> {
   static constexpr int kRow = 32;
   __device__ static __forceinline__ float logit(const void* lbase, uint32_t i) {
@@ -77,6 +90,15 @@ template <> struct Store<DT_F32> {
     float4 a = q[0], b = q[1];
     v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
     v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  }
+  __device__ static __forceinline__ float logit_s(const void* lbase, uint32_t i) {
+    return ((c_f32*)lbase)[i];
+  }
+  __device__ static __forceinline__ void feat_s(const void* lbase, uint32_t i, float v[8]) {
+    c_f32x4* q = (c_f32x4*)(reinterpret_cast<const char*>(lbase) + (size_t(i) << 5));
+    const ev_f32x4 a = q[0], b = q[1];
+    v[0] = a[0]; v[1] = a[1]; v[2] = a[2]; v[3] = a[3];
+    v[4] = b[0]; v[5] = b[1]; v[6] = b[2]; v[7] = b[3];
   }
 };
 
@@ -89,10 +111,24 @@ template <> struct Store<DT_BF16> {
   }
   __device__ static __forceinline__ void feat(const void* lbase, uint32_t i, float v[8]) {
     uint4 w = *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(lbase) + (i << 4));
-    v[0] = __uint_as_float(w.x << 16); v[1] = __uint_as_float(w.x & 0xFFFF0000u);
-    v[2] = __uint_as_float(w.y << 16); v[3] = __uint_as_float(w.y & 0xFFFF0000u);
-    v[4] = __uint_as_float(w.z << 16); v[5] = __uint_as_float(w.z & 0xFFFF0000u);
-    v[6] = __uint_as_float(w.w << 16); v[7] = __uint_as_float(w.w & 0xFFFF0000u);
+    unpack(w.x, w.y, w.z, w.w, v);
+  }
+  __device__ static __forceinline__ void unpack(uint32_t x, uint32_t y, uint32_t z, uint32_t w,
+                                                float v[8]) {
+    v[0] = __uint_as_float(x << 16); v[1] = __uint_as_float(x & 0xFFFF0000u);
+    v[2] = __uint_as_float(y << 16); v[3] = __uint_as_float(y & 0xFFFF0000u);
+    v[4] = __uint_as_float(z << 16); v[5] = __uint_as_float(z & 0xFFFF0000u);
+    v[6] = __uint_as_float(w << 16); v[7] = __uint_as_float(w & 0xFFFF0000u);
+  }
+  // the dword holding the logit (a level holds T >= 16 entries, so the dword
+  // lies inside the level)
+  __device__ static __forceinline__ float logit_s(const void* lbase, uint32_t i) {
+    const uint32_t w = ((c_u32*)lbase)[i >> 1];
+    return __uint_as_float((i & 1u) ? (w & 0xFFFF0000u) : (w << 16));
+  }
+  __device__ static __forceinline__ void feat_s(const void* lbase, uint32_t i, float v[8]) {
+    const ev_u32x4 w = *(c_u32x4*)(reinterpret_cast<const char*>(lbase) + (size_t(i) << 4));
+    unpack(w[0], w[1], w[2], w[3], v);
   }
 };
 
@@ -112,10 +148,23 @@ template <> struct Store<DT_FP8> {
   }
   __device__ static __forceinline__ void feat(const void* lbase, uint32_t i, float v[8]) {
     uint2 w = *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(lbase) + (i << 3));
-    fp8pair a = fp8x2_decode(w.x, false), b = fp8x2_decode(w.x, true);
-    fp8pair c = fp8x2_decode(w.y, false), d = fp8x2_decode(w.y, true);
+    unpack(w.x, w.y, v);
+  }
+  __device__ static __forceinline__ void unpack(uint32_t x, uint32_t y, float v[8]) {
+    fp8pair a = fp8x2_decode(x, false), b = fp8x2_decode(x, true);
+    fp8pair c = fp8x2_decode(y, false), d = fp8x2_decode(y, true);
     v[0] = a[0]; v[1] = a[1]; v[2] = b[0]; v[3] = b[1];
     v[4] = c[0]; v[5] = c[1]; v[6] = d[0]; v[7] = d[1];
+  }
+  // the dword holding the logit (a level holds T >= 16 entries, so the dword
+  // lies inside the level)
+  __device__ static __forceinline__ float logit_s(const void* lbase, uint32_t i) {
+    const uint32_t w = ((c_u32*)lbase)[i >> 2];
+    return fp8x2_decode((w >> ((i & 3u) * 8u)) & 0xFFu, false)[0];
+  }
+  __device__ static __forceinline__ void feat_s(const void* lbase, uint32_t i, float v[8]) {
+    const ev_u32x2 w = *(c_u32x2*)(reinterpret_cast<const char*>(lbase) + (size_t(i) << 3));
+    unpack(w[0], w[1], v);
   }
 };
 
@@ -134,6 +183,7 @@ __device__ __forceinline__ const void* logit_level(const void* logit, int l, int
 struct Corners {
   uint32_t idx[8];
   float w[8];
+  uint32_t key0, key1;   // the cell (i0 of each axis, < 2^20): x | y << 20, y >> 12 | z << 8
 };
 
 __device__ __forceinline__ void level_corners(const float u[3], int N, float Nf, uint32_t mask,
@@ -156,6 +206,8 @@ __device__ __forceinline__ void level_corners(const float u[3], int N, float Nf,
     c.w[k] = ((bx ? f[0] : g[0]) * (by ? f[1] : g[1])) * (bz ? f[2] : g[2]);
     c.idx[k] = hash3(uint32_t(i0[0] + bx), uint32_t(i0[1] + by), uint32_t(i0[2] + bz), mask);
   }
+  c.key0 = uint32_t(i0[0]) | (uint32_t(i0[1]) << 20);
+  c.key1 = (uint32_t(i0[1]) >> 12) | (uint32_t(i0[2]) << 8);
 }
 
 // Lookup + attention at grid coordinate u, in one pass over the levels.
@@ -169,8 +221,19 @@ __device__ __forceinline__ void level_corners(const float u[3], int N, float Nf,
 // the offset of its logits.  Each corner sum is acc = fma(w_k, v_k, acc)
 // from acc = 0, corners in order.  Optionally the
 // attention weights exp32(a_l - m) / S [L] and corner indices [L][8].
+// When every active lane of the wave samples the same cell of a level (most
+// of the time on the coarse levels: the wave's rays are an 8x8 pixel tile),
+// the eight rows come in once by scalar loads instead of 24 vector loads;
+// the arithmetic is the same.
 #ifndef NGPRT_LEVEL_UNROLL
 #define NGPRT_LEVEL_UNROLL 1
+#endif
+// storage types (bit DT) whose lookups read a wave-shared cell by scalar
+// loads: F32 only (BF16 and FP8 rows read that way need their unpacking on
+// the scalar ALU, and measured slower: 42.6 -> 44.6 ms and 41.3 -> 43.3 ms
+// on the 8-view 1080p workload, against 51.3 -> 46.6 ms for F32)
+#ifndef NGPRT_SHARED_CELL
+#define NGPRT_SHARED_CELL 1
 #endif
 
 template <int DT, int LMAX, bool DEBUG = false>
@@ -190,22 +253,59 @@ __device__ __forceinline__ void eval_fused(const SceneArgs& S, const float u[3],
       float acc[9];
 #pragma unroll
       for (int j = 0; j < 9; ++j) acc[j] = 0.0f;
-      // two groups of four corners keep the gathered rows in flight within
-      // the register budget
+      // one cell for the whole wave (common on the coarse levels, where a
+      // wave's 64 neighbouring rays sample close together): its eight rows
+      // are read once by scalar loads and every lane accumulates from scalar
+      // registers, in the same order as the per-lane gather below
+      bool shared = false;
+      if constexpr ((NGPRT_SHARED_CELL >> DT) & 1) {
+        const uint32_t k0 = __builtin_amdgcn_readfirstlane(c.key0);
+        const uint32_t k1 = __builtin_amdgcn_readfirstlane(c.key1);
+        shared = __ballot(c.key0 != k0 || c.key1 != k1) == 0ull;
+      }
+      if (shared) {
+        uint32_t ik[8];
 #pragma unroll
-      for (int g = 0; g < 2; ++g) {
-        float v[4][8], lg[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          Store<DT>::feat(fb, c.idx[4 * g + k], v[k]);
-          lg[k] = Store<DT>::logit(lb, c.idx[4 * g + k]);
+        for (int k = 0; k < 8; ++k) {
+          ik[k] = __builtin_amdgcn_readfirstlane(c.idx[k]);
+          // opaque, so that the compiler keeps the scalar index instead of
+          // substituting the lane's own (equal) vector index
+          asm volatile("" : "+s"(ik[k]));
         }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const float wk = c.w[4 * g + k];
-          acc[8] = __builtin_fmaf(wk, lg[k], acc[8]);
+        for (int g = 0; g < 2; ++g) {
+          float v[4][8], lg[4];
 #pragma unroll
-          for (int j = 0; j < 8; ++j) acc[j] = __builtin_fmaf(wk, v[k][j], acc[j]);
+          for (int k = 0; k < 4; ++k) {
+            Store<DT>::feat_s(fb, ik[4 * g + k], v[k]);
+            lg[k] = Store<DT>::logit_s(lb, ik[4 * g + k]);
+          }
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const float wk = c.w[4 * g + k];
+            acc[8] = __builtin_fmaf(wk, lg[k], acc[8]);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc[j] = __builtin_fmaf(wk, v[k][j], acc[j]);
+          }
+        }
+      } else {
+        // two groups of four corners keep the gathered rows in flight within
+        // the register budget
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+          float v[4][8], lg[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            Store<DT>::feat(fb, c.idx[4 * g + k], v[k]);
+            lg[k] = Store<DT>::logit(lb, c.idx[4 * g + k]);
+          }
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const float wk = c.w[4 * g + k];
+            acc[8] = __builtin_fmaf(wk, lg[k], acc[8]);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc[j] = __builtin_fmaf(wk, v[k][j], acc[j]);
+          }
         }
       }
       if (DT == DT_FP8) {

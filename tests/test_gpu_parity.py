@@ -162,6 +162,37 @@ def test_render_parity_tiny(dtype):
     _check_render(out, render(inp, o, d))
 
 
+@pytest.mark.parametrize("name", ["tiny", "hd"])
+def test_render_wave_shared_and_split_cells(name):
+    """Waves whose 64 rays are one ray repeated (at every level the wave's
+    samples share one cell, whose rows are read once by scalar loads) and
+    waves with one ray differing (every level takes the per-lane gathers),
+    plus a ragged tail, against the oracle."""
+    print(f"[render shared/split cells {name}]", flush=True)
+    inp = oracle_inputs(name)
+    sc, _ = scene_and_dist(name)
+    cams = synth.camera_positions(sc.cfg)[:1]
+    o, d, _ = synth.scene_rays(sc.cfg, cams=cams)
+    rng = np.random.default_rng(5)
+    cand = rng.choice(len(o), size=48, replace=False)
+    ns = render(inp, o[cand], d[cand]).n_samples
+    hit = cand[ns >= 3]
+    assert len(hit) >= 2
+    a, b = int(hit[0]), int(hit[-1])
+    idx = np.r_[np.full(64, a), np.full(64, b), np.full(64, a), np.full(64, b), np.full(10, a)]
+    idx[128 + 17] = b                     # third wave: one lane differs
+    idx[192 + 40] = a                     # fourth wave: one lane differs
+    oo, dd = np.ascontiguousarray(o[idx]), np.ascontiguousarray(d[idx])
+    r = gpu_renderer(name)
+    go, gd = to_gpu(oo, dd)
+    out = r.render(go, gd)
+    _check_render(out, render(inp, oo, dd))
+    rgb = _np(out["rgb"])
+    # a ray's colour does not depend on the path its wave took
+    assert np.array_equal(rgb[0], rgb[128]) and np.array_equal(rgb[64], rgb[192])
+    assert np.array_equal(rgb[145], rgb[64]) and np.array_equal(rgb[232], rgb[0])
+
+
 def test_render_edge_rays_and_ragged_batches():
     print("[render edge rays]", flush=True)
     inp = oracle_inputs("tiny")
