@@ -52,9 +52,11 @@ SceneArgs scene_args(const ngprt_ctx* ctx) {
   S.max_samples = d.max_samples;
   S.pyr_n = d.occ_levels > 0 ? d.occ_levels : 0;
   S.use_dist = d.use_distance;
+  S.pyr_jg = 0;
   for (int j = 0; j < kMaxPyr; ++j) {
     S.pyrR[j] = j < S.pyr_n ? (d.occ_fine_res >> j) : 32;
     S.pyr[j] = j < S.pyr_n ? ctx->pyr[j] : nullptr;
+    if (j < S.pyr_n && S.pyrR[j] == d.occ_res) S.pyr_jg = j;
   }
   S.view_mlp = d.mlp_hidden == 64 ? 1 : 0;
   S.model = d.feature_model;

@@ -208,6 +208,33 @@ __global__ void pyr_unpack_kernel(const uint32_t* __restrict__ bits, uint8_t* __
   out[v] = uint8_t((bits[v >> 5] >> (v & 31)) & 1u);
 }
 
+// Level codes of the march (Eq. 9's multi-level occupancy): for every voxel
+// of the distance grid (pyramid level jg, resolution R), the coarsest level
+// j >= jg whose cell holding the voxel is empty, as 1 + j - jg in bits 9-11
+// of the voxel's word (0: occupied at every level >= jg).  Level j's cell is
+// the voxel's coordinates shifted right by j - jg (the resolutions halve).
+struct PyrLevels {
+  const uint32_t* bits[kMaxPyr];
+};
+
+__global__ void pyr_code_kernel(uint16_t* __restrict__ grid, int R, int jg, int nl, PyrLevels P) {
+  const int64_t n = int64_t(R) * R * R;
+  const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int x = int(v % R), y = int((v / R) % R), z = int(v / (int64_t(R) * R));
+  uint32_t code = 0;
+  for (int j = nl - 1; j >= jg; --j) {
+    const int m = j - jg, Rj = R >> m;
+    const int cx = x >> m, cy = y >> m, cz = z >> m;
+    const uint32_t w = P.bits[j][(size_t(cz) * Rj + cy) * size_t(Rj >> 5) + size_t(cx >> 5)];
+    if (!((w >> (cx & 31)) & 1u)) {
+      code = uint32_t(1 + m);
+      break;
+    }
+  }
+  grid[v] = uint16_t((grid[v] & 0x1FFu) | (code << 9));
+}
+
 int launch_build_pyramid(ngprt_ctx* ctx, const uint8_t* occ_fine, hipStream_t st) {
   const ngprt_desc& d = ctx->desc;
   const int nl = d.occ_levels;
@@ -247,7 +274,11 @@ int launch_build_pyramid(ngprt_ctx* ctx, const uint8_t* occ_fine, hipStream_t st
   rc = check_launch(ctx, "pyr_unpack_kernel");
   if (rc == NGPRT_OK) rc = launch_build_distance(ctx, tmp, nullptr, st);
   (void)hipFreeAsync(tmp, st);
-  return rc;
+  if (rc) return rc;
+  PyrLevels P = {};
+  for (int j = 0; j < nl; ++j) P.bits[j] = ctx->pyr[j];
+  hipLaunchKernelGGL(pyr_code_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, ctx->grid, d.occ_res, jg, nl, P);
+  return check_launch(ctx, "pyr_code_kernel");
 }
 
 }  // namespace ngprt

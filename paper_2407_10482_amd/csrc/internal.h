@@ -70,6 +70,9 @@ struct SceneArgs {
   float gconst[4][2];
   // multi-level occupancy (pyr_n > 0): bit grids, level j of resolution pyrR[j]
   int pyr_n;
+  int pyr_jg;                     // pyramid level of the distance grid's resolution; its words hold
+                                  // in bits 9-11 the coarsest empty level >= pyr_jg (1 + level - pyr_jg,
+                                  // 0: all occupied)
   int use_dist;                   // consult the distance grid (Eq. 9) when the exiting level is coarser
   int view_mlp;                   // the deferred MLP is the view-dependent one (a separate pass)
   int pyrR[kMaxPyr];

@@ -91,6 +91,23 @@ __device__ __forceinline__ uint32_t voxel_of(const SceneArgs& S, const float p[3
   return uint32_t(q[0]) + uint32_t(S.R) * (uint32_t(q[1]) + uint32_t(S.R) * uint32_t(q[2]));
 }
 
+// Occupancy pyramid level j: the cell of grid coordinate u, and whether it
+// is empty (levels x fastest, 32 voxels per word).
+__device__ __forceinline__ void pyr_cell(const float u[3], int Rj, int q[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    int i = (int)floorf(u[a] * (float)Rj);
+    q[a] = i < 0 ? 0 : (i > Rj - 1 ? Rj - 1 : i);
+  }
+}
+__device__ __forceinline__ bool pyr_empty(const SceneArgs& S, int j, const float u[3]) {
+  const int Rj = S.pyrR[j];
+  int q[3];
+  pyr_cell(u, Rj, q);
+  const uint32_t w = S.pyr[j][(size_t(q[2]) * Rj + q[1]) * size_t(Rj >> 5) + size_t(q[0] >> 5)];
+  return !((w >> (q[0] & 31)) & 1u);
+}
+
 // Advance this lane's march to its next occupied lattice point.  Returns
 // true with (u, ts, ks) set when a sample was found; sets m.done when the
 // ray leaves the domain.
@@ -154,22 +171,25 @@ __device__ __forceinline__ bool march_next(const SceneArgs& S, MarchState& m, bo
       // reads counts marching points (lattice points checked), whatever the
       // number of levels read there
       ++reads;
+      // the coarsest empty level decides.  The distance grid's word carries
+      // it for the levels at and above the grid's resolution (one read for
+      // the code and G); only when all of those are occupied are the finer
+      // levels read, coarse to fine.  The exhaustive march reads level 0.
       int lev = -1;
-      int qe[3] = {0, 0, 0};
-      for (int j = naive ? 0 : S.pyr_n - 1; j >= 0; --j) {
-        const int Rj = S.pyrR[j];
-        int q[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          int i = (int)floorf(u[a] * (float)Rj);
-          q[a] = i < 0 ? 0 : (i > Rj - 1 ? Rj - 1 : i);
-        }
-        const uint32_t w =
-            S.pyr[j][(size_t(q[2]) * Rj + q[1]) * size_t(Rj >> 5) + size_t(q[0] >> 5)];
-        if (!((w >> (q[0] & 31)) & 1u)) {
-          lev = j;
-          qe[0] = q[0]; qe[1] = q[1]; qe[2] = q[2];
-          break;
+      uint32_t word = 0;
+      if (naive) {
+        lev = pyr_empty(S, 0, u) ? 0 : -1;
+      } else {
+        word = S.grid[v];
+        const uint32_t code = (word >> 9) & 7u;
+        if (code) {
+          lev = S.pyr_jg + int(code) - 1;
+        } else {
+          for (int j = S.pyr_jg - 1; j >= 0; --j)
+            if (pyr_empty(S, j, u)) {
+              lev = j;
+              break;
+            }
         }
       }
       if (lev < 0) {
@@ -179,10 +199,13 @@ __device__ __forceinline__ bool march_next(const SceneArgs& S, MarchState& m, bo
         return true;
       }
       if (naive) continue;
-      const int Rl = S.pyrR[lev];
+      int Rl = S.pyrR[0];
+#pragma unroll
+      for (int j = 1; j < kMaxPyr; ++j) Rl = lev == j ? S.pyrR[j] : Rl;
+      int qe[3];
+      pyr_cell(u, Rl, qe);
       const bool use_g = S.use_dist && Rl < S.R;
-      uint32_t g = 0;
-      if (use_g) g = S.grid[v] & 0xFFu;
+      const uint32_t g = use_g ? (word & 0xFFu) : 0u;
       const float vj = (-S.lo - S.lo) / (float)Rl;
       if (DOM == DOM_BOX) {
         float te = __int_as_float(0x7F800000);
