@@ -347,6 +347,20 @@ int ngprt_render_backward_reg(ngprt_ctx* ctx, int64_t n_rays, const float* dev_o
                               const float* dev_dirs, const float* dev_grad_rgb, const float* dev_grad_dist,
                               float* dev_grad_tables, float* dev_grad_mlp, void* stream);
 
+/* The backward of ngprt_render_backward (hash model) or
+ * ngprt_render_backward_baked (baked model; dev_grad_atlas as there, NULL
+ * for the hash model), 7-16-16-3 deferred MLP, without the regulariser,
+ * given the forward's per-ray composited features: dev_c_d float32 [n][3]
+ * and dev_feat float32 [n][4] as ngprt_render wrote them to out->c_d and
+ * out->feat for the same scene, MLP, step and rays (Eq. 5's C_d and F).
+ * The backward then skips its first re-march, which recomputes exactly
+ * these values, and gives the same gradients (the MLP gradient bit for
+ * bit).  NULL dev_c_d or dev_feat -> NGPRT_E_INVALID_ARG; the other
+ * conditions are those of the two entry points it stands for. */
+int ngprt_render_backward_fwd(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins, const float* dev_dirs,
+                              const float* dev_c_d, const float* dev_feat, const float* dev_grad_rgb,
+                              float* dev_grad_tables, float* dev_grad_atlas, float* dev_grad_mlp, void* stream);
+
 /* For callers that cannot allocate device memory (code under stream
  * capture, tight training loops, hosts that forbid allocation): the same
  * computation as ngprt_render_backward_reg (same arguments, conditions and

@@ -498,8 +498,8 @@ int ngprt_render_backward_reg(ngprt_ctx* ctx, int64_t n_rays, const float* dev_o
   if (n_rays == 0) return NGPRT_OK;
   int rc = check_backward_args(ctx, dev_origins, dev_dirs, dev_grad_rgb, dev_grad_tables, dev_grad_mlp);
   if (rc) return rc;
-  return launch_backward(ctx, n_rays, dev_origins, dev_dirs, dev_grad_rgb, dev_grad_dist, nullptr,
-                         dev_grad_tables, nullptr, dev_grad_mlp, (hipStream_t)stream);
+  return launch_backward(ctx, n_rays, dev_origins, dev_dirs, dev_grad_rgb, dev_grad_dist, nullptr, nullptr,
+                         nullptr, dev_grad_tables, nullptr, dev_grad_mlp, (hipStream_t)stream);
 }
 
 int ngprt_render_backward_baked(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins, const float* dev_dirs,
@@ -522,8 +522,8 @@ int ngprt_render_backward_baked(ngprt_ctx* ctx, int64_t n_rays, const float* dev
   if (rc) return rc;
   if (!ctx->mlp_loaded) return fail(ctx, NGPRT_E_NOT_LOADED, "mlp not loaded");
   if (ctx->n_blocks > 0 && !dev_grad_atlas) return fail(ctx, NGPRT_E_INVALID_ARG, "NULL pointer");
-  return launch_backward(ctx, n_rays, dev_origins, dev_dirs, dev_grad_rgb, dev_grad_dist, nullptr,
-                         dev_grad_tables, dev_grad_atlas, dev_grad_mlp, (hipStream_t)stream);
+  return launch_backward(ctx, n_rays, dev_origins, dev_dirs, dev_grad_rgb, dev_grad_dist, nullptr, nullptr,
+                         nullptr, dev_grad_tables, dev_grad_atlas, dev_grad_mlp, (hipStream_t)stream);
 }
 
 int ngprt_view_mlp_backward(ngprt_ctx* ctx, int64_t n_rays, const float* dev_dirs, const float* dev_c_d,
@@ -557,8 +557,36 @@ int ngprt_render_backward_features(ngprt_ctx* ctx, int64_t n_rays, const float* 
   int rc = check_ready(ctx);
   if (rc) return rc;
   if (baked && ctx->n_blocks > 0 && !dev_grad_atlas) return fail(ctx, NGPRT_E_INVALID_ARG, "NULL pointer");
-  return launch_backward(ctx, n_rays, dev_origins, dev_dirs, nullptr, dev_grad_dist, dev_grad_cf,
-                         dev_grad_tables, baked ? dev_grad_atlas : nullptr, nullptr, (hipStream_t)stream);
+  return launch_backward(ctx, n_rays, dev_origins, dev_dirs, nullptr, dev_grad_dist, dev_grad_cf, nullptr,
+                         nullptr, dev_grad_tables, baked ? dev_grad_atlas : nullptr, nullptr, (hipStream_t)stream);
+}
+
+int ngprt_render_backward_fwd(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins, const float* dev_dirs,
+                              const float* dev_c_d, const float* dev_feat, const float* dev_grad_rgb,
+                              float* dev_grad_tables, float* dev_grad_atlas, float* dev_grad_mlp, void* stream) {
+  if (!ctx) return NGPRT_E_INVALID_ARG;
+  if (n_rays < 0) return fail(ctx, NGPRT_E_INVALID_ARG, "n_rays < 0");
+  if (n_rays == 0) return NGPRT_OK;
+  if (!dev_c_d || !dev_feat) return fail(ctx, NGPRT_E_INVALID_ARG, "NULL pointer");
+  const bool baked = ctx->desc.feature_model == NGPRT_MODEL_BAKED;
+  if (baked) {
+    if (!dev_origins || !dev_dirs || !dev_grad_rgb || !dev_grad_tables || !dev_grad_mlp)
+      return fail(ctx, NGPRT_E_INVALID_ARG, "NULL pointer");
+    if (ctx->desc.table_dtype != NGPRT_F32) return fail(ctx, NGPRT_E_DTYPE, "backward needs float32 tables");
+    if (ctx->desc.aggregation != NGPRT_AGG_SEPARATE_V)
+      return fail(ctx, NGPRT_E_UNSUPPORTED, "the baked backward supports Separate-Att (V) only");
+    if (is_view_mlp(&ctx->desc))
+      return fail(ctx, NGPRT_E_UNSUPPORTED, "backward supports the 7-16-16-3 deferred MLP only");
+    int rc = check_ready(ctx);
+    if (rc) return rc;
+    if (!ctx->mlp_loaded) return fail(ctx, NGPRT_E_NOT_LOADED, "mlp not loaded");
+    if (ctx->n_blocks > 0 && !dev_grad_atlas) return fail(ctx, NGPRT_E_INVALID_ARG, "NULL pointer");
+  } else {
+    int rc = check_backward_args(ctx, dev_origins, dev_dirs, dev_grad_rgb, dev_grad_tables, dev_grad_mlp);
+    if (rc) return rc;
+  }
+  return launch_backward(ctx, n_rays, dev_origins, dev_dirs, dev_grad_rgb, nullptr, nullptr, dev_c_d, dev_feat,
+                         dev_grad_tables, baked ? dev_grad_atlas : nullptr, dev_grad_mlp, (hipStream_t)stream);
 }
 
 int ngprt_render_backward(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins, const float* dev_dirs,

@@ -367,6 +367,8 @@ __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, c
                                                        const float* __restrict__ grad_rgb,
                                                        const float* __restrict__ grad_dist,
                                                        const float* __restrict__ ups,
+                                                       const float* __restrict__ fcd,
+                                                       const float* __restrict__ ffv,
                                                        float* __restrict__ gtab, float* __restrict__ gatlas,
                                                        float* __restrict__ partial,
                                                        const float* __restrict__ P) {
@@ -385,11 +387,21 @@ __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, c
   const float gdist = (grad_dist && in_range) ? grad_dist[ray] : 0.0f;
   float dW = 0.0f, dS = 0.0f, dP = 0.0f, dQ = 0.0f;
 
-  // ---------------- pass 1: forward
+  // ---------------- pass 1: forward (or the forward's C_d and F, given:
+  // the same float32 values, so pass 1 is skipped; not with the regulariser,
+  // whose sums pass 1 also takes)
   MarchState m;
-  march_init<DOM>(S, o, d, in_range, m);
   float T = 1.0f, cd[3] = {0.f, 0.f, 0.f}, fv[4] = {0.f, 0.f, 0.f, 0.f};
   int ns = 0, reads = 0;
+  if (fcd) {
+    if (in_range) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) cd[j] = fcd[ray * 3 + j];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) fv[j] = ffv[ray * 4 + j];
+    }
+  } else {
+  march_init<DOM>(S, o, d, in_range, m);
   for (;;) {
     float u[3], ts;
     int ks;
@@ -414,6 +426,7 @@ __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, c
       ++ns;
       if (T < S.thr || ns >= S.max_samples) m.done = true;
     }
+  }
   }
 
   float gcd[3], gfv[4];
@@ -691,8 +704,8 @@ size_t backward_workspace_bytes(int64_t n) {
 }
 
 int launch_backward(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const float* grad_rgb,
-                    const float* grad_dist, const float* ups, float* gtab, float* gatlas, float* gmlp,
-                    hipStream_t st) {
+                    const float* grad_dist, const float* ups, const float* fcd, const float* ffv,
+                    float* gtab, float* gatlas, float* gmlp, hipStream_t st) {
   if ((n + 255) / 256 > 0x7FFFFFFF) return fail(ctx, NGPRT_E_SHAPE, "too many rays for one launch");
   const size_t need = backward_workspace_bytes(n);
   if (need > ctx->ws_bytes) {
@@ -705,13 +718,13 @@ int launch_backward(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, c
     }
     ctx->ws_bytes = need;
   }
-  return launch_backward_ws(ctx, n, o, d, grad_rgb, grad_dist, ups, gtab, gatlas, gmlp,
+  return launch_backward_ws(ctx, n, o, d, grad_rgb, grad_dist, ups, fcd, ffv, gtab, gatlas, gmlp,
                             reinterpret_cast<float*>(ctx->ws), st);
 }
 
 int launch_backward_ws(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const float* grad_rgb,
-                       const float* grad_dist, const float* ups, float* gtab, float* gatlas, float* gmlp,
-                       float* partial, hipStream_t st) {
+                       const float* grad_dist, const float* ups, const float* fcd, const float* ffv,
+                       float* gtab, float* gatlas, float* gmlp, float* partial, hipStream_t st) {
   SceneArgs S = scene_args(ctx);
   const int64_t blocks = (n + 255) / 256;
   if (blocks > 0x7FFFFFFF) return fail(ctx, NGPRT_E_SHAPE, "too many rays for one launch");
@@ -720,7 +733,7 @@ int launch_backward_ws(ngprt_ctx* ctx, int64_t n, const float* o, const float* d
   const bool box = ctx->desc.domain == DOM_BOX;
 #define NGPRT_BW(DOMV, LM, PY, MD)                                                                 \
   hipLaunchKernelGGL((backward_kernel<DOMV, LM, PY, MD>), g, dim3(256), 0, st, S, n, o, d, grad_rgb,   \
-                     grad_dist, ups, gtab, gatlas, partial, ctx->mlp)
+                     grad_dist, ups, fcd, ffv, gtab, gatlas, partial, ctx->mlp)
   if (S.model == NGPRT_MODEL_BAKED) {
     // L <= 2 fine levels: coarse rows of at most 12 channels, so the wave
     // sums in the coarse scatter carry 12 values instead of 16

@@ -147,15 +147,17 @@ int launch_eval_points(ngprt_ctx* ctx, int64_t n, const float* pos, int32_t* idx
                        float* weights, hipStream_t s);
 int launch_march(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, int32_t cap,
                  int32_t* sk, int32_t* ns, int32_t* nr, int naive, hipStream_t s);
+// fcd, ffv: the forward's per-ray C_d [n][3] and F [n][4], or NULL (pass 1
+// recomputes them); given only without grad_dist
 int launch_backward(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const float* grad_rgb,
-                    const float* grad_dist, const float* ups, float* gtab, float* gatlas, float* gmlp,
-                    hipStream_t s);
+                    const float* grad_dist, const float* ups, const float* fcd, const float* ffv,
+                    float* gtab, float* gatlas, float* gmlp, hipStream_t s);
 // workspace of launch_backward_ws: one MLP-gradient partial per wave of 64
 // rays plus kSumGroups group sums, every element written before it is read
 size_t backward_workspace_bytes(int64_t n);
 int launch_backward_ws(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const float* grad_rgb,
-                       const float* grad_dist, const float* ups, float* gtab, float* gatlas, float* gmlp,
-                       float* workspace, hipStream_t s);
+                       const float* grad_dist, const float* ups, const float* fcd, const float* ffv,
+                       float* gtab, float* gatlas, float* gmlp, float* workspace, hipStream_t s);
 int init_static_scratch(ngprt_ctx* ctx);
 // sum of n int32 counts on the GPU in a fixed order; synchronises the stream
 int sum_counts(ngprt_ctx* ctx, int64_t n, const int32_t* counts, long long* host_total, hipStream_t s);

@@ -74,7 +74,7 @@ extern "C" int ngprt_render_backward_noalloc(ngprt_ctx* ctx, int64_t n_rays, con
     return fail(ctx, NGPRT_E_SHAPE, "workspace exceeds the static scratch");
   void* ws = scratch_of(ctx->device);
   if (!ws) return fail(ctx, NGPRT_E_HIP, "the static scratch of this device was not found at ngprt_create");
-  return launch_backward_ws(ctx, n_rays, dev_origins, dev_dirs, dev_grad_rgb, dev_grad_dist, nullptr,
-                            dev_grad_tables, nullptr, dev_grad_mlp, reinterpret_cast<float*>(ws),
+  return launch_backward_ws(ctx, n_rays, dev_origins, dev_dirs, dev_grad_rgb, dev_grad_dist, nullptr, nullptr,
+                            nullptr, dev_grad_tables, nullptr, dev_grad_mlp, reinterpret_cast<float*>(ws),
                             (hipStream_t)stream);
 }

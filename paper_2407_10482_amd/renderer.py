@@ -326,6 +326,26 @@ def _renderer_backward_baked(self: Renderer, origins, dirs, grad_rgb, grad_table
           self.ctx)
 
 
+def _renderer_backward_fwd(self: Renderer, origins, dirs, c_d, feat, grad_rgb, grad_tables, grad_mlp,
+                           grad_atlas=None):
+    """backward (hash model) or backward_baked (baked model) without the
+    regulariser, given the forward's c_d [n, 3] and feat [n, 4] from render()
+    of the same scene and rays: the library skips its first re-march."""
+    n = origins.shape[0]
+    _dev(c_d, torch.float32, (n, 3), "c_d")
+    _dev(feat, torch.float32, (n, 4), "feat")
+    _dev(grad_rgb, torch.float32, (n, 3), "grad_rgb")
+    _dev(grad_tables, torch.float32, (self.L, self.T, 9), "grad_tables")
+    _dev(grad_mlp, torch.float32, (self.n_mlp,), "grad_mlp")
+    nblk = getattr(self, "n_blocks", 0) if self.feature_model == MODEL_BAKED else 0
+    if nblk:
+        _dev(grad_atlas, torch.float32, (nblk, 8, 8, 8, 8 + 2 * self.L), "grad_atlas")
+    check(self.lib.ngprt_render_backward_fwd(self.ctx, n, _ptr(origins), _ptr(dirs), _ptr(c_d), _ptr(feat),
+                                             _ptr(grad_rgb), _ptr(grad_tables),
+                                             _ptr(grad_atlas) if nblk else None, _ptr(grad_mlp), _stream()),
+          self.ctx)
+
+
 def _renderer_view_mlp_backward(self: Renderer, dirs, c_d, feat, grad_rgb, grad_mlp) -> torch.Tensor:
     """View-dependent MLP: dL/dC_d and dL/dF per ray [n, 7] for dL/drgb,
     accumulating dL/dpsi [5891] into grad_mlp."""
@@ -369,6 +389,7 @@ Renderer.backward_noalloc = _renderer_backward_noalloc
 Renderer.backward_baked = _renderer_backward_baked
 Renderer.view_mlp_backward = _renderer_view_mlp_backward
 Renderer.backward_features = _renderer_backward_features
+Renderer.backward_fwd = _renderer_backward_fwd
 Renderer.set_step = _renderer_set_step
 
 
@@ -407,6 +428,20 @@ def adam_step(param: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch
                                          float(lr), float(beta1), float(beta2), float(eps), _stream()))
 
 
+def _forward_outputs(n: int, device, with_dist: bool) -> dict:
+    """Output buffers of a differentiable forward: rgb, and either the
+    per-ray regulariser value or the composited C_d and F that the backward
+    then takes instead of re-marching for them."""
+    f = dict(dtype=torch.float32, device=device)
+    out = {"rgb": torch.empty((n, 3), **f)}
+    if with_dist:
+        out["dist_loss"] = torch.empty((n,), **f)
+    else:
+        out["c_d"] = torch.empty((n, 3), **f)
+        out["feat"] = torch.empty((n, 4), **f)
+    return out
+
+
 def _same_scene(renderer: Renderer, gen: int):
     """The library's backward recomputes the forward from the scene loaded in
     the renderer: refuse when it changed since the forward."""
@@ -427,30 +462,34 @@ class RenderFunction(torch.autograd.Function):
         renderer.load_tables(tables.detach().contiguous())
         renderer.load_mlp(mlp.detach().contiguous())
         n = origins.shape[0]
-        out = {"rgb": torch.empty((n, 3), dtype=torch.float32, device=origins.device)}
-        if with_dist:
-            out["dist_loss"] = torch.empty((n,), dtype=torch.float32, device=origins.device)
+        out = _forward_outputs(n, origins.device, with_dist)
         renderer.render(origins, dirs, out=out)
         ctx.renderer = renderer
         ctx.load_gen = renderer.load_gen
         ctx.with_dist = with_dist
-        ctx.save_for_backward(origins, dirs)
         if not with_dist:
+            # the backward takes the forward's C_d and F instead of re-marching for them
+            ctx.save_for_backward(origins, dirs, out["c_d"], out["feat"])
             dist = torch.zeros((n,), dtype=torch.float32, device=origins.device)
             ctx.mark_non_differentiable(dist)
             return out["rgb"], dist
+        ctx.save_for_backward(origins, dirs)
         return out["rgb"], out["dist_loss"]
 
     @staticmethod
     def backward(ctx, grad_rgb, grad_dist):
-        origins, dirs = ctx.saved_tensors
+        saved = ctx.saved_tensors
+        origins, dirs = saved[0], saved[1]
         r = ctx.renderer
         _same_scene(r, ctx.load_gen)
         gt = torch.zeros((r.L, r.T, 9), dtype=torch.float32, device=origins.device)
         gm = torch.zeros((r.n_mlp,), dtype=torch.float32, device=origins.device)
         if grad_rgb is None:
             grad_rgb = torch.zeros((origins.shape[0], 3), dtype=torch.float32, device=origins.device)
-        gdist = grad_dist.contiguous().float() if (ctx.with_dist and grad_dist is not None) else None
+        if not ctx.with_dist:
+            r.backward_fwd(origins, dirs, saved[2], saved[3], grad_rgb.contiguous().float(), gt, gm)
+            return gt, gm, None, None, None, None
+        gdist = grad_dist.contiguous().float() if grad_dist is not None else None
         r.backward(origins, dirs, grad_rgb.contiguous().float(), gt, gm, gdist)
         return gt, gm, None, None, None, None
 
@@ -467,24 +506,24 @@ class BakedRenderFunction(torch.autograd.Function):
         renderer.load_coarse(renderer._coarse_index, atlas.detach().contiguous(), renderer._coarse_default)
         renderer.load_mlp(mlp.detach().contiguous())
         n = origins.shape[0]
-        out = {"rgb": torch.empty((n, 3), dtype=torch.float32, device=origins.device)}
-        if with_dist:
-            out["dist_loss"] = torch.empty((n,), dtype=torch.float32, device=origins.device)
+        out = _forward_outputs(n, origins.device, with_dist)
         renderer.render(origins, dirs, out=out)
         ctx.renderer = renderer
         ctx.load_gen = renderer.load_gen
         ctx.with_dist = with_dist
         ctx.atlas_shape = tuple(atlas.shape)
-        ctx.save_for_backward(origins, dirs)
         if not with_dist:
+            ctx.save_for_backward(origins, dirs, out["c_d"], out["feat"])
             dist = torch.zeros((n,), dtype=torch.float32, device=origins.device)
             ctx.mark_non_differentiable(dist)
             return out["rgb"], dist
+        ctx.save_for_backward(origins, dirs)
         return out["rgb"], out["dist_loss"]
 
     @staticmethod
     def backward(ctx, grad_rgb, grad_dist):
-        origins, dirs = ctx.saved_tensors
+        saved = ctx.saved_tensors
+        origins, dirs = saved[0], saved[1]
         r = ctx.renderer
         _same_scene(r, ctx.load_gen)
         gt = torch.zeros((r.L, r.T, 9), dtype=torch.float32, device=origins.device)
@@ -492,7 +531,10 @@ class BakedRenderFunction(torch.autograd.Function):
         gm = torch.zeros((r.n_mlp,), dtype=torch.float32, device=origins.device)
         if grad_rgb is None:
             grad_rgb = torch.zeros((origins.shape[0], 3), dtype=torch.float32, device=origins.device)
-        gdist = grad_dist.contiguous().float() if (ctx.with_dist and grad_dist is not None) else None
+        if not ctx.with_dist:
+            r.backward_fwd(origins, dirs, saved[2], saved[3], grad_rgb.contiguous().float(), gt, gm, ga)
+            return gt, ga, gm, None, None, None, None
+        gdist = grad_dist.contiguous().float() if grad_dist is not None else None
         r.backward_baked(origins, dirs, grad_rgb.contiguous().float(), gt, ga, gm, gdist)
         return gt, ga, gm, None, None, None, None
 

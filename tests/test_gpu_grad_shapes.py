@@ -112,3 +112,43 @@ def test_baked_backward_three_and_four_fine_levels(name):
     _close(_np(gt), gf64, "fine tables")
     _close(_np(ga), ga64, "atlas")
     assert np.allclose(_np(gm), gm64, rtol=1e-3, atol=1e-5 * np.abs(gm64).max())
+
+
+@pytest.mark.parametrize("name", ["tiny", "train_large", "hd", "baked_tiny"])
+def test_backward_from_forward_outputs_matches(name):
+    """ngprt_render_backward_fwd (the forward's C_d and F given, first
+    re-march skipped) against the backward that re-marches for them: MLP
+    gradient bit for bit (fixed-order sums), table and atlas gradients to
+    the rounding of the atomic adds' order."""
+    import torch
+    print(f"[backward from forward outputs {name}]", flush=True)
+    sc, dist, cfg, o, d = _rays(name, 2048, 7)
+    r = gpu_renderer(name)
+    go, gd = to_gpu(o, d)
+    n = len(o)
+    out = {"rgb": torch.empty((n, 3), dtype=torch.float32, device="cuda"),
+           "c_d": torch.empty((n, 3), dtype=torch.float32, device="cuda"),
+           "feat": torch.empty((n, 4), dtype=torch.float32, device="cuda")}
+    r.render(go, gd, out=out)
+    g_rgb = torch.from_numpy(np.random.default_rng(2).standard_normal((n, 3)).astype(np.float32)).cuda()
+    baked = sc.cfg.model == synth.MODEL_BAKED
+    grads = []
+    for use_fwd in (False, True):
+        gt = torch.zeros((r.L, r.T, 9), dtype=torch.float32, device="cuda")
+        gm = torch.zeros((451,), dtype=torch.float32, device="cuda")
+        ga = torch.zeros(sc.atlas.shape, dtype=torch.float32, device="cuda") if baked else None
+        if use_fwd:
+            r.backward_fwd(go, gd, out["c_d"], out["feat"], g_rgb, gt, gm, ga)
+        elif baked:
+            r.backward_baked(go, gd, g_rgb, gt, ga, gm)
+        else:
+            r.backward(go, gd, g_rgb, gt, gm)
+        torch.cuda.synchronize()
+        grads.append((_np(gt), _np(gm), None if ga is None else _np(ga)))
+    (t0, m0, a0), (t1, m1, a1) = grads
+    assert np.array_equal(m0.view(np.uint32), m1.view(np.uint32))
+    assert np.abs(t0).max() > 0
+    assert np.allclose(t1, t0, rtol=1e-5, atol=1e-6 * np.abs(t0).max())
+    assert np.array_equal(t0 != 0, t1 != 0)
+    if baked:
+        assert np.allclose(a1, a0, rtol=1e-5, atol=1e-6 * np.abs(a0).max())
