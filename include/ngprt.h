@@ -414,10 +414,15 @@ int ngprt_view_mlp_backward(ngprt_ctx* ctx, int64_t n_rays, const float* dev_dir
  * and, for NGPRT_MODEL_BAKED, dL/datlas into dev_grad_atlas (layouts and
  * conditions as ngprt_render_backward_reg / ngprt_render_backward_baked;
  * dev_grad_atlas is ignored for the hash model).  dev_grad_dist as in
- * ngprt_render_backward_reg. */
+ * ngprt_render_backward_reg.  dev_c_d [n][3] and dev_feat [n][4]: the
+ * forward's composited C_d and F (out->c_d, out->feat of ngprt_render on
+ * the same scene and rays), or both NULL; given, the first re-march that
+ * recomputes them is skipped (same gradients).  Not with dev_grad_dist
+ * (NGPRT_E_INVALID_ARG), nor one of the two alone. */
 int ngprt_render_backward_features(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins,
                                    const float* dev_dirs, const float* dev_grad_cf, const float* dev_grad_dist,
-                                   float* dev_grad_tables, float* dev_grad_atlas, void* stream);
+                                   float* dev_grad_tables, float* dev_grad_atlas, const float* dev_c_d,
+                                   const float* dev_feat, void* stream);
 
 /* Change the lattice step (the paper's marching-step auto-tuning,
  * supplement Eq. S3, scales it between training batches).  Same checks as

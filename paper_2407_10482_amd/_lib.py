@@ -90,7 +90,7 @@ SIGNATURES = [
     ("ngprt_render_backward_baked", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P]),
     ("ngprt_render_backward_fwd", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     ("ngprt_view_mlp_backward", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P]),
-    ("ngprt_render_backward_features", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P]),
+    ("ngprt_render_backward_features", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     ("ngprt_set_step", ctypes.c_int, [_P, ctypes.c_float]),
     ("ngprt_step_autotune", ctypes.c_int, [_P, _I64, _P, ctypes.POINTER(NgprtStepTuner), _P]),
     ("ngprt_adam_step", ctypes.c_int, [_I64, _P, _P, _P, _P, _I32, ctypes.c_float, ctypes.c_float,

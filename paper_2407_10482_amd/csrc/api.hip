@@ -543,12 +543,17 @@ int ngprt_view_mlp_backward(ngprt_ctx* ctx, int64_t n_rays, const float* dev_dir
 
 int ngprt_render_backward_features(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins,
                                    const float* dev_dirs, const float* dev_grad_cf, const float* dev_grad_dist,
-                                   float* dev_grad_tables, float* dev_grad_atlas, void* stream) {
+                                   float* dev_grad_tables, float* dev_grad_atlas, const float* dev_c_d,
+                                   const float* dev_feat, void* stream) {
   if (!ctx) return NGPRT_E_INVALID_ARG;
   if (n_rays < 0) return fail(ctx, NGPRT_E_INVALID_ARG, "n_rays < 0");
   if (n_rays == 0) return NGPRT_OK;
   if (!dev_origins || !dev_dirs || !dev_grad_cf || !dev_grad_tables)
     return fail(ctx, NGPRT_E_INVALID_ARG, "NULL pointer");
+  if ((dev_c_d == nullptr) != (dev_feat == nullptr))
+    return fail(ctx, NGPRT_E_INVALID_ARG, "dev_c_d and dev_feat go together");
+  if (dev_c_d && dev_grad_dist)
+    return fail(ctx, NGPRT_E_INVALID_ARG, "the forward's C_d and F are taken without the regulariser only");
   if (ctx->desc.table_dtype != NGPRT_F32)
     return fail(ctx, NGPRT_E_DTYPE, "backward needs float32 tables");
   const bool baked = ctx->desc.feature_model == NGPRT_MODEL_BAKED;
@@ -557,8 +562,8 @@ int ngprt_render_backward_features(ngprt_ctx* ctx, int64_t n_rays, const float* 
   int rc = check_ready(ctx);
   if (rc) return rc;
   if (baked && ctx->n_blocks > 0 && !dev_grad_atlas) return fail(ctx, NGPRT_E_INVALID_ARG, "NULL pointer");
-  return launch_backward(ctx, n_rays, dev_origins, dev_dirs, nullptr, dev_grad_dist, dev_grad_cf, nullptr,
-                         nullptr, dev_grad_tables, baked ? dev_grad_atlas : nullptr, nullptr, (hipStream_t)stream);
+  return launch_backward(ctx, n_rays, dev_origins, dev_dirs, nullptr, dev_grad_dist, dev_grad_cf, dev_c_d,
+                         dev_feat, dev_grad_tables, baked ? dev_grad_atlas : nullptr, nullptr, (hipStream_t)stream);
 }
 
 int ngprt_render_backward_fwd(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins, const float* dev_dirs,

@@ -362,11 +362,15 @@ def _renderer_view_mlp_backward(self: Renderer, dirs, c_d, feat, grad_rgb, grad_
 
 
 def _renderer_backward_features(self: Renderer, origins, dirs, grad_cf, grad_tables, grad_atlas=None,
-                                grad_dist=None):
+                                grad_dist=None, c_d=None, feat=None):
     """Accumulate dL/dtables (and, baked model, dL/datlas) from dL/dC_d and
-    dL/dF per ray [n, 7]."""
+    dL/dF per ray [n, 7].  c_d [n, 3], feat [n, 4]: the forward's, if at
+    hand (then the library skips its first re-march; not with grad_dist)."""
     n = origins.shape[0]
     _dev(grad_cf, torch.float32, (n, 7), "grad_cf")
+    if c_d is not None or feat is not None:
+        _dev(c_d, torch.float32, (n, 3), "c_d")
+        _dev(feat, torch.float32, (n, 4), "feat")
     _dev(grad_tables, torch.float32, (self.L, self.T, 9), "grad_tables")
     if grad_dist is not None:
         _dev(grad_dist, torch.float32, (n,), "grad_dist")
@@ -375,7 +379,8 @@ def _renderer_backward_features(self: Renderer, origins, dirs, grad_cf, grad_tab
         _dev(grad_atlas, torch.float32, (nblk, 8, 8, 8, 8 + 2 * self.L), "grad_atlas")
     check(self.lib.ngprt_render_backward_features(self.ctx, n, _ptr(origins), _ptr(dirs), _ptr(grad_cf),
                                                   _ptr(grad_dist), _ptr(grad_tables),
-                                                  _ptr(grad_atlas) if nblk else None, _stream()), self.ctx)
+                                                  _ptr(grad_atlas) if nblk else None, _ptr(c_d), _ptr(feat),
+                                                  _stream()), self.ctx)
 
 
 def _renderer_set_step(self: Renderer, step: float):
@@ -583,7 +588,11 @@ class ViewRenderFunction(torch.autograd.Function):
         grad_cf = r.view_mlp_backward(dirs, c_d, feat, grad_rgb.contiguous().float(), gm)
         gt = torch.zeros((r.L, r.T, 9), dtype=torch.float32, device=dev)
         ga = None if ctx.atlas_shape is None else torch.zeros(ctx.atlas_shape, dtype=torch.float32, device=dev)
-        gdist = grad_dist.contiguous().float() if (ctx.with_dist and grad_dist is not None) else None
+        if not ctx.with_dist:
+            # the forward's C_d and F stand in for the backward's first re-march
+            r.backward_features(origins, dirs, grad_cf, gt, ga, None, c_d, feat)
+            return gt, ga, gm, None, None, None, None
+        gdist = grad_dist.contiguous().float() if grad_dist is not None else None
         r.backward_features(origins, dirs, grad_cf, gt, ga, gdist)
         return gt, ga, gm, None, None, None, None
 
