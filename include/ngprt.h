@@ -361,6 +361,14 @@ int ngprt_render_backward_fwd(ngprt_ctx* ctx, int64_t n_rays, const float* dev_o
                               const float* dev_c_d, const float* dev_feat, const float* dev_grad_rgb,
                               float* dev_grad_tables, float* dev_grad_atlas, float* dev_grad_mlp, void* stream);
 
+/* Test hook for failure handling (not for production use): after `after`
+ * more successful device allocations by the library (any context, any
+ * thread), the next one fails as if the device were out of memory, and the
+ * hook disarms; after < 0 disarms it.  The call that meets the failure
+ * returns NGPRT_E_ALLOC (ngprt_create: and no context) and leaves its
+ * context usable.  Always NGPRT_OK. */
+int ngprt_test_fail_alloc(int64_t after);
+
 /* For callers that cannot allocate device memory (code under stream
  * capture, tight training loops, hosts that forbid allocation): the same
  * computation as ngprt_render_backward_reg (same arguments, conditions and

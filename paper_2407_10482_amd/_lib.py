@@ -89,6 +89,7 @@ SIGNATURES = [
     ("ngprt_render_backward_noalloc", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P]),
     ("ngprt_render_backward_baked", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P]),
     ("ngprt_render_backward_fwd", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    ("ngprt_test_fail_alloc", ctypes.c_int, [_I64]),
     ("ngprt_view_mlp_backward", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P]),
     ("ngprt_render_backward_features", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     ("ngprt_set_step", ctypes.c_int, [_P, ctypes.c_float]),

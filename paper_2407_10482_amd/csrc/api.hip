@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -97,6 +98,27 @@ static bool is_view_mlp(const ngprt_desc* d) { return d->mlp_hidden == 64; }
 static int mlp_param_count(const ngprt_desc* d) { return is_view_mlp(d) ? kMlpViewParams : kMlpParams; }
 
 static size_t dtype_bytes(int dt) { return dt == DT_F32 ? 4 : (dt == DT_BF16 ? 2 : 1); }
+
+// armed: the number of device allocations still to succeed before one fails
+static std::atomic<int64_t> g_fail_alloc_after{-1};
+
+static bool injected_alloc_failure() {
+  int64_t k = g_fail_alloc_after.load();
+  while (k >= 0) {
+    if (g_fail_alloc_after.compare_exchange_weak(k, k - 1)) return k == 0;
+  }
+  return false;
+}
+
+hipError_t dev_malloc(void** p, size_t bytes) {
+  if (injected_alloc_failure()) return hipErrorOutOfMemory;
+  return hipMalloc(p, bytes);
+}
+
+hipError_t dev_malloc_async(void** p, size_t bytes, hipStream_t s) {
+  if (injected_alloc_failure()) return hipErrorOutOfMemory;
+  return hipMallocAsync(p, bytes, s);
+}
 
 }  // namespace ngprt
 
@@ -199,6 +221,11 @@ void ngprt_destroy(ngprt_ctx* ctx) {
   delete ctx;
 }
 
+int ngprt_test_fail_alloc(int64_t after) {
+  g_fail_alloc_after.store(after < 0 ? -1 : after);
+  return NGPRT_OK;
+}
+
 int ngprt_create(const ngprt_desc* desc, ngprt_ctx** out) {
   if (!out) return NGPRT_E_INVALID_ARG;
   int rc = ngprt_validate_desc(desc);
@@ -217,13 +244,13 @@ int ngprt_create(const ngprt_desc* desc, ngprt_ctx** out) {
   const int64_t L = desc->n_levels;
   const size_t eb = dtype_bytes(desc->table_dtype);
   const int64_t R = desc->occ_res;
-  bool ok = hipMalloc(&ctx->feat, size_t(L * ctx->T * 8) * eb) == hipSuccess &&
-            hipMalloc(&ctx->logit, size_t(L * ctx->T) * eb) == hipSuccess &&
-            hipMalloc((void**)&ctx->scales_dev, sizeof(float) * (NGPRT_MAX_LEVELS * 9 + 1)) == hipSuccess &&
-            hipMalloc((void**)&ctx->grid, size_t(R * R * R) * sizeof(uint16_t)) == hipSuccess &&
-            hipMalloc((void**)&ctx->mlp, sizeof(float) * mlp_param_count(desc)) == hipSuccess &&
+  bool ok = dev_malloc((void**)&ctx->feat, size_t(L * ctx->T * 8) * eb) == hipSuccess &&
+            dev_malloc((void**)&ctx->logit, size_t(L * ctx->T) * eb) == hipSuccess &&
+            dev_malloc((void**)&ctx->scales_dev, sizeof(float) * (NGPRT_MAX_LEVELS * 9 + 1)) == hipSuccess &&
+            dev_malloc((void**)&ctx->grid, size_t(R * R * R) * sizeof(uint16_t)) == hipSuccess &&
+            dev_malloc((void**)&ctx->mlp, sizeof(float) * mlp_param_count(desc)) == hipSuccess &&
             (!is_view_mlp(desc) ||
-             hipMalloc((void**)&ctx->mlp_rec, sizeof(float) * kMlpViewRec) == hipSuccess);
+             dev_malloc((void**)&ctx->mlp_rec, sizeof(float) * kMlpViewRec) == hipSuccess);
   if (ok)
     ok = hipMemcpy(ctx->scales_dev, &ctx->scales_host[0][0], sizeof(float) * NGPRT_MAX_LEVELS * 9,
                    hipMemcpyHostToDevice) == hipSuccess;
@@ -281,9 +308,9 @@ int ngprt_load_coarse(ngprt_ctx* ctx, int64_t n_blocks, const int32_t* dev_block
     ctx->cidx = nullptr;
     ctx->catlas = nullptr;
     ctx->n_blocks = -1;
-    if (hipMalloc((void**)&ctx->cidx, sizeof(int32_t) * n_idx) != hipSuccess ||
+    if (dev_malloc((void**)&ctx->cidx, sizeof(int32_t) * n_idx) != hipSuccess ||
         (n_blocks > 0 &&
-         hipMalloc((void**)&ctx->catlas, sizeof(float) * size_t(n_blocks) * 512 * Cpad) != hipSuccess)) {
+         dev_malloc((void**)&ctx->catlas, sizeof(float) * size_t(n_blocks) * 512 * Cpad) != hipSuccess)) {
       (void)hipGetLastError();
       return fail(ctx, NGPRT_E_ALLOC, "coarse grid allocation failed");
     }

@@ -124,9 +124,9 @@ int launch_build_distance(ngprt_ctx* ctx, const uint8_t* occ, const uint8_t* dis
   uint8_t* dil = nullptr;
   int* f0 = nullptr;
   int* f1 = nullptr;
-  if (hipMallocAsync((void**)&dil, size_t(n), st) != hipSuccess ||
-      hipMallocAsync((void**)&f0, size_t(n) * sizeof(int), st) != hipSuccess ||
-      hipMallocAsync((void**)&f1, size_t(n) * sizeof(int), st) != hipSuccess) {
+  if (dev_malloc_async((void**)&dil, size_t(n), st) != hipSuccess ||
+      dev_malloc_async((void**)&f0, size_t(n) * sizeof(int), st) != hipSuccess ||
+      dev_malloc_async((void**)&f1, size_t(n) * sizeof(int), st) != hipSuccess) {
     if (dil) (void)hipFreeAsync(dil, st);
     if (f0) (void)hipFreeAsync(f0, st);
     (void)hipGetLastError();
@@ -241,7 +241,7 @@ int launch_build_pyramid(ngprt_ctx* ctx, const uint8_t* occ_fine, hipStream_t st
   for (int j = 0; j < nl; ++j) {
     if (!ctx->pyr[j]) {
       const int64_t Rj = int64_t(d.occ_fine_res) >> j;
-      if (hipMalloc((void**)&ctx->pyr[j], size_t(Rj * Rj * Rj / 32) * sizeof(uint32_t)) != hipSuccess) {
+      if (dev_malloc((void**)&ctx->pyr[j], size_t(Rj * Rj * Rj / 32) * sizeof(uint32_t)) != hipSuccess) {
         (void)hipGetLastError();
         return fail(ctx, NGPRT_E_ALLOC, "occupancy pyramid allocation failed");
       }
@@ -266,7 +266,7 @@ int launch_build_pyramid(ngprt_ctx* ctx, const uint8_t* occ_fine, hipStream_t st
   if (jg < 0) return fail(ctx, NGPRT_E_SHAPE, "occ_res is not a pyramid resolution");
   const int64_t n = int64_t(d.occ_res) * d.occ_res * d.occ_res;
   uint8_t* tmp = nullptr;
-  if (hipMallocAsync((void**)&tmp, size_t(n), st) != hipSuccess) {
+  if (dev_malloc_async((void**)&tmp, size_t(n), st) != hipSuccess) {
     (void)hipGetLastError();
     return fail(ctx, NGPRT_E_ALLOC, "pyramid scratch allocation failed");
   }

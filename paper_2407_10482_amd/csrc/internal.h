@@ -159,6 +159,10 @@ int launch_backward_ws(ngprt_ctx* ctx, int64_t n, const float* o, const float* d
                        const float* grad_dist, const float* ups, const float* fcd, const float* ffv,
                        float* gtab, float* gatlas, float* gmlp, float* workspace, hipStream_t s);
 int init_static_scratch(ngprt_ctx* ctx);
+// Every device allocation of the library goes through these two, so that a
+// test can make one fail (ngprt_test_fail_alloc).
+hipError_t dev_malloc(void** p, size_t bytes);
+hipError_t dev_malloc_async(void** p, size_t bytes, hipStream_t s);
 // sum of n int32 counts on the GPU in a fixed order; synchronises the stream
 int sum_counts(ngprt_ctx* ctx, int64_t n, const int32_t* counts, long long* host_total, hipStream_t s);
 int check_backward_args(ngprt_ctx* ctx, const float* o, const float* d, const float* grad_rgb,

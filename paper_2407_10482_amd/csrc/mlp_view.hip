@@ -339,7 +339,7 @@ int launch_view_mlp_backward(ngprt_ctx* ctx, int64_t n, const float* d, const fl
     if (ctx->ws) (void)hipFreeAsync(ctx->ws, st);
     ctx->ws = nullptr;
     ctx->ws_bytes = 0;
-    if (hipMallocAsync(&ctx->ws, need, st) != hipSuccess) {
+    if (dev_malloc_async((void**)&ctx->ws, need, st) != hipSuccess) {
       (void)hipGetLastError();
       return fail(ctx, NGPRT_E_ALLOC, "view MLP backward workspace allocation failed");
     }

@@ -324,19 +324,19 @@ __global__ void prop_cast_kernel(const float* __restrict__ P, uint16_t* __restri
 }
 
 static int ensure_prop_buffers(ngprt_ctx* ctx, int64_t n_waves, hipStream_t st) {
-  if (!ctx->prop_wb) {
-    if (hipMallocAsync(&ctx->prop_wb, kPParams * sizeof(uint16_t), st) != hipSuccess ||
-        hipMallocAsync(&ctx->prop_grad, kPParams * sizeof(float), st) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(ctx, NGPRT_E_ALLOC, "proposal buffers");
-    }
+  // each buffer on its own, so that a failed call leaves nothing half made
+  if ((!ctx->prop_wb &&
+       dev_malloc_async((void**)&ctx->prop_wb, kPParams * sizeof(uint16_t), st) != hipSuccess) ||
+      (!ctx->prop_grad && dev_malloc_async((void**)&ctx->prop_grad, kPParams * sizeof(float), st) != hipSuccess)) {
+    (void)hipGetLastError();
+    return fail(ctx, NGPRT_E_ALLOC, "proposal buffers");
   }
   const size_t need = size_t(n_waves) * kPPartial * sizeof(float);
   if (need > ctx->ws_bytes) {
     if (ctx->ws) (void)hipFreeAsync(ctx->ws, st);
     ctx->ws = nullptr;
     ctx->ws_bytes = 0;
-    if (hipMallocAsync(&ctx->ws, need, st) != hipSuccess) {
+    if (dev_malloc_async((void**)&ctx->ws, need, st) != hipSuccess) {
       (void)hipGetLastError();
       return fail(ctx, NGPRT_E_ALLOC, "proposal workspace");
     }
@@ -357,7 +357,7 @@ int launch_prop_arrange(ngprt_ctx* ctx, const float* P, void* dst, hipStream_t s
 
 int launch_prop_infer(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const float* P, float* out,
                       hipStream_t st) {
-  if (!ctx->prop_tmp && hipMalloc(&ctx->prop_tmp, kPropNetBytes) != hipSuccess) {
+  if (!ctx->prop_tmp && dev_malloc((void**)&ctx->prop_tmp, kPropNetBytes) != hipSuccess) {
     (void)hipGetLastError();
     ctx->prop_tmp = nullptr;
     return fail(ctx, NGPRT_E_ALLOC, "proposal inference weights");
@@ -374,7 +374,7 @@ int launch_prop_infer(ngprt_ctx* ctx, int64_t n, const float* o, const float* d,
 }
 
 int load_proposal(ngprt_ctx* ctx, const float* P, hipStream_t st) {
-  if (!ctx->prop_net && hipMalloc(&ctx->prop_net, kPropNetBytes) != hipSuccess) {
+  if (!ctx->prop_net && dev_malloc((void**)&ctx->prop_net, kPropNetBytes) != hipSuccess) {
     (void)hipGetLastError();
     ctx->prop_net = nullptr;
     return fail(ctx, NGPRT_E_ALLOC, "proposal network");

@@ -44,7 +44,7 @@ __global__ void __launch_bounds__(256) count_final_kernel(const long long* __res
 
 int sum_counts(ngprt_ctx* ctx, int64_t n, const int32_t* counts, long long* host_total, hipStream_t st) {
   if (!ctx->count_ws) {
-    if (hipMalloc(&ctx->count_ws, (kCountBlocks + 1) * sizeof(long long)) != hipSuccess) {
+    if (dev_malloc((void**)&ctx->count_ws, (kCountBlocks + 1) * sizeof(long long)) != hipSuccess) {
       (void)hipGetLastError();
       ctx->count_ws = nullptr;
       return fail(ctx, NGPRT_E_ALLOC, "sample-count workspace");
