@@ -361,6 +361,21 @@ int ngprt_render_backward_fwd(ngprt_ctx* ctx, int64_t n_rays, const float* dev_o
                               const float* dev_c_d, const float* dev_feat, const float* dev_grad_rgb,
                               float* dev_grad_tables, float* dev_grad_atlas, float* dev_grad_mlp, void* stream);
 
+/* Deterministic table gradients, for gradient checks (off by default).
+ * The backward adds float contributions with atomics, in an order that
+ * varies from run to run, so a table gradient's last bits vary.  With on
+ * != 0, the hash-model backward entry points of this context instead write
+ * every corner contribution to a record of its own, sort the records by
+ * table entry (stably, so each entry keeps the order ray, sample, level,
+ * corner) and add each entry's records in that order: the same gradient
+ * bit for bit on every run.  Slower; allocates about 52 bytes per
+ * contribution (samples x L x 8 of them, at most NGPRT_DET_MAX_RECORDS per
+ * call, else NGPRT_E_SHAPE) and synchronises the stream.  The baked model's
+ * backward then returns NGPRT_E_UNSUPPORTED, as does
+ * ngprt_render_backward_noalloc (it cannot allocate the records). */
+#define NGPRT_DET_MAX_RECORDS 67108864
+int ngprt_set_deterministic_gradients(ngprt_ctx* ctx, int on);
+
 /* Test hook for failure handling (not for production use): after `after`
  * more successful device allocations by the library (any context, any
  * thread), the next one fails as if the device were out of memory, and the

@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(HERE, "libngprt.so")
 
 MAX_LEVELS = 16
 NOALLOC_MAX_RAYS = 524288        # NGPRT_NOALLOC_MAX_RAYS
+DET_MAX_RECORDS = 67108864       # NGPRT_DET_MAX_RECORDS
 NGPRT_OK = 0
 STATUS = {0: "NGPRT_OK", -1: "NGPRT_E_INVALID_ARG", -2: "NGPRT_E_SHAPE", -3: "NGPRT_E_DTYPE",
           -4: "NGPRT_E_NOT_LOADED", -5: "NGPRT_E_ALLOC", -6: "NGPRT_E_HIP", -7: "NGPRT_E_UNSUPPORTED"}
@@ -90,6 +91,7 @@ SIGNATURES = [
     ("ngprt_render_backward_baked", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P]),
     ("ngprt_render_backward_fwd", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     ("ngprt_test_fail_alloc", ctypes.c_int, [_I64]),
+    ("ngprt_set_deterministic_gradients", ctypes.c_int, [_P, ctypes.c_int]),
     ("ngprt_view_mlp_backward", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P]),
     ("ngprt_render_backward_features", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     ("ngprt_set_step", ctypes.c_int, [_P, ctypes.c_float]),

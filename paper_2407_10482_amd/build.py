@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libngprt.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "render.hip", "grid.hip", "tables.hip", "backward.hip", "proposal.hip", "probe.hip", "mlp_view.hip", "noalloc.hip", "tuning.hip"]
+SOURCES = ["api.hip", "render.hip", "grid.hip", "tables.hip", "backward.hip", "proposal.hip", "probe.hip", "mlp_view.hip", "noalloc.hip", "tuning.hip", "det.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

@@ -593,6 +593,12 @@ int ngprt_render_backward_features(ngprt_ctx* ctx, int64_t n_rays, const float* 
                          dev_feat, dev_grad_tables, baked ? dev_grad_atlas : nullptr, nullptr, (hipStream_t)stream);
 }
 
+int ngprt_set_deterministic_gradients(ngprt_ctx* ctx, int on) {
+  if (!ctx) return NGPRT_E_INVALID_ARG;
+  ctx->det_grad = on != 0;
+  return NGPRT_OK;
+}
+
 int ngprt_render_backward_fwd(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins, const float* dev_dirs,
                               const float* dev_c_d, const float* dev_feat, const float* dev_grad_rgb,
                               float* dev_grad_tables, float* dev_grad_atlas, float* dev_grad_mlp, void* stream) {

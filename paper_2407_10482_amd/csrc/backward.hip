@@ -371,7 +371,7 @@ __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, c
                                                        const float* __restrict__ ffv,
                                                        float* __restrict__ gtab, float* __restrict__ gatlas,
                                                        float* __restrict__ partial,
-                                                       const float* __restrict__ P) {
+                                                       const float* __restrict__ P, DetRecords det) {
   __shared__ float sA_all[4][64 * kPad];
   __shared__ float sB_all[4][64 * kPad];
   __shared__ float stage_all[4][64 * kStageRow];
@@ -641,7 +641,21 @@ __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, c
         gv[8] = wl[l] * (gw - gff);
       }
       float* gbase = gtab + (size_t(l) * T_entries) * 9;
-      if (S.N[l] >= NGPRT_BW_SORT_MIN_RES) {
+      if (det.off) {
+        // deterministic mode: every contribution to its own record
+        if (have) {
+          const int64_t base = ((det.off[ray] + (ns - 1)) * S.L + l) * 8;
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const int64_t rec = base + k;
+            if (rec >= det.n) break;
+            det.keys[rec] = uint32_t(l) * uint32_t(T_entries) + c.idx[k];
+            det.order[rec] = uint32_t(rec);
+#pragma unroll
+            for (int j = 0; j < 9; ++j) det.vals[rec * 9 + j] = c.w[k] * gv[j];
+          }
+        }
+      } else if (S.N[l] >= NGPRT_BW_SORT_MIN_RES) {
         // equal entries summed after a sort across the wave; the last lane
         // of each run issues the atomics
 #pragma unroll 1
@@ -703,6 +717,8 @@ size_t backward_workspace_bytes(int64_t n) {
   return (size_t(n_waves) + kSumGroups) * kMlpParams * sizeof(float);
 }
 
+static bool is_baked_model(const ngprt_ctx* ctx) { return ctx->desc.feature_model == NGPRT_MODEL_BAKED; }
+
 int launch_backward(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const float* grad_rgb,
                     const float* grad_dist, const float* ups, const float* fcd, const float* ffv,
                     float* gtab, float* gatlas, float* gmlp, hipStream_t st) {
@@ -718,13 +734,20 @@ int launch_backward(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, c
     }
     ctx->ws_bytes = need;
   }
+  if (ctx->det_grad) {
+    if (is_baked_model(ctx))
+      return fail(ctx, NGPRT_E_UNSUPPORTED, "deterministic gradients are built for the hash model");
+    return launch_backward_det(ctx, n, o, d, grad_rgb, grad_dist, ups, fcd, ffv, gtab, gmlp,
+                               reinterpret_cast<float*>(ctx->ws), st);
+  }
   return launch_backward_ws(ctx, n, o, d, grad_rgb, grad_dist, ups, fcd, ffv, gtab, gatlas, gmlp,
                             reinterpret_cast<float*>(ctx->ws), st);
 }
 
 int launch_backward_ws(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const float* grad_rgb,
                        const float* grad_dist, const float* ups, const float* fcd, const float* ffv,
-                       float* gtab, float* gatlas, float* gmlp, float* partial, hipStream_t st) {
+                       float* gtab, float* gatlas, float* gmlp, float* partial, hipStream_t st,
+                       const DetRecords& det) {
   SceneArgs S = scene_args(ctx);
   const int64_t blocks = (n + 255) / 256;
   if (blocks > 0x7FFFFFFF) return fail(ctx, NGPRT_E_SHAPE, "too many rays for one launch");
@@ -733,7 +756,7 @@ int launch_backward_ws(ngprt_ctx* ctx, int64_t n, const float* o, const float* d
   const bool box = ctx->desc.domain == DOM_BOX;
 #define NGPRT_BW(DOMV, LM, PY, MD)                                                                 \
   hipLaunchKernelGGL((backward_kernel<DOMV, LM, PY, MD>), g, dim3(256), 0, st, S, n, o, d, grad_rgb,   \
-                     grad_dist, ups, fcd, ffv, gtab, gatlas, partial, ctx->mlp)
+                     grad_dist, ups, fcd, ffv, gtab, gatlas, partial, ctx->mlp, det)
   if (S.model == NGPRT_MODEL_BAKED) {
     // L <= 2 fine levels: coarse rows of at most 12 channels, so the wave
     // sums in the coarse scatter carry 12 values instead of 16

@@ -114,6 +114,7 @@ struct ngprt_ctx {
   void* prop_tmp = nullptr;   // the same layout for ngprt_proposal_infer's caller-owned weights
   bool prop_loaded = false;
   void* count_ws = nullptr;   // step auto-tuning: per-block partial sums of sample counts + total
+  bool det_grad = false;      // table gradients by sorted segment sums instead of atomics
   void* prop_grad = nullptr;  // proposal gradient [7556] when the caller wants none
   int32_t* cidx = nullptr;    // baked model: block index grid [nb^3]
   float* catlas = nullptr;    // baked model: atlas [n_blocks][512][Cpad]
@@ -147,6 +148,16 @@ int launch_eval_points(ngprt_ctx* ctx, int64_t n, const float* pos, int32_t* idx
                        float* weights, hipStream_t s);
 int launch_march(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, int32_t cap,
                  int32_t* sk, int32_t* ns, int32_t* nr, int naive, hipStream_t s);
+// Deterministic table gradients: the backward writes every corner
+// contribution (key = level * T + entry, 9 values) to record
+// ((off[ray] + sample) * L + level) * 8 + corner instead of adding it.
+struct DetRecords {
+  const int64_t* off = nullptr;   // per ray: its first sample's index among all samples; NULL: off
+  uint32_t* keys = nullptr;
+  uint32_t* order = nullptr;      // record index (the sort's payload)
+  float* vals = nullptr;          // [records][9]
+  int64_t n = 0;                  // records; an index at or beyond is not written
+};
 // fcd, ffv: the forward's per-ray C_d [n][3] and F [n][4], or NULL (pass 1
 // recomputes them); given only without grad_dist
 int launch_backward(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const float* grad_rgb,
@@ -157,7 +168,13 @@ int launch_backward(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, c
 size_t backward_workspace_bytes(int64_t n);
 int launch_backward_ws(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const float* grad_rgb,
                        const float* grad_dist, const float* ups, const float* fcd, const float* ffv,
-                       float* gtab, float* gatlas, float* gmlp, float* workspace, hipStream_t s);
+                       float* gtab, float* gatlas, float* gmlp, float* workspace, hipStream_t s,
+                       const DetRecords& det = DetRecords());
+// the same with deterministic table gradients (hash model; allocates the
+// records, synchronises the stream)
+int launch_backward_det(ngprt_ctx* ctx, int64_t n, const float* o, const float* d, const float* grad_rgb,
+                        const float* grad_dist, const float* ups, const float* fcd, const float* ffv,
+                        float* gtab, float* gmlp, float* workspace, hipStream_t s);
 int init_static_scratch(ngprt_ctx* ctx);
 // Every device allocation of the library goes through these two, so that a
 // test can make one fail (ngprt_test_fail_alloc).

@@ -68,6 +68,8 @@ extern "C" int ngprt_render_backward_noalloc(ngprt_ctx* ctx, int64_t n_rays, con
     return fail(ctx, NGPRT_E_SHAPE,
                 "ngprt_render_backward_noalloc takes at most NGPRT_NOALLOC_MAX_RAYS (524288) rays per call");
   if (n_rays == 0) return NGPRT_OK;
+  if (ctx->det_grad)
+    return fail(ctx, NGPRT_E_UNSUPPORTED, "deterministic gradients allocate their records");
   int rc = check_backward_args(ctx, dev_origins, dev_dirs, dev_grad_rgb, dev_grad_tables, dev_grad_mlp);
   if (rc) return rc;
   if (backward_workspace_bytes(n_rays) > size_t(NGPRT_NOALLOC_SCRATCH_BYTES))

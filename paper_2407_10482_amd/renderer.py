@@ -383,6 +383,12 @@ def _renderer_backward_features(self: Renderer, origins, dirs, grad_cf, grad_tab
                                                   _stream()), self.ctx)
 
 
+def _renderer_set_deterministic(self: Renderer, on: bool = True):
+    """Table gradients by sorted, fixed-order sums instead of atomics (the
+    same bits on every run; slower, for gradient checks; hash model)."""
+    check(self.lib.ngprt_set_deterministic_gradients(self.ctx, 1 if on else 0), self.ctx)
+
+
 def _renderer_set_step(self: Renderer, step: float):
     self.load_gen += 1
     check(self.lib.ngprt_set_step(self.ctx, float(step)), self.ctx)
@@ -395,6 +401,7 @@ Renderer.backward_baked = _renderer_backward_baked
 Renderer.view_mlp_backward = _renderer_view_mlp_backward
 Renderer.backward_features = _renderer_backward_features
 Renderer.backward_fwd = _renderer_backward_fwd
+Renderer.set_deterministic = _renderer_set_deterministic
 Renderer.set_step = _renderer_set_step
 
 
