@@ -57,6 +57,9 @@ def parse():
                    default="separate_v",
                    help="baked model: fusion of the fine levels (Table 3's variants; separate_v is the "
                         "paper's sigmoid-gated separate attention)")
+    p.add_argument("--scene", choices=["hd", "hd_regime"], default="hd",
+                   help="hash model: hd (the headline scene: 15.2 samples, 34.8 grid reads per ray) or "
+                        "hd_regime (calibrated to the paper's Table 4 regime: 17.3 samples, 42.6 reads)")
     p.add_argument("--occ", choices=["single", "pyramid"], default="single",
                    help="single: one 256^3 occupancy grid + distance grid (the headline); pyramid: "
                         "the paper's 512^3..32^3 occupancy pyramid + 256^3 distance grid")
@@ -480,7 +483,12 @@ def main():
             cfg.mlp_dims = (23, 64, 64, 3)
         sc = make_baked_scene(cfg)
     else:
-        cfg = synth.hd_pyramid(table_dtype=dtype) if pyr else synth.hd(table_dtype=dtype)
+        if args.scene == "hd_regime":
+            if pyr:
+                raise SystemExit("--scene hd_regime marches the single distance grid")
+            cfg = synth.hd_regime(table_dtype=dtype)
+        else:
+            cfg = synth.hd_pyramid(table_dtype=dtype) if pyr else synth.hd(table_dtype=dtype)
         if args.mlp == "view":
             cfg.mlp_dims = (23, 64, 64, 3)
         sc = synth.make_scene(cfg)
@@ -551,7 +559,8 @@ def main():
     gather = n_samples * per_sample
     alg_bytes = gather + 2 * n_reads + n * (24 + 12)
     sec = ms / 1e3
-    ctr = None if (baked or pyr or args.mlp == "view") else committed_counters(DTYPE_NAME[dtype])
+    ctr = (None if (baked or pyr or args.mlp == "view" or args.scene != "hd")
+           else committed_counters(DTYPE_NAME[dtype]))
     levels = {
         # what the method asks for: every corner row of every level of every
         # sample; most of it is served by the L1 and L2 caches, so this is no
@@ -606,6 +615,11 @@ def main():
                     f"{cfg.resolutions[0]}..{cfg.resolutions[-1]}, 2^22 entries, {DTYPE_NAME[dtype]} fine "
                     f"tables, {AGG_NAME[args.agg]}, contracted scene of 200 blobs, 256^3 "
                     "occupancy + distance grid, <=1024 samples/ray, T<1e-4")
+    elif args.scene == "hd_regime":
+        workload = ("hd_regime: 8 views x 1920x1080 rays, 16 hash levels 16..4096, 2^19 entries, "
+                    f"{DTYPE_NAME[dtype]} tables, contracted scene of 400 blobs (sigma 0.02-0.08, "
+                    "calibrated to the paper's Table 4 regime), 256^3 occupancy + distance grid, "
+                    "<=1024 samples/ray, T<1e-4")
     else:
         workload = ("hd: 8 views x 1920x1080 rays, 16 hash levels 16..4096, 2^19 entries, "
                     f"{DTYPE_NAME[dtype]} tables, contracted scene of 200 blobs, 256^3 "
