@@ -2,7 +2,10 @@
 // model but states no gradient code).  FP32 tables only.
 //
 // Forward state is recomputed per ray instead of stored per sample:
-//  pass 1  re-march the ray: composited C_d and F (Eq. 2, Eq. 5); then, per
+//  pass 1  re-march the ray: composited C_d and F (Eq. 2, Eq. 5), or take
+//          the forward's per-ray C_d and F when the caller hands them over
+//          (the same float32 values; not with the regulariser, whose sums
+//          this pass also forms); then, per
 //          lane, the deferred MLP forward and backward give dL/dC_d, dL/dF,
 //          and per-ray outer products whose sum over the wave's 64 rays is
 //          taken on v_mfma_f32_16x16x4_f32 (K = rays) and written as one
@@ -27,7 +30,8 @@
 //          lanes of one instruction (scatter_runs) then 92 -> 20 ms and
 //          14 -> 7 ms.
 //          The baked model scatters into its fine levels and coarse atlas
-//          rows instead (baked_scatter).
+//          rows instead (baked_scatter).  In the deterministic mode each
+//          contribution goes to a record of its own instead (det.hip).
 // The per-wave MLP partials are then added in a fixed order (reduce.h).
 #include <hip/hip_runtime.h>
 
