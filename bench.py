@@ -474,6 +474,8 @@ def main():
     baked = args.model == "baked"
     t0 = time.time()
     pyr = args.occ == "pyramid"
+    if baked and args.scene != "hd":
+        raise SystemExit("--scene applies to the hash model")
     if baked:
         from synth.baked import make_baked_scene
         cfg = synth.with_aggregation(synth.baked_hd(table_dtype=dtype, n_fine=args.fine_levels), args.agg)
