@@ -120,3 +120,30 @@ def test_unrescaled_running_sums_are_caught():
     """A new running maximum that does not rescale the sums taken so far."""
     rd = _mutated("oracle.render", "esum = fma32(esum, scale, e)", "esum = esum + e")
     _fails(pins.test_softmax_mirror_with_extreme_logits, "ramp", fused32=rd.fused32)
+
+
+def test_double_rounding_fma32_is_caught():
+    """fma32 computed as the float64 sum rounded to float32 (two roundings)."""
+    ex = _mutated("oracle.exact32", "    return np.asarray(s_odd).astype(F32)\n",
+                  "    return np.asarray(s).astype(F32)\n")
+    import oracle.exact32 as real
+    real_fma = real.fma32
+    real.fma32 = ex.fma32
+    try:
+        _fails(pins.test_fma32_is_the_single_rounding_of_the_exact_value)
+    finally:
+        real.fma32 = real_fma
+
+
+def test_contraction_without_normalising_is_caught():
+    """The float64 sample positions contracted as (2 - 1/r) x instead of
+    (2 - 1/r) x / r."""
+    rd = _mutated("oracle.render", "x[outer] = ((2.0 - 1.0 / r[outer]) / r[outer])[:, None] * x[outer]",
+                  "x[outer] = (2.0 - 1.0 / r[outer])[:, None] * x[outer]")
+    import oracle.render as real
+    real_fn = real.sample_coords64
+    real.sample_coords64 = rd.sample_coords64
+    try:
+        _fails(pins.test_sample_coords64_closed_forms)
+    finally:
+        real.sample_coords64 = real_fn
