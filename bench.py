@@ -407,10 +407,10 @@ VALU_PEAK_G = 256 * 4 * 2.4 / 4     # wave64 VALU instructions per ns: 256 CUs x
                                    # one wave64 instruction per 4 cycles on a 16-lane SIMD
 
 
-def committed_counters(dtype_name: str):
+def committed_counters(dtype_name: str, scene: str = "hd"):
     """Per-launch hardware counters of the render kernel from the committed
     summary, or None when it is missing or was taken on other kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"render_kernel_hd_{dtype_name}_counters.md")
+    path = os.path.join(ROOT, "profiles", f"render_kernel_{scene}_{dtype_name}_counters.md")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -561,8 +561,7 @@ def main():
     gather = n_samples * per_sample
     alg_bytes = gather + 2 * n_reads + n * (24 + 12)
     sec = ms / 1e3
-    ctr = (None if (baked or pyr or args.mlp == "view" or args.scene != "hd")
-           else committed_counters(DTYPE_NAME[dtype]))
+    ctr = None if (baked or pyr or args.mlp == "view") else committed_counters(DTYPE_NAME[dtype], args.scene)
     levels = {
         # what the method asks for: every corner row of every level of every
         # sample; most of it is served by the L1 and L2 caches, so this is no
