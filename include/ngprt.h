@@ -328,9 +328,10 @@ int ngprt_debug_march(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins,
  * dev_grad_rgb: float32 [n][3] dL/drgb.  Accumulates (+=) dL/dtables into
  * dev_grad_tables, float32 [L][T][9] in the layout ngprt_load_tables takes,
  * and dL/dmlp into dev_grad_mlp, float32 [451]; the caller zeroes them.
- * The forward is recomputed per ray (two re-marches, no per-sample state);
+ * The forward is recomputed per ray (two re-marches, no per-sample state;
+ * ngprt_render_backward_fwd takes the forward's C_d and F and needs one);
  * table gradients are summed with float atomics, so their low bits depend
- * on execution order.  Needs float32 tables (NGPRT_E_DTYPE otherwise) and
+ * on execution order (ngprt_set_deterministic_gradients removes that).  Needs float32 tables (NGPRT_E_DTYPE otherwise) and
  * the hash feature model (NGPRT_E_UNSUPPORTED for NGPRT_MODEL_BAKED).  May
  * grow a library-owned workspace (stream-ordered allocation). */
 int ngprt_render_backward(ngprt_ctx* ctx, int64_t n_rays, const float* dev_origins,

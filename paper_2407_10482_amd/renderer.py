@@ -466,8 +466,9 @@ class RenderFunction(torch.autograd.Function):
     """rgb = render(tables, mlp; rays) with the library's hand-written backward.
 
     forward loads `tables` (float32 [L, T, 9]) and `mlp` (float32 [451]) into
-    the renderer and renders; backward recomputes the forward per ray inside
-    the library and returns dL/dtables and dL/dmlp."""
+    the renderer and renders; backward re-marches each ray inside the
+    library (taking the forward's C_d and F when no regulariser is on) and
+    returns dL/dtables and dL/dmlp."""
 
     @staticmethod
     def forward(ctx, tables, mlp, origins, dirs, renderer, with_dist):
