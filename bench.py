@@ -68,9 +68,10 @@ def parse():
                         "view-dependent MLP_psi 23-64-64-3 of (C_d, F, SH(d))")
     p.add_argument("--no-dist", action="store_true",
                    help="pyramid only: march without the distance grid (the ablation of Table 4)")
-    p.add_argument("--mode", choices=["render", "train", "proposal"], default="render",
+    p.add_argument("--mode", choices=["render", "train", "proposal", "cache"], default="render",
                    help="render: the headline; train: forward+backward+Adam steps; "
-                        "proposal: learned sample-interval proposal vs plain marching")
+                        "proposal: learned sample-interval proposal vs plain marching; "
+                        "cache: the random-gather probe over table sizes")
     p.add_argument("--train-size", choices=["tiny", "train_large"], default="tiny")
     p.add_argument("--prop-epochs", type=int, default=12)
     p.add_argument("--regime-steps", type=int, default=20,
@@ -476,6 +477,37 @@ def committed_counters(dtype_name: str, scene: str = "hd"):
     return out
 
 
+def bench_cache(args) -> dict:
+    """The random-gather probe over table sizes: 16 levels of 2^13..2^21
+    entries in F32, BF16 and FP8 rows, uniform random entries per level (no
+    reuse but what the caches hold).  Where the whole table outgrows the
+    256 MB Infinity Cache the achieved rate drops; this locates that knee
+    for the gather pattern of the render."""
+    import torch
+    import synth
+    from paper_2407_10482_amd.renderer import Renderer
+    torch.cuda.set_device(0)
+    curve = []
+    for dt in (0, 1, 2):
+        for log2t in range(13, 22):
+            cfg = synth.hd(table_dtype=dt)
+            cfg.log2_table = log2t
+            r = Renderer.from_config(cfg, dt)
+            T = 1 << log2t
+            g = torch.Generator(device="cuda").manual_seed(log2t)
+            r.load_tables(torch.randn((cfg.n_levels, T, 9), generator=g, device="cuda") * 0.5)
+            gbs = gather_probe(r, args.probe_points, 5, False)
+            curve.append({"dtype": DTYPE_NAME[dt], "entries_per_level": T,
+                          "table_mb": round(cfg.n_levels * T * BYTES_PER_ENTRY[dt] / 1e6, 1),
+                          "requested_gbs": round(gbs, 1),
+                          "g_rows_per_s": round(gbs / BYTES_PER_ENTRY[dt], 2)})
+            print(json.dumps(curve[-1]), file=sys.stderr, flush=True)
+            del r
+            torch.cuda.empty_cache()
+    return {"metric": "random-gather probe over table sizes (G corner rows/s)", "points": args.probe_points,
+            "levels": 16, "unit": "G rows/s", "higher_is_better": True, "curve": curve}
+
+
 def gather_probe(r, n_points: int, reps: int, pairs: bool) -> float:
     """Requested-gather GB/s of the random-gather probe (mean over reps)."""
     import torch
@@ -502,6 +534,9 @@ def main():
         return
     if args.mode == "proposal":
         print(json.dumps(bench_proposal(args)), flush=True)
+        return
+    if args.mode == "cache":
+        print(json.dumps(bench_cache(args)), flush=True)
         return
     import torch
 
