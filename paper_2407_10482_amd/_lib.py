@@ -175,6 +175,12 @@ def make_desc(resolutions, log2_table_size, table_dtype, domain, roi_half, occ_r
     return d
 
 
+def mlp_param_count(dims) -> int:
+    """Parameters of an in -> h -> h -> out MLP with biases (weights, then biases, layer by layer)."""
+    i, h, h2, o = dims
+    return h * i + h + h2 * h + h2 + o * h2 + o
+
+
 def coarse_channels(n_levels: int, aggregation: int = AGG_SEPARATE_V) -> int:
     """Channels per coarse vertex of the baked model under an aggregation."""
     return 8 + {AGG_SEPARATE_V: 2 * n_levels, AGG_SHARED_V: n_levels}.get(aggregation, 0)

@@ -8,7 +8,7 @@ from typing import Dict, Optional, Sequence
 import numpy as np
 import torch
 
-from . import _lib
+from . import _lib, assets
 from ._lib import (BF16, F32, FP8E4M3, MODEL_BAKED, MODEL_HASH, ROI_BOX, ROI_CONTRACT, NgprtOutputs,
                    check, load_library)
 
@@ -54,8 +54,14 @@ class Renderer:
         self.aggregation = int(aggregation)
         self.mlp_dims = tuple(mlp_dims)
         self.view_mlp = self.mlp_dims[1] == 64
-        i, h, _, o = self.mlp_dims
-        self.n_mlp = h * i + h + h * h + h + o * h + o
+        self.n_mlp = _lib.mlp_param_count(self.mlp_dims)
+        # the constructor's arguments: the descriptor a scene's manifest records
+        self.descriptor = assets.normalise_descriptor(dict(
+            resolutions=self.resolutions, log2_table_size=log2_table_size, table_dtype=table_dtype,
+            domain=domain, roi_half=roi_half, occ_res=occ_res, step=step, max_samples=max_samples,
+            t_threshold=t_threshold, feature_model=feature_model, coarse_res=coarse_res,
+            occ_levels=occ_levels, occ_fine_res=occ_fine_res, use_distance=use_distance,
+            mlp_dims=self.mlp_dims, aggregation=aggregation, gate_params=gate_params))
         self.desc = _lib.make_desc(resolutions, log2_table_size, table_dtype, domain, roi_half,
                                    occ_res, step, max_samples, t_threshold,
                                    feature_model=feature_model, coarse_res=coarse_res,
@@ -137,6 +143,46 @@ class Renderer:
         self.load_tables(tables)
         self.load_occupancy(occ, dist)
         self.load_mlp(mlp)
+
+    # ------------------------------------------------------------ scene files
+    @classmethod
+    def from_assets(cls, path: str) -> "Renderer":
+        """A renderer built from a scene directory's descriptor with all of
+        its assets loaded (every file verified against the manifest first)."""
+        desc, arrays = assets.read_scene(path)
+        kw = dict(desc)
+        kw["mlp_dims"] = tuple(kw["mlp_dims"])
+        kw["gate_params"] = tuple(kw["gate_params"])
+        r = cls(**kw)
+        r.load_assets(arrays)
+        return r
+
+    def load_assets(self, arrays: Dict[str, np.ndarray]):
+        """Load verified host arrays (the names of ``assets.DTYPES``) into this
+        context: tables, occupancy (pyramid or single grid), MLP, coarse
+        grid and proposal network, each through its C-ABI loader."""
+        assets.check_assets(self.descriptor, arrays)
+        dev = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in arrays.items()
+               if k != "coarse_default"}
+        self.load_tables(dev["tables"])
+        if "occ_fine" in dev:
+            self.load_occupancy_pyramid(dev["occ_fine"])
+        else:
+            self.load_occupancy(dev["occ"], dev.get("dist"))
+        self.load_mlp(dev["mlp"])
+        if "coarse_index" in dev:
+            self.load_coarse(dev["coarse_index"], dev["coarse_atlas"], arrays["coarse_default"].tolist())
+        if "proposal" in dev:
+            self.load_proposal(dev["proposal"])
+        torch.cuda.current_stream().synchronize()
+
+    def save_assets(self, path: str, **arrays) -> Dict:
+        """Write a scene directory for this renderer's descriptor from the
+        caller's arrays (numpy or torch, already in the asset dtypes; device
+        tensors are copied to the host).  Returns the manifest."""
+        host = {k: (v.detach().cpu().numpy() if isinstance(v, torch.Tensor) else np.asarray(v))
+                for k, v in arrays.items()}
+        return assets.save_scene(path, self.descriptor, host)
 
     # ---------------------------------------------------------------- export
     def export_tables(self):
