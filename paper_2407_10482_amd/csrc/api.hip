@@ -59,6 +59,7 @@ SceneArgs scene_args(const ngprt_ctx* ctx) {
     S.pyr[j] = j < S.pyr_n ? ctx->pyr[j] : nullptr;
     if (j < S.pyr_n && S.pyrR[j] == d.occ_res) S.pyr_jg = j;
   }
+  S.pwide = S.pyr_n > 0 && S.pyr_jg == 1 ? ctx->pwide : nullptr;
   S.view_mlp = d.mlp_hidden == 64 ? 1 : 0;
   S.model = d.feature_model;
   if (d.feature_model == NGPRT_MODEL_BAKED) {
@@ -217,6 +218,7 @@ void ngprt_destroy(ngprt_ctx* ctx) {
   if (ctx->catlas) (void)hipFree(ctx->catlas);
   for (int j = 0; j < 5; ++j)
     if (ctx->pyr[j]) (void)hipFree(ctx->pyr[j]);
+  if (ctx->pwide) (void)hipFree(ctx->pwide);
   if (switched) (void)hipSetDevice(cur);
   delete ctx;
 }

@@ -213,11 +213,15 @@ __global__ void pyr_unpack_kernel(const uint32_t* __restrict__ bits, uint8_t* __
 // j >= jg whose cell holding the voxel is empty, as 1 + j - jg in bits 9-11
 // of the voxel's word (0: occupied at every level >= jg).  Level j's cell is
 // the voxel's coordinates shifted right by j - jg (the resolutions halve).
+// With jg == 1 the finest level holds exactly the voxel's 2x2x2 children:
+// wide (when given) gets the word in bits 0-15 and child (dx, dy, dz)'s
+// occupancy in bit 16 + dx + 2 dy + 4 dz.
 struct PyrLevels {
   const uint32_t* bits[kMaxPyr];
 };
 
-__global__ void pyr_code_kernel(uint16_t* __restrict__ grid, int R, int jg, int nl, PyrLevels P) {
+__global__ void pyr_code_kernel(uint16_t* __restrict__ grid, uint32_t* __restrict__ wide, int R, int jg,
+                                int nl, PyrLevels P) {
   const int64_t n = int64_t(R) * R * R;
   const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (v >= n) return;
@@ -232,7 +236,18 @@ __global__ void pyr_code_kernel(uint16_t* __restrict__ grid, int R, int jg, int 
       break;
     }
   }
-  grid[v] = uint16_t((grid[v] & 0x1FFu) | (code << 9));
+  const uint16_t word = uint16_t((grid[v] & 0x1FFu) | (code << 9));
+  grid[v] = word;
+  if (wide) {
+    const int Rf = 2 * R, wpr = Rf >> 5;
+    uint32_t kids = 0;
+    for (int c = 0; c < 8; ++c) {
+      const int fx = 2 * x + (c & 1), fy = 2 * y + ((c >> 1) & 1), fz = 2 * z + (c >> 2);
+      const uint32_t w = P.bits[0][(size_t(fz) * Rf + fy) * size_t(wpr) + size_t(fx >> 5)];
+      kids |= ((w >> (fx & 31)) & 1u) << c;
+    }
+    wide[v] = uint32_t(word) | (kids << 16);
+  }
 }
 
 int launch_build_pyramid(ngprt_ctx* ctx, const uint8_t* occ_fine, hipStream_t st) {
@@ -245,6 +260,13 @@ int launch_build_pyramid(ngprt_ctx* ctx, const uint8_t* occ_fine, hipStream_t st
         (void)hipGetLastError();
         return fail(ctx, NGPRT_E_ALLOC, "occupancy pyramid allocation failed");
       }
+    }
+  }
+  const int64_t nR = int64_t(d.occ_res) * d.occ_res * d.occ_res;
+  if (int64_t(d.occ_fine_res) == 2 * int64_t(d.occ_res) && !ctx->pwide) {
+    if (dev_malloc((void**)&ctx->pwide, size_t(nR) * sizeof(uint32_t)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(ctx, NGPRT_E_ALLOC, "occupancy pyramid allocation failed");
     }
   }
   const int64_t R0 = d.occ_fine_res;
@@ -277,7 +299,9 @@ int launch_build_pyramid(ngprt_ctx* ctx, const uint8_t* occ_fine, hipStream_t st
   if (rc) return rc;
   PyrLevels P = {};
   for (int j = 0; j < nl; ++j) P.bits[j] = ctx->pyr[j];
-  hipLaunchKernelGGL(pyr_code_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, ctx->grid, d.occ_res, jg, nl, P);
+  uint32_t* wide = jg == 1 ? ctx->pwide : nullptr;
+  hipLaunchKernelGGL(pyr_code_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, ctx->grid, wide, d.occ_res, jg,
+                     nl, P);
   return check_launch(ctx, "pyr_code_kernel");
 }
 

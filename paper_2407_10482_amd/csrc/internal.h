@@ -77,6 +77,11 @@ struct SceneArgs {
   int view_mlp;                   // the deferred MLP is the view-dependent one (a separate pass)
   int pyrR[kMaxPyr];
   const uint32_t* pyr[kMaxPyr];   // [R^3 / 32] words, x fastest, bit x & 31
+  // pyramid whose distance grid is one level above the finest (pyr_jg == 1),
+  // else NULL: per voxel of the distance grid the word of `grid` in bits
+  // 0-15 and, in bit 16 + (x & 1) + 2 (y & 1) + 4 (z & 1), whether the finest
+  // level's child (x, y, z) is occupied, so one read decides every level
+  const uint32_t* pwide;
 };
 
 struct RayOut {
@@ -122,6 +127,7 @@ struct ngprt_ctx {
   float cdef[16] = {};
   bool coarse_loaded = false;
   uint32_t* pyr[5] = {};      // occupancy pyramid bit grids
+  uint32_t* pwide = nullptr;  // [R^3] distance-grid words with the finest level's child bits
   bool pyr_loaded = false;
   bool tables_loaded = false;
   bool occ_loaded = false;

@@ -179,6 +179,21 @@ __device__ __forceinline__ bool march_next(const SceneArgs& S, MarchState& m, bo
       uint32_t word = 0;
       if (naive) {
         lev = pyr_empty(S, 0, u) ? 0 : -1;
+      } else if (S.pwide) {
+        // the finest level is the one below the distance grid: the word also
+        // holds the voxel's 8 children there (level-0 cell = the voxel's
+        // coordinates doubled plus the child offsets, exactly, since u * 2R
+        // and u * R differ by a power of two)
+        word = S.pwide[v];
+        const uint32_t code = (word >> 9) & 7u;
+        if (code) {
+          lev = int(code);
+        } else {
+          int q0[3];
+          pyr_cell(u, S.pyrR[0], q0);
+          const uint32_t c = uint32_t(q0[0] & 1) | (uint32_t(q0[1] & 1) << 1) | (uint32_t(q0[2] & 1) << 2);
+          lev = ((word >> (16 + c)) & 1u) ? -1 : 0;
+        }
       } else {
         word = S.grid[v];
         const uint32_t code = (word >> 9) & 7u;

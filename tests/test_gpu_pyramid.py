@@ -64,13 +64,15 @@ def test_pyramid_render_parity_tiny(use_dist):
     assert np.abs(_np(out["rgb"]).astype(np.float64) - ref.rgb).max() < COLOUR_TOL
 
 
-@pytest.mark.parametrize("use_dist", [True, False])
-def test_pyramid_march_contracted_random_grid(use_dist):
+@pytest.mark.parametrize("use_dist,jg", [(True, 1), (False, 1), (True, 2), (False, 2)])
+def test_pyramid_march_contracted_random_grid(use_dist, jg):
     """Contracted domain, a random 128^3 .. 32^3 pyramid with the distance
-    grid at 64^3."""
+    grid at 64^3 (one level above the finest: one word per marching point
+    holds the finest level's bits) or at 32^3 (the finer levels read
+    one by one)."""
     import torch
     from paper_2407_10482_amd.renderer import Renderer
-    print(f"[pyramid march contracted G={use_dist}]", flush=True)
+    print(f"[pyramid march contracted G={use_dist} jg={jg}]", flush=True)
     rng = np.random.default_rng(7)
     fine = np.zeros((128, 128, 128), np.uint8)
     for _ in range(15):
@@ -80,7 +82,7 @@ def test_pyramid_march_contracted_random_grid(use_dist):
     sc, _ = scene_and_dist("tiny")
     step = float(synth.CONTRACT_STEP)
     pyr = pyramid.build_pyramid(fine, 3)
-    occ = pyr[1]
+    occ = pyr[jg]
     inp = OracleInputs(tables=sc.tables, occ=occ, dist=distance_grid_edt(occ), mlp=sc.mlp,
                        resolutions=sc.cfg.resolutions, domain=CONTRACT, roi_half=2.0, step=step,
                        max_samples=1024, t_threshold=1e-4, pyramid=pyr, use_dist=use_dist)
@@ -88,7 +90,7 @@ def test_pyramid_march_contracted_random_grid(use_dist):
     o = rng.uniform(-3, 3, size=(n, 3)).astype(F32)
     dd = rng.uniform(-1.5, 1.5, size=(n, 3)) - o
     d = (dd / np.linalg.norm(dd, axis=1, keepdims=True)).astype(F32)
-    r = Renderer(sc.cfg.resolutions, sc.cfg.log2_table, 0, CONTRACT, 2.0, 64, step, 1024, 1e-4,
+    r = Renderer(sc.cfg.resolutions, sc.cfg.log2_table, 0, CONTRACT, 2.0, 128 >> jg, step, 1024, 1e-4,
                  occ_levels=3, occ_fine_res=128, use_distance=use_dist)
     r.load_tables(torch.from_numpy(sc.tables).cuda())
     r.load_occupancy_pyramid(torch.from_numpy(fine).cuda())
