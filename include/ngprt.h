@@ -223,7 +223,13 @@ int ngprt_load_occupancy(ngprt_ctx* ctx, const uint8_t* dev_occ, const uint8_t* 
  * if that skips further.  The sampled lattice points are those of an
  * exhaustive march over the finest level.  Needs occ_levels > 0
  * (NGPRT_E_UNSUPPORTED otherwise); ngprt_load_occupancy then returns
- * NGPRT_E_UNSUPPORTED. */
+ * NGPRT_E_UNSUPPORTED.  Device memory held: the levels (F^3 / 8 bytes for
+ * the finest, an eighth of that for each next), the G grid (2 R^3 bytes) and,
+ * when occ_res = F / 2, a 4 R^3-byte copy of G's words that also carries each
+ * voxel's 8 finest-level children, so the march decides a lattice point with
+ * one read; allocated by the first call, reused by later ones
+ * (NGPRT_E_ALLOC if an allocation fails; the context then has no occupancy
+ * until a load succeeds). */
 int ngprt_load_occupancy_pyramid(ngprt_ctx* ctx, const uint8_t* dev_occ_fine, void* stream);
 
 /* Copy the distance grid in use to dev_dist (uint8 [R^3]). */
