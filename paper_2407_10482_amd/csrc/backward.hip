@@ -185,6 +185,20 @@ __device__ __forceinline__ bf32x4 wave_outer_sum(const float* sA, const float* s
   return acc;
 }
 
+// Corner k of a cell for a loop counter k that is the same on every lane:
+// picked from registers by selects, where indexing the arrays with k would
+// put them in per-lane scratch memory (a store per level and a load per
+// corner through the vector memory pipeline).
+__device__ __forceinline__ void corner_pick(const Corners& c, int k, uint32_t& idx, float& w) {
+  idx = c.idx[0];
+  w = c.w[0];
+#pragma unroll
+  for (int j = 1; j < 8; ++j) {
+    idx = k == j ? c.idx[j] : idx;
+    w = k == j ? c.w[j] : w;
+  }
+}
+
 // Adjoint of the baked feature construction at one sample (Sec. 4.2 Eq. 7-8):
 // with f_0 = f~_0 + sum_l g(omega_l) s_l and f_j = f~_j + sum_l g(beta_l) v_lj
 // (j >= 1), dL/df (gf) gives
@@ -285,10 +299,12 @@ __device__ __forceinline__ void baked_scatter(const SceneArgs& S, const float u[
     if (S.N[l] >= NGPRT_BW_SORT_MIN_RES) {
 #pragma unroll 1
       for (int k = 0; k < 8; ++k) {
-        uint32_t key = c.idx[k];
+        uint32_t key;
+        float wk;
+        corner_pick(c, k, key, wk);
         float x[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) x[j] = c.w[k] * gv[j];
+        for (int j = 0; j < 8; ++j) x[j] = wk * gv[j];
         const bool tail = wave_sort_merge<8>(key, have, x, lane);
         scatter_runs<8>(gbase, tail, key, x, lane, stage);
       }
@@ -664,10 +680,12 @@ __global__ void __launch_bounds__(256) backward_kernel(SceneArgs S, int64_t n, c
         // of each run issues the atomics
 #pragma unroll 1
         for (int k = 0; k < 8; ++k) {
-          uint32_t key = c.idx[k];
+          uint32_t key;
+          float wk;
+          corner_pick(c, k, key, wk);
           float x[9];
 #pragma unroll
-          for (int j = 0; j < 9; ++j) x[j] = c.w[k] * gv[j];
+          for (int j = 0; j < 9; ++j) x[j] = wk * gv[j];
           const bool tail = wave_sort_merge<9>(key, have, x, lane);
           scatter_runs<9>(gbase, tail, key, x, lane, stage_all[wave]);
         }
