@@ -119,6 +119,7 @@ struct ngprt_ctx {
   void* prop_tmp = nullptr;   // the same layout for ngprt_proposal_infer's caller-owned weights
   bool prop_loaded = false;
   void* count_ws = nullptr;   // step auto-tuning: per-block partial sums of sample counts + total
+  int vmlp_resident = 0;      // view_mlp_kernel workgroups resident together (0: not yet queried)
   bool det_grad = false;      // table gradients by sorted segment sums instead of atomics
   void* prop_grad = nullptr;  // proposal gradient [7556] when the caller wants none
   int32_t* cidx = nullptr;    // baked model: block index grid [nb^3]

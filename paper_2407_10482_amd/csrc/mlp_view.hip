@@ -5,10 +5,13 @@
 //
 // A separate pass after the march: the render kernel leaves C_d and F in the
 // caller's output buffers, and this kernel runs the MLP over all rays.  One
-// workgroup = 4 waves = 256 rays; the weights, pre-arranged at load time in
-// the order the MFMA sequence consumes them (one 64-float record per
-// instruction, lane l reading element l), are staged once per workgroup in
-// LDS.  Per wave the 64 rays are 4 column blocks of 16; every layer is a
+// workgroup = 4 waves; the weights, pre-arranged at load time in the order
+// the MFMA sequence consumes them (one 64-float record per instruction, lane
+// l reading element l), are staged once per workgroup in LDS, and the grid
+// holds only as many workgroups as stay resident together, each taking
+// groups of 256 rays in turn (so the 35 KB of weights are read once per
+// resident workgroup, not once per 256 rays).  Per wave the 64 rays are 4
+// column blocks of 16; every layer is a
 // chain of v_mfma_f32_16x16x4f32 with the hidden units as rows and the rays
 // as columns; the hidden index handed to the next layer is permuted (k-slot
 // s of chunk (m, r) = unit 16 m + 4 s + r) so each layer consumes the
@@ -93,9 +96,17 @@ __global__ void __launch_bounds__(256) view_mlp_kernel(int64_t n, const float* _
   __shared__ float xin_all[4][24 * 64];
   for (int t = threadIdx.x; t < kViewRecFloats; t += 256) W[t] = rec[t];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t ray_base = (int64_t(blockIdx.x) * 4 + wave) * 64;
-  const int64_t ray = ray_base + lane;
   float* xin = xin_all[wave];
+  const int i = lane & 15, s = lane >> 4;
+  const float* R1 = W;
+  const float* R2 = W + kL1Rec * 64;
+  const float* R3 = R2 + kL2Rec * 64;
+  const float* B = R3 + kL3Rec * 64;
+  const int64_t groups = (n + 255) / 256;
+  // the group loop is uniform across the workgroup, so its barriers are too
+  for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {
+  const int64_t ray_base = (g * 4 + wave) * 64;
+  const int64_t ray = ray_base + lane;
   float x[24];
 #pragma unroll
   for (int j = 0; j < 24; ++j) x[j] = 0.0f;
@@ -108,14 +119,12 @@ __global__ void __launch_bounds__(256) view_mlp_kernel(int64_t n, const float* _
     const float nn = sqrtf((d0 * d0 + d1 * d1) + d2 * d2);
     if (nn > 0.0f && isfinite(nn)) sh16(d0 / nn, d1 / nn, d2 / nn, x + 7);
   }
+  // every wave has read the previous group's inputs (and, the first time,
+  // the weights are in place) before the slabs are written again
+  __syncthreads();
 #pragma unroll
   for (int j = 0; j < 24; ++j) xin[j * 64 + lane] = x[j];
   __syncthreads();
-  const int i = lane & 15, s = lane >> 4;
-  const float* R1 = W;
-  const float* R2 = W + kL1Rec * 64;
-  const float* R3 = R2 + kL2Rec * 64;
-  const float* B = R3 + kL3Rec * 64;
   for (int rb = 0; rb < 4; ++rb) {
     const int col = rb * 16 + i;
     float h1[4][4], h2[4][4];
@@ -157,6 +166,7 @@ __global__ void __launch_bounds__(256) view_mlp_kernel(int64_t n, const float* _
         }
       }
     }
+  }
   }
 }
 
@@ -362,8 +372,20 @@ int launch_view_mlp_arrange(ngprt_ctx* ctx, const float* params, hipStream_t st)
 
 int launch_view_mlp(ngprt_ctx* ctx, int64_t n, const float* d, const float* c_d, const float* feat,
                     float* rgb, hipStream_t st) {
-  const int64_t blocks = (n + 255) / 256;
-  if (blocks > 0x7FFFFFFF) return fail(ctx, NGPRT_E_SHAPE, "too many rays for one launch");
+  if (n <= 0) return NGPRT_OK;
+  if (ctx->vmlp_resident <= 0) {
+    // workgroups of view_mlp_kernel that stay resident together on the device
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, view_mlp_kernel, 256, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess ||
+        per_cu <= 0 || cus <= 0) {
+      (void)hipGetLastError();
+      return fail(ctx, NGPRT_E_HIP, "view_mlp_kernel occupancy query failed");
+    }
+    ctx->vmlp_resident = per_cu * cus;
+  }
+  const int64_t groups = (n + 255) / 256;
+  const int64_t blocks = groups < ctx->vmlp_resident ? groups : ctx->vmlp_resident;
   hipLaunchKernelGGL(view_mlp_kernel, dim3(unsigned(blocks)), dim3(256), 0, st, n, d, c_d, feat,
                      ctx->mlp_rec, rgb);
   return check_launch(ctx, "view_mlp_kernel");
