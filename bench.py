@@ -87,6 +87,21 @@ def _events():
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
+def copy_probe(mb: int):
+    """One device copy of mb MiB: the plain copy kernel whose FETCH_SIZE and
+    WRITE_SIZE calibrate the counter passes of the same command."""
+    if mb <= 0:
+        return
+    import torch
+    nbytes = mb << 20
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"# copy probe: {nbytes} bytes read + {nbytes} bytes written", file=sys.stderr, flush=True)
+    del src, dst
+
+
 def bench_train(args):
     """One step = render 2^18 rays (16 cameras x 128^2) with the student
     tables, mean-squared colour loss against a teacher (tables of seed 1),
@@ -115,6 +130,7 @@ def bench_train(args):
     cams = synth.random_sphere_cameras(16, 1.0, seed=123)
     o, d, _ = synth.scene_rays(cfg, cams=cams, width=128, height=128)
     torch.cuda.set_device(0)
+    copy_probe(args.copy_probe_mb)
     r = Renderer.from_config(cfg)
     r.load_scene(torch.from_numpy(teacher.tables).cuda(), torch.from_numpy(sc.occ).cuda(),
                  torch.from_numpy(sc.mlp).cuda())
@@ -575,14 +591,7 @@ def main():
     # the CPU oracle leg forks worker processes: run it before any GPU call
     cpu = cpu_baseline(sc, o, d, dtype, args.cpu_seconds) if args.cpu_seconds > 0 else None
     torch.cuda.set_device(0)
-    if args.copy_probe_mb > 0:
-        nbytes = args.copy_probe_mb << 20
-        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        print(f"# copy probe: {nbytes} bytes read + {nbytes} bytes written", file=sys.stderr, flush=True)
-        del src, dst
+    copy_probe(args.copy_probe_mb)
     r = Renderer.from_config(cfg, dtype, use_distance=not args.no_dist)
     r.load_tables(torch.from_numpy(sc.tables).cuda())
     if pyr:
