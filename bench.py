@@ -37,7 +37,7 @@ AGG_NAME = {"separate_v": "sigmoid-gated separate attention (Separate-Att (V))",
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=100)
+    p.add_argument("--steps", type=int, default=120)
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--dtype", choices=["f32", "bf16", "fp8"], default="f32")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
