@@ -21,6 +21,7 @@ the device and loads them through the C ABI.
 from __future__ import annotations
 
 import hashlib
+import io
 import json
 import os
 from typing import Dict, Mapping, Optional, Tuple
@@ -205,18 +206,25 @@ def read_scene(path: str) -> Tuple[Dict, Dict[str, np.ndarray]]:
     for name, entry in sorted(manifest["assets"].items()):
         if name not in DTYPES:
             raise AssetError(f"manifest lists unknown asset {name!r}")
+        if not isinstance(entry, dict):
+            raise AssetError(f"asset {name!r}: manifest entry must be an object")
         fname = entry.get("file", "")
+        if not isinstance(fname, str):
+            raise AssetError(f"asset {name!r}: manifest 'file' must be a string")
         if os.path.basename(fname) != fname or not fname.endswith(".npy"):
             raise AssetError(f"asset {name!r}: file {fname!r} must be a .npy file in the scene directory")
         fpath = os.path.join(path, fname)
         if not os.path.isfile(fpath):
             raise AssetError(f"asset {name!r}: {fname} is missing")
-        digest = _sha256(fpath)
+        # the bytes that are hashed are the bytes that are parsed
+        with open(fpath, "rb") as f:
+            data = f.read()
+        digest = hashlib.sha256(data).hexdigest()
         if digest != entry.get("sha256"):
             raise AssetError(f"asset {name!r}: {fname} has SHA-256 {digest}, the manifest says "
                              f"{entry.get('sha256')}")
         try:
-            a = np.load(fpath, allow_pickle=False)
+            a = np.load(io.BytesIO(data), allow_pickle=False)
         except ValueError as e:
             raise AssetError(f"asset {name!r}: {fname} is not a plain array file ({e})") from None
         if str(a.dtype) != entry.get("dtype") or list(a.shape) != entry.get("shape"):

@@ -98,6 +98,10 @@ def test_manifest_format_and_paths_are_checked(tmp_path):
     _rewrite_manifest(path, lambda m: m["assets"]["mlp"].update(shape=[452]))
     with pytest.raises(AssetError, match="the manifest says"):
         assets.read_scene(path)
+    path, *_ = _save(tmp_path / "e")
+    _rewrite_manifest(path, lambda m: m["assets"].update(mlp=["mlp.npy"]))
+    with pytest.raises(AssetError, match="must be an object"):
+        assets.read_scene(path)
 
 
 def test_object_array_is_not_unpickled(tmp_path):
