@@ -5,13 +5,13 @@
 //
 // A separate pass after the march: the render kernel leaves C_d and F in the
 // caller's output buffers, and this kernel runs the MLP over all rays.  One
-// workgroup = 4 waves; the weights, pre-arranged at load time in the order
-// the MFMA sequence consumes them (one 64-float record per instruction, lane
-// l reading element l), are staged once per workgroup in LDS, and the grid
-// holds only as many workgroups as stay resident together, each taking
-// groups of 256 rays in turn (so the 35 KB of weights are read once per
-// resident workgroup, not once per 256 rays).  Per wave the 64 rays are 4
-// column blocks of 16; every layer is a
+// workgroup = 16 waves sharing one copy of the weights, pre-arranged at load
+// time in the order the MFMA sequence consumes them (one 64-float record per
+// instruction, lane l reading element l), staged once per workgroup in LDS
+// (35 KB of weights + 6 KB of inputs per wave: 131 KB, one workgroup and
+// four waves per SIMD on a CU); the grid holds only as many workgroups as
+// stay resident together, each taking groups of 1024 rays in turn.  Per wave
+// the 64 rays are 4 column blocks of 16; every layer is a
 // chain of v_mfma_f32_16x16x4f32 with the hidden units as rows and the rays
 // as columns; the hidden index handed to the next layer is permuted (k-slot
 // s of chunk (m, r) = unit 16 m + 4 s + r) so each layer consumes the
@@ -87,14 +87,16 @@ __device__ __forceinline__ void sh16(float x, float y, float z, float* Y) {
   Y[14] = c3e * z * (xx - yy); Y[15] = c3a * x * (xx - 3.0f * yy);
 }
 
-__global__ void __launch_bounds__(256) view_mlp_kernel(int64_t n, const float* __restrict__ D,
+constexpr int kViewWaves = 16;                    // waves per workgroup of view_mlp_kernel
+
+__global__ void __launch_bounds__(64 * kViewWaves) view_mlp_kernel(int64_t n, const float* __restrict__ D,
                                                        const float* __restrict__ c_d,
                                                        const float* __restrict__ feat,
                                                        const float* __restrict__ rec,
                                                        float* __restrict__ rgb) {
   __shared__ float W[kViewRecFloats];
-  __shared__ float xin_all[4][24 * 64];
-  for (int t = threadIdx.x; t < kViewRecFloats; t += 256) W[t] = rec[t];
+  __shared__ float xin_all[kViewWaves][24 * 64];
+  for (int t = threadIdx.x; t < kViewRecFloats; t += 64 * kViewWaves) W[t] = rec[t];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   float* xin = xin_all[wave];
   const int i = lane & 15, s = lane >> 4;
@@ -102,10 +104,10 @@ __global__ void __launch_bounds__(256) view_mlp_kernel(int64_t n, const float* _
   const float* R2 = W + kL1Rec * 64;
   const float* R3 = R2 + kL2Rec * 64;
   const float* B = R3 + kL3Rec * 64;
-  const int64_t groups = (n + 255) / 256;
+  const int64_t groups = (n + 64 * kViewWaves - 1) / (64 * kViewWaves);
   // the group loop is uniform across the workgroup, so its barriers are too
   for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {
-  const int64_t ray_base = (g * 4 + wave) * 64;
+  const int64_t ray_base = (g * kViewWaves + wave) * 64;
   const int64_t ray = ray_base + lane;
   float x[24];
 #pragma unroll
@@ -376,7 +378,7 @@ int launch_view_mlp(ngprt_ctx* ctx, int64_t n, const float* d, const float* c_d,
   if (ctx->vmlp_resident <= 0) {
     // workgroups of view_mlp_kernel that stay resident together on the device
     int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, view_mlp_kernel, 256, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, view_mlp_kernel, 64 * kViewWaves, 0) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess ||
         per_cu <= 0 || cus <= 0) {
       (void)hipGetLastError();
@@ -384,9 +386,9 @@ int launch_view_mlp(ngprt_ctx* ctx, int64_t n, const float* d, const float* c_d,
     }
     ctx->vmlp_resident = per_cu * cus;
   }
-  const int64_t groups = (n + 255) / 256;
+  const int64_t groups = (n + 64 * kViewWaves - 1) / (64 * kViewWaves);
   const int64_t blocks = groups < ctx->vmlp_resident ? groups : ctx->vmlp_resident;
-  hipLaunchKernelGGL(view_mlp_kernel, dim3(unsigned(blocks)), dim3(256), 0, st, n, d, c_d, feat,
+  hipLaunchKernelGGL(view_mlp_kernel, dim3(unsigned(blocks)), dim3(64 * kViewWaves), 0, st, n, d, c_d, feat,
                      ctx->mlp_rec, rgb);
   return check_launch(ctx, "view_mlp_kernel");
 }
