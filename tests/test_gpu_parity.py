@@ -266,9 +266,11 @@ def test_render_hd_full_frame_sampled():
            "f64_positions": {"max_abs": float(np.abs(gpu - ref_c.rgb).max()),
                              "mean_abs": float(np.abs(gpu - ref_c.rgb).mean())}}
     print("hd colour error vs float64 oracle:", json.dumps(rep), flush=True)
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open("gpurun_out/hd_colour_error.json", "w") as f:
-        json.dump(rep, f, indent=1)
+    report_dir = os.environ.get("NGPRT_REPORT_DIR")
+    if report_dir:
+        os.makedirs(report_dir, exist_ok=True)
+        with open(os.path.join(report_dir, "hd_colour_error.json"), "w") as f:
+            json.dump(rep, f, indent=1)
     assert rep["f64_positions"]["max_abs"] < COLOUR_TOL
 
 
