@@ -177,7 +177,10 @@ __global__ void __launch_bounds__(64 * kViewWaves) view_mlp_kernel(int64_t n, co
 // one workgroup = 64 rays, a lane per ray; the weights come from the
 // flattened parameters by uniform (scalar) loads.  Per lane: the forward
 // again (activation rows a1, a2 in LDS, ReLU masks as bits), gz = dL/drgb
-// * rgb (1 - rgb), g2 = (W2^T gz) masked, g1 = (W1^T g2) masked,
+// * rgb (1 - rgb), g2 = (W2^T gz) masked, g1 = (W1^T g2) masked, each
+// gradient row written over the activation rows whose last reader is done
+// (g2 over a2 after dW2, g1 over a1 after dW1: two 64-row buffers, 45 KB of
+// LDS per wave, three waves per CU),
 // dL/dC_d = gz + (W0^T g1)[0..2], dL/dF = (W0^T g1)[3..6].  The weight
 // gradients are sums over the wave's rays of outer products, taken on
 // v_mfma_f32_16x16x4f32 with the rays as K, and written as one 5891-float
@@ -208,9 +211,8 @@ __global__ void __launch_bounds__(64) view_mlp_backward_kernel(int64_t n, const 
                                                                const float* __restrict__ P,
                                                                float* __restrict__ grad_cf,
                                                                float* __restrict__ partial) {
-  __shared__ float sA[64 * kVP];       // a1
-  __shared__ float sB[64 * kVP];       // a2, then g1
-  __shared__ float sC[64 * kVP];       // g2
+  __shared__ float sA[64 * kVP];       // a1, then g1
+  __shared__ float sB[64 * kVP];       // a2, then g2
   __shared__ float sX[64 * 32];        // x (23 used, zero padded)
   __shared__ float sG[64 * 16];        // gz (3 used, zero padded)
   const int lane = threadIdx.x;
@@ -233,7 +235,6 @@ __global__ void __launch_bounds__(64) view_mlp_backward_kernel(int64_t n, const 
   }
   float* rowA = sA + lane * kVP;
   float* rowB = sB + lane * kVP;
-  float* rowC = sC + lane * kVP;
   float* rowX = sX + lane * 32;
   float* rowG = sG + lane * 16;
 #pragma unroll
@@ -264,13 +265,6 @@ __global__ void __launch_bounds__(64) view_mlp_backward_kernel(int64_t n, const 
     gz[c] = g[c] * C * (1.0f - C);
     rowG[c] = gz[c];
   }
-  // g2
-  for (int i = 0; i < 64; ++i) {
-    float a = 0.0f;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) a = __builtin_fmaf(P[kW2 + c * 64 + i], gz[c], a);
-    rowC[i] = ((m2 >> i) & 1) ? a : 0.0f;
-  }
   __syncthreads();
   float* part = partial + int64_t(blockIdx.x) * kMlpViewParams;
   const int qi = lane >> 4, col = lane & 15;
@@ -289,29 +283,38 @@ __global__ void __launch_bounds__(64) view_mlp_backward_kernel(int64_t n, const 
     for (int r = 0; r < 64; ++r) a += sG[r * 16 + lane];
     part[kB2 + lane] = a;
   }
+  __syncthreads();
+  // g2 (over a2's rows: dW2 was their last reader)
+  for (int i = 0; i < 64; ++i) {
+    float a = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a = __builtin_fmaf(P[kW2 + c * 64 + i], gz[c], a);
+    rowB[i] = ((m2 >> i) & 1) ? a : 0.0f;
+  }
+  __syncthreads();
   // dW1 [64][64] = sum g2 (x) a1; db1
 #pragma unroll
   for (int ia = 0; ia < 64; ia += 16) {
 #pragma unroll
     for (int jb = 0; jb < 64; jb += 16) {
-      f32x4v r = outer16(sC, kVP, ia, sA, kVP, jb, lane);
+      f32x4v r = outer16(sB, kVP, ia, sA, kVP, jb, lane);
 #pragma unroll
       for (int q = 0; q < 4; ++q) part[kW1 + (ia + 4 * qi + q) * 64 + jb + col] = r[q];
     }
   }
   {
     float a = 0.0f;
-    for (int r = 0; r < 64; ++r) a += sC[r * kVP + lane];
+    for (int r = 0; r < 64; ++r) a += sB[r * kVP + lane];
     part[kB1 + lane] = a;
   }
   __syncthreads();
-  // g1 (over a2's rows, no longer needed) and the input gradients
+  // g1 (over a1's rows: dW1 was their last reader) and the input gradients
   float gx[7] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
   for (int j = 0; j < 64; ++j) {
     float a = 0.0f;
-    for (int i = 0; i < 64; ++i) a = __builtin_fmaf(P[kW1 + i * 64 + j], rowC[i], a);
+    for (int i = 0; i < 64; ++i) a = __builtin_fmaf(P[kW1 + i * 64 + j], rowB[i], a);
     const float g1 = ((m1 >> j) & 1) ? a : 0.0f;
-    rowB[j] = g1;
+    rowA[j] = g1;
 #pragma unroll
     for (int k = 0; k < 7; ++k) gx[k] = __builtin_fmaf(P[kW0 + j * 23 + k], g1, gx[k]);
   }
@@ -327,7 +330,7 @@ __global__ void __launch_bounds__(64) view_mlp_backward_kernel(int64_t n, const 
   for (int ia = 0; ia < 64; ia += 16) {
 #pragma unroll
     for (int jb = 0; jb < 32; jb += 16) {
-      f32x4v r = outer16(sB, kVP, ia, sX, 32, jb, lane);
+      f32x4v r = outer16(sA, kVP, ia, sX, 32, jb, lane);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int k = jb + col;
@@ -337,7 +340,7 @@ __global__ void __launch_bounds__(64) view_mlp_backward_kernel(int64_t n, const 
   }
   {
     float a = 0.0f;
-    for (int r = 0; r < 64; ++r) a += sB[r * kVP + lane];
+    for (int r = 0; r < 64; ++r) a += sA[r * kVP + lane];
     part[kB0 + lane] = a;
   }
 }
