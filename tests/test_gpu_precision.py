@@ -1,7 +1,8 @@
 """Reduced-precision tables: per-image error of the GPU render against the
 float64 oracle with the unquantised tables (quantisation loss + kernel
 error), and of the oracle on the quantised tables (quantisation loss alone).
-Writes gpurun_out/precision_report.json."""
+The report is printed, and written as precision_report.json into the
+directory named by NGPRT_REPORT_DIR when that is set."""
 import json
 import os
 
@@ -45,6 +46,8 @@ def test_precision_report():
     assert report["f32"]["gpu_vs_fp64_f32tables"]["max_abs"] < 1e-5
     assert report["bf16"]["gpu_vs_fp64_f32tables"]["psnr_db"] > 40.0
     assert report["fp8"]["gpu_vs_fp64_f32tables"]["psnr_db"] > 25.0
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open("gpurun_out/precision_report.json", "w") as f:
-        json.dump(report, f, indent=1)
+    report_dir = os.environ.get("NGPRT_REPORT_DIR")
+    if report_dir:
+        os.makedirs(report_dir, exist_ok=True)
+        with open(os.path.join(report_dir, "precision_report.json"), "w") as f:
+            json.dump(report, f, indent=1)
