@@ -74,6 +74,9 @@ def parse():
                         "cache: the random-gather probe over table sizes")
     p.add_argument("--train-size", choices=["tiny", "train_large"], default="tiny")
     p.add_argument("--prop-epochs", type=int, default=12)
+    p.add_argument("--paper-steps", type=int, default=20,
+                   help="default line: timed steps of the paper's rendering choices together (baked L = 2, "
+                        "pyramid + G, MLP_psi) on the hd workload (0 skips it)")
     p.add_argument("--regime-steps", type=int, default=20,
                    help="timed renders of the scene calibrated to the paper's regime in the default "
                         "line (0 = skip)")
@@ -235,6 +238,50 @@ def regime_scene(steps: int) -> dict:
                         "Table 4 regime of samples and marching points per ray",
             "fps": round(8 / (ms / 1e3), 3), "ms": round(ms, 4), "steps": steps,
             "samples_per_ray": round(n_samples / len(o), 3), "reads_per_ray": round(n_reads / len(o), 3),
+            "msamples_per_s": round(n_samples / (ms / 1e3) / 1e6, 1)}
+
+
+def paper_configuration(steps: int) -> dict:
+    """The paper's rendering choices together on the hd workload: baked coarse
+    grid (L_C = 512) + two sigmoid-gated fine levels, the 512^3..32^3
+    occupancy pyramid with the 256^3 distance grid, and the view-dependent
+    MLP as a second pass; F32 tables, timed like the headline (8 views x
+    1080p, HIP events around render + MLP_psi)."""
+    import torch
+    import synth
+    from synth.baked import make_baked_scene
+    from paper_2407_10482_amd.renderer import Renderer
+    cfg = synth.with_aggregation(synth.baked_hd(table_dtype=0, n_fine=2), "separate_v")
+    cfg.occ_levels, cfg.occ_fine_res = 5, 512
+    cfg.mlp_dims = (23, 64, 64, 3)
+    sc = make_baked_scene(cfg)
+    o, d, _ = synth.scene_rays(cfg, cams=synth.camera_positions(cfg)[:8])
+    r = Renderer.from_config(cfg, 0)
+    r.load_tables(torch.from_numpy(sc.tables).cuda())
+    r.load_occupancy_pyramid(torch.from_numpy(sc.occ_fine).cuda())
+    r.load_mlp(torch.from_numpy(sc.mlp).cuda())
+    r.load_coarse(torch.from_numpy(sc.block_index).cuda(), torch.from_numpy(sc.atlas).cuda(), sc.default)
+    go, gd = torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda()
+    counts = r.render(go, gd)
+    n_samples = int(counts["n_samples"].long().sum().item())
+    n_reads = int(counts["n_reads"].long().sum().item())
+    del counts
+    n = len(o)
+    out = {k: torch.empty((n, c), dtype=torch.float32, device="cuda") for k, c in (("rgb", 3), ("c_d", 3), ("feat", 4))}
+    for _ in range(2):
+        r.render(go, gd, out=out)
+    a, b = _events()
+    a.record()
+    for _ in range(steps):
+        r.render(go, gd, out=out)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    return {"workload": "paper_hd: baked coarse grid L_C=512 + 2 sigmoid-gated fine levels (1024, 2048; 2^22 "
+                        "entries, f32), occupancy pyramid 512^3..32^3 + 256^3 distance grid, view-dependent MLP "
+                        "23-64-64-3 with SH(d); 8 views x 1920x1080",
+            "fps": round(8 / (ms / 1e3), 3), "ms": round(ms, 4), "steps": steps,
+            "samples_per_ray": round(n_samples / n, 3), "marching_points_per_ray": round(n_reads / n, 3),
             "msamples_per_s": round(n_samples / (ms / 1e3) / 1e6, 1)}
 
 
@@ -752,6 +799,9 @@ def main():
     if args.regime_steps > 0 and headline:
         torch.cuda.empty_cache()
         res["regime_scene"] = regime_scene(args.regime_steps)
+    if args.paper_steps > 0 and headline:
+        torch.cuda.empty_cache()
+        res["paper_configuration"] = paper_configuration(args.paper_steps)
     print(json.dumps(res), flush=True)
 
 
